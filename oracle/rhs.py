@@ -1,0 +1,256 @@
+"""Semi-discrete right-hand side, time stepping and error norms, FP64.
+
+TEST INFRASTRUCTURE ONLY.
+
+* Diffusion: the fully reference form (eq.
+  NDG_diffusion_once_matrixForm_Fullyreference), in weak form,
+      du/dt = -D [ (r_x Drw + s_x Dsw) q_x + (r_y Drw + s_y Dsw) q_y ]
+              + sum_f (J_f / J) LIFT_f F_f ,
+  q = (r_x Dr + s_x Ds, r_y Dr + s_y Ds) u, Drw = M^{-1} Dr^T M, with F_f the
+  reconstructed flux (D included) and J_f = |edge| / 2 with LIFT built from the
+  1D mass matrix on [-1, 1] (reading of "ratio between the lengths").  The
+  element's own geometric factors are kept in the volume term (eq. for S^k).
+  With an element-wise D the volume term carries D_k and the flux comes from
+  Algorithm 1 (eq. NDG_diffusion_once_matrixForm_reference_general).
+* Convection (the v.grad part of eq. convection_diffusion): nodal collocation
+  of v u, weak form, upwind numerical flux f* = max(n.v,0) u- + min(n.v,0) u+,
+  with u+ = 0 outside the domain.  The velocity is affine, v(x) = v0 + W x.
+* Time stepping: classic four-stage RK4 and the five-stage fourth-order
+  low-storage RK of Carpenter and Kennedy (the paper's integrator).
+* Norms: cell-normalised L2 and L_inf (eqs. L2_norm_cellUnit,
+  Linf_norm_cellUnit) by collapsed Gauss quadrature.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ardg
+from .mesh import Geometry
+from .reference_element import RefOps, vandermonde
+
+
+class Problem:
+    """A mesh, an order N, diffusion coefficients and an optional velocity.
+
+    D_mode: "const" (D is a float, or a list with one value per field) or
+    "element" (D is an array [K], Algorithm 1).
+    """
+
+    def __init__(self, vxy, etov, N: int, D, D_mode: str = "const",
+                 velocity=None, nfields: int = 1):
+        self.geom = Geometry(vxy, etov)
+        self.ops = RefOps(N)
+        self.N = N
+        self.nfields = nfields
+        self.D_mode = D_mode
+        if D_mode == "const":
+            Dv = np.atleast_1d(np.asarray(D, dtype=np.float64))
+            if Dv.size == 1:
+                Dv = np.repeat(Dv, nfields)
+            self.Dfield = Dv
+        elif D_mode == "element":
+            if nfields != 1:
+                raise ValueError("element-wise D is for one field")
+            self.Delem = np.asarray(D, dtype=np.float64)
+        else:
+            raise ValueError(D_mode)
+        self.velocity = velocity   # None or (v0x, v0y, W11, W12, W21, W22)
+        self._build_edges()
+
+    # -- per-edge operators (literal Algorithm aRDG / Algorithm 1) -----------
+    def _build_edges(self):
+        g, ops = self.geom, self.ops
+        self.int_edges = g.interior
+        self.bdy_edges = g.boundary
+        E1, E2 = [], []
+        self.edge_geom = []
+        for (k1, f1, k2, f2) in self.int_edges:
+            eg = ardg.interior_edge_geometry(g, k1, f1, k2, f2)
+            self.edge_geom.append(eg)
+            if self.D_mode == "element":
+                W1, W2 = ardg.edge_operator_alg1(ops, eg, f1, f2, self.Delem[k1], self.Delem[k2])
+            else:
+                W1, W2 = ardg.edge_operator(ops, eg, f1, f2)
+            E1.append(W1)
+            E2.append(W2)
+        self.W1 = np.array(E1).reshape(-1, ops.Nfp, ops.Np)
+        self.W2 = np.array(E2).reshape(-1, ops.Nfp, ops.Np)
+        B = []
+        self.bdy_geom = []
+        for (k1, f1) in self.bdy_edges:
+            eg = ardg.boundary_edge_geometry(g, k1, f1)
+            self.bdy_geom.append(eg)
+            if self.D_mode == "element":
+                B.append(ardg.boundary_edge_operator_alg1(ops, g, k1, f1, eg, self.Delem[k1]))
+            else:
+                B.append(ardg.boundary_edge_operator(ops, g, k1, f1, eg))
+        self.WB = np.array(B).reshape(-1, ops.Nfp, ops.Np)
+
+    # -- fluxes -----------------------------------------------------------------
+    def diffusive_flux(self, u: np.ndarray, field: int = 0):
+        """Fluxes F in element-1 (CCW) order: [E_int, Nfp] and [E_bdy, Nfp]."""
+        k1 = np.array([e[0] for e in self.int_edges], dtype=np.int64)
+        k2 = np.array([e[2] for e in self.int_edges], dtype=np.int64)
+        kb = np.array([e[0] for e in self.bdy_edges], dtype=np.int64)
+        Fi = (np.einsum("eij,ej->ei", self.W1, u[k1]) if len(k1) else np.zeros((0, self.ops.Nfp)))
+        if len(k2):
+            Fi = Fi + np.einsum("eij,ej->ei", self.W2, u[k2])
+        Fb = np.einsum("eij,ej->ei", self.WB, u[kb]) if len(kb) else np.zeros((0, self.ops.Nfp))
+        if self.D_mode == "const":
+            Fi = Fi * self.Dfield[field]
+            Fb = Fb * self.Dfield[field]
+        return Fi, Fb
+
+    def face_fluxes(self, Fi, Fb):
+        """[K, 3, Nfp] flux seen by each element face, in its own CCW order.
+
+        Side 1 reads the edge flux as is; side 2 (outward normal reversed, face
+        traversed B -> A) reads it negated and in reverse order.
+        """
+        ops = self.ops
+        out = np.zeros((self.geom.K, 3, ops.Nfp))
+        if len(self.int_edges):
+            ie = np.array(self.int_edges, dtype=np.int64)
+            out[ie[:, 0], ie[:, 1]] = Fi
+            out[ie[:, 2], ie[:, 3]] = -Fi[:, ::-1]
+        if len(self.bdy_edges):
+            be = np.array(self.bdy_edges, dtype=np.int64)
+            out[be[:, 0], be[:, 1]] = Fb
+        return out
+
+    # -- velocity ------------------------------------------------------------
+    def velocity_at(self, xy):
+        v0x, v0y, a, b, c, d = self.velocity
+        return v0x + a * xy[..., 0] + b * xy[..., 1], v0y + c * xy[..., 0] + d * xy[..., 1]
+
+    def upwind_face_flux(self, u):
+        """[K, 3, Nfp] upwind flux f* per element face (CCW order)."""
+        ops, g = self.ops, self.geom
+        xyn = g.physical(ops.rs)
+        vx, vy = self.velocity_at(xyn)
+        out = np.zeros((g.K, 3, ops.Nfp))
+        for k in range(g.K):
+            for f in range(3):
+                idx = ops.fmask[f]
+                vn = g.nx[k, f] * vx[k, idx] + g.ny[k, f] * vy[k, idx]
+                um = u[k, idx]
+                k2 = g.EToE[k, f]
+                if k2 < 0:
+                    up = np.zeros_like(um)
+                else:
+                    f2 = g.EToF[k, f]
+                    up = u[k2, ops.fmask[f2]][::-1]
+                out[k, f] = np.maximum(vn, 0.0) * um + np.minimum(vn, 0.0) * up
+        return out
+
+    # -- right-hand side ------------------------------------------------------
+    def rhs(self, u: np.ndarray) -> np.ndarray:
+        """du/dt for state u [F, K, Np] (or [K, Np] for one field)."""
+        single = (u.ndim == 2)
+        U = u[None] if single else u
+        out = np.stack([self._rhs_field(U[f], f) for f in range(U.shape[0])])
+        return out[0] if single else out
+
+    def _rhs_field(self, u, field):
+        ops, g = self.ops, self.geom
+        rx, ry, sx, sy = (a[:, None] for a in (g.rx, g.ry, g.sx, g.sy))
+        ur = u @ ops.Dr.T
+        us = u @ ops.Ds.T
+        qx = rx * ur + sx * us
+        qy = ry * ur + sy * us
+        Dk = self.Delem[:, None] if self.D_mode == "element" else self.Dfield[field]
+        vol = (rx * (qx @ ops.Drw.T) + sx * (qx @ ops.Dsw.T)
+               + ry * (qy @ ops.Drw.T) + sy * (qy @ ops.Dsw.T))
+        rhs = -Dk * vol
+        Fi, Fb = self.diffusive_flux(u, field)
+        Ff = self.face_fluxes(Fi, Fb)
+        surf = np.zeros_like(u)
+        for f in range(3):
+            scale = (g.sJ[:, f] / g.J)[:, None]
+            surf += scale * (Ff[:, f, :] @ ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp].T)
+        rhs = rhs + surf
+        if self.velocity is not None:
+            rhs = rhs + self._convection_weak(u)
+        return rhs
+
+    def _convection_weak(self, u):
+        """-div(v u) in weak form: Dxw (vx u) + Dyw (vy u) - sum_f LIFT_f f*."""
+        ops, g = self.ops, self.geom
+        xyn = g.physical(ops.rs)
+        vx, vy = self.velocity_at(xyn)
+        fx, fy = vx * u, vy * u
+        rx, ry, sx, sy = (a[:, None] for a in (g.rx, g.ry, g.sx, g.sy))
+        vol = (rx * (fx @ ops.Drw.T) + sx * (fx @ ops.Dsw.T)
+               + ry * (fy @ ops.Drw.T) + sy * (fy @ ops.Dsw.T))
+        fs = self.upwind_face_flux(u)
+        surf = np.zeros_like(u)
+        for f in range(3):
+            scale = (g.sJ[:, f] / g.J)[:, None]
+            surf += scale * (fs[:, f, :] @ ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp].T)
+        return vol - surf
+
+    # -- nodal coordinates ------------------------------------------------------
+    def nodal_xy(self):
+        return self.geom.physical(self.ops.rs)
+
+
+# ----------------------------------------------------------------------------
+# Time integration
+# ----------------------------------------------------------------------------
+
+def rk4_step(rhs, u, dt):
+    k1 = rhs(u)
+    k2 = rhs(u + 0.5 * dt * k1)
+    k3 = rhs(u + 0.5 * dt * k2)
+    k4 = rhs(u + dt * k3)
+    return u + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+# Carpenter & Kennedy (1994), five-stage fourth-order 2N-storage scheme
+LSERK_A = np.array([0.0,
+                    -567301805773.0 / 1357537059087.0,
+                    -2404267990393.0 / 2016746695238.0,
+                    -3550918686646.0 / 2091501179385.0,
+                    -1275806237668.0 / 842570457699.0])
+LSERK_B = np.array([1432997174477.0 / 9575080441755.0,
+                    5161836677717.0 / 13612068292357.0,
+                    1720146321549.0 / 2090206949498.0,
+                    3134564353537.0 / 4481467310338.0,
+                    2277821191437.0 / 14882151754819.0])
+
+
+def lserk_step(rhs, u, dt):
+    res = np.zeros_like(u)
+    for s in range(5):
+        res = LSERK_A[s] * res + dt * rhs(u)
+        u = u + LSERK_B[s] * res
+    return u
+
+
+# ----------------------------------------------------------------------------
+# Norms
+# ----------------------------------------------------------------------------
+
+def mass_norm(prob: Problem, e: np.ndarray) -> float:
+    """sqrt(sum_k J_k e_k^T M e_k / sum_k |Omega_k|) for nodal e [K, Np]."""
+    ops, g = prob.ops, prob.geom
+    num = float(np.sum(g.J * np.einsum("ki,ij,kj->k", e, ops.M, e)))
+    area = float(np.sum(2.0 * g.J))
+    return np.sqrt(num / area)
+
+
+def error_norms(prob: Problem, u: np.ndarray, exact, nq: int = None):
+    """Cell-normalised L2 and L_inf errors against exact(x, y)."""
+    ops, g = prob.ops, prob.geom
+    N = ops.N
+    nq = nq or (N + 4)
+    r, s, w = ardg.triangle_quadrature(nq)
+    Vq = vandermonde(N, r, s) @ ops.Vinv                     # nodal -> quadrature
+    uq = u @ Vq.T                                            # [K, Q]
+    xy = g.physical(np.column_stack([r, s]))                 # [K, Q, 2]
+    ue = exact(xy[..., 0], xy[..., 1])
+    err = uq - ue
+    area = 2.0 * g.J
+    l2 = np.sqrt(np.sum(g.J * (err ** 2 @ w)) / np.sum(area))
+    linf = np.max(g.J * (np.abs(err) @ w) / area)
+    return l2, linf

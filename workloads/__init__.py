@@ -1,0 +1,159 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module holds no arithmetic of the reconstruction method: it only builds
+meshes (vertex coordinates and CCW vertex lists), coefficient fields, smooth
+functions evaluated at caller-supplied points, and random nodal data.  Both the
+oracle and the HIP library consume what it returns; neither side's operators,
+node sets or geometry live here.
+
+Input recipe (the paper runs on grids of split quadrilaterals; the workloads
+below are synthetic stand-ins with the same structure):
+
+* ``split_square_mesh(m, jitter)``: the unit square cut into m x m cells, each
+  cell split along its (i,j)->(i+1,j+1) diagonal into two CCW triangles.  Every
+  interior vertex is moved independently in x and y by U[-jitter*h, jitter*h]
+  (h = 1/m); boundary vertices stay fixed.  Unjittered, every interior pair of
+  triangles forms a parallelogram (the paper's grid-a situation).
+* ``circle_contrast_D``: piecewise constant per element, ``inside`` within a
+  circle and ``outside`` elsewhere, assigned by element centroid.
+* ``loguniform_per_element``: per-element coefficient, log-uniform in [lo, hi].
+* ``fourier_modes``: sum_{k,l=1..4} a_kl sin(k pi x) sin(l pi y) with
+  a_kl = g_kl/(k^2+l^2), g ~ N(0,1); vanishes on the boundary of the square.
+* ``manufactured``: exp(-2 pi^2 D t) sin(pi x) sin(pi y), an exact solution of
+  the heat equation with zero Dirichlet data on the unit square.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "Mesh", "split_square_mesh", "centroids", "circle_contrast_D",
+    "loguniform_per_element", "fourier_modes", "manufactured",
+    "random_nodal", "seed_for", "WORKLOADS", "batch_problems",
+]
+
+
+def seed_for(config: int, what: str) -> int:
+    """Seed convention: 1000*config + {mesh:1, D:2, IC:3, batch:4}."""
+    return 1000 * int(config) + {"mesh": 1, "D": 2, "IC": 3, "batch": 4}[what]
+
+
+@dataclass
+class Mesh:
+    vxy: np.ndarray    # [Nv, 2] float64 vertex coordinates
+    etov: np.ndarray   # [K, 3] int32 vertex indices, counter-clockwise
+
+    @property
+    def K(self) -> int:
+        return int(self.etov.shape[0])
+
+
+def split_square_mesh(m: int, jitter: float = 0.0, seed: int = 0) -> Mesh:
+    """m x m cells on [0,1]^2, each split along its (i,j)->(i+1,j+1) diagonal.
+
+    Elements are numbered cell by cell in row-major order (cell (i,j) holds
+    elements 2(j*m+i) and 2(j*m+i)+1), which keeps face neighbours close in
+    memory.
+    """
+    if m < 1:
+        raise ValueError("m must be >= 1")
+    h = 1.0 / m
+    ii, jj = np.meshgrid(np.arange(m + 1), np.arange(m + 1), indexing="xy")
+    x = (ii * h).astype(np.float64).ravel()
+    y = (jj * h).astype(np.float64).ravel()
+    if jitter > 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        d = rng.uniform(-jitter * h, jitter * h, size=(2, (m + 1) * (m + 1)))
+        interior = ((ii > 0) & (ii < m) & (jj > 0) & (jj < m)).ravel()
+        x = x + np.where(interior, d[0], 0.0)
+        y = y + np.where(interior, d[1], 0.0)
+    vxy = np.stack([x, y], axis=1)
+
+    def vid(i, j):
+        return j * (m + 1) + i
+
+    ci, cj = np.meshgrid(np.arange(m), np.arange(m), indexing="xy")
+    ci = ci.ravel()
+    cj = cj.ravel()
+    a = vid(ci, cj)
+    b = vid(ci + 1, cj)
+    c = vid(ci + 1, cj + 1)
+    d = vid(ci, cj + 1)
+    lower = np.stack([a, b, c], axis=1)   # (i,j),(i+1,j),(i+1,j+1)
+    upper = np.stack([a, c, d], axis=1)   # (i,j),(i+1,j+1),(i,j+1)
+    etov = np.empty((2 * m * m, 3), dtype=np.int32)
+    etov[0::2] = lower
+    etov[1::2] = upper
+    return Mesh(vxy=vxy, etov=etov)
+
+
+def centroids(mesh: Mesh) -> np.ndarray:
+    return mesh.vxy[mesh.etov].mean(axis=1)
+
+
+def circle_contrast_D(mesh: Mesh, inside: float = 1e2, outside: float = 1e-2,
+                      radius: float = 0.25, centre=(0.5, 0.5)) -> np.ndarray:
+    c = centroids(mesh)
+    r2 = (c[:, 0] - centre[0]) ** 2 + (c[:, 1] - centre[1]) ** 2
+    return np.where(r2 < radius * radius, inside, outside).astype(np.float64)
+
+
+def loguniform_per_element(K: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size=K))
+
+
+def fourier_modes(x: np.ndarray, y: np.ndarray, seed: int, modes: int = 4) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = rng.standard_normal((modes, modes))
+    out = np.zeros(np.broadcast(x, y).shape)
+    for k in range(1, modes + 1):
+        sx = np.sin(k * math.pi * x)
+        for l in range(1, modes + 1):
+            out = out + g[k - 1, l - 1] / (k * k + l * l) * sx * np.sin(l * math.pi * y)
+    return out
+
+
+def manufactured(x, y, t: float = 0.0, D: float = 1.0):
+    return math.exp(-2.0 * math.pi ** 2 * D * t) * np.sin(math.pi * x) * np.sin(math.pi * y)
+
+
+def random_nodal(shape, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-1.0, 1.0, size=shape)
+
+
+# Named workloads (sizes as quoted for each configuration).
+WORKLOADS = {
+    "heat_8x8_N2": dict(config=0, m=8, jitter=0.0, N=2, D="const", Dval=1.0,
+                        ic="manufactured", steps=100, fields=1),
+    "contrast_256x256_N4": dict(config=1, m=256, jitter=0.2, N=4, D="circle",
+                                ic="fourier", steps=100, fields=1),
+    "loguniformD_512x512_N6": dict(config=2, m=512, jitter=0.2, N=6, D="loguniform",
+                                   Dlo=1e-3, Dhi=1e1, ic="fourier", steps=50, fields=1),
+    "convdiff_708x708_N3_4f": dict(config=4, m=708, jitter=0.2, N=3, D="perfield",
+                                   Dfield=(1e-4, 1e-3, 1e-2, 1.0), ic="fourier",
+                                   velocity="rotation", steps=200, fields=4),
+}
+
+
+def batch_problems(n: int = 512, seed: int = seed_for(3, "batch"),
+                   kmin: int = 200, kmax: int = 20000):
+    """Independent heat problems of uneven size and order.
+
+    Returns a list of dicts with m (cells per side, K = 2 m^2 ~ n_i), N in
+    {2,3,4} and a constant D log-uniform in [1e-3, 1].
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        ni = math.exp(rng.uniform(math.log(kmin), math.log(kmax)))
+        m = max(2, int(round(math.sqrt(ni / 2.0))))
+        N = int(rng.integers(2, 5))
+        D = math.exp(rng.uniform(math.log(1e-3), math.log(1.0)))
+        out.append(dict(m=m, N=N, D=D, mesh_seed=seed * 1000 + 2 * i,
+                        ic_seed=seed * 1000 + 2 * i + 1))
+    return out
