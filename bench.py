@@ -1,0 +1,249 @@
+"""Benchmark: DOF x RK-stage per second of the aRDG right-hand side on one MI355X.
+
+Workload (default): unit square 256 x 256 x 2 = 131072 triangles, interior
+vertices jittered by +-0.2 h (seeded), N = 4 (Np = 15), element-wise D with
+contrast 1e4 (1e-2 outside, 1e2 inside a circle of radius 0.25; Algorithm 1
+flux), initial data a seeded sum of 16 Fourier modes, classic RK4.  The FP64
+path is the headline value; the mixed mode (FP32 operators and arithmetic,
+FP64 RK state) is reported beside it with its L2 difference to the FP64 path.
+
+One bench step = one RK4 time step = 4 passes of the whole hot path (edge
+reconstruction kernel + element kernel with the fused RK update).  Inputs are
+resident in HBM before timing starts; the step loop is a replayed HIP graph.
+
+`cpu_baseline` times the FP64 NumPy oracle (test infrastructure) on a bounded
+sample: one RHS stage on the first S elements of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    spec = W.WORKLOADS[name]
+    cfg = spec["config"]
+    mesh = W.split_square_mesh(spec["m"], spec["jitter"], seed=W.seed_for(cfg, "mesh"))
+    return spec, mesh
+
+
+def nodal_xy(mesh, rs):
+    v = mesh.vxy[mesh.etov]
+    r, s = rs[:, 0], rs[:, 1]
+    x = 0.5 * (-(r + s)[None] * v[:, 0:1, 0] + (r + 1)[None] * v[:, 1:2, 0] + (s + 1)[None] * v[:, 2:3, 0])
+    y = 0.5 * (-(r + s)[None] * v[:, 0:1, 1] + (r + 1)[None] * v[:, 1:2, 1] + (s + 1)[None] * v[:, 2:3, 1])
+    return x, y
+
+
+def algorithmic_bytes(K, Np, Nfp, E_int, E_bdy, s, alg1, nfields=1):
+    """Bytes each kernel must move per launch (each value counted once).
+
+    edge kernel:    state read F*K*Np*s, edge table 56 B per interior edge
+                    (int2 elements+faces, 3 x double2: apex weights of both
+                    sides, gamma_R/gamma_S), 36 B per boundary face, D per
+                    element (Algorithm 1) 8K, flux write F*E*Nfp*s.
+    element kernel: RK4 stage averaged over the 4 stages: stage input read
+                    F*K*Np*s, flux read F*E*Nfp*s, vertices 48K, face map
+                    12K, D 8K, FP64 state/accumulator traffic 34 B per DOF on
+                    average (stage 0: u, acc w, v w; 1-2: v, u, acc r/w, v w;
+                    3: v, u r/w, acc r) with the FP64 v counted in the 34 B
+                    when s = 8, and 26 + 4*... per DOF otherwise.
+    """
+    E = E_int + E_bdy
+    dof = nfields * K * Np
+    edge = dof * s + 56 * E_int + 36 * E_bdy + (8 * K if alg1 else 0) + nfields * E * Nfp * s
+    if s == 8:
+        state = 34.0 * dof          # includes the FP64 stage vector
+        vin = 0.0
+    else:
+        # FP32: v read (4), u read 8 (stages 0-2) / r+w 16 (stage 3), acc as FP64,
+        # v write 4 (all stages)
+        state = (8 + 16 + 16 + 8) / 4.0 * dof + (8 * 3 + 16) / 4.0 * dof + 4.0 * dof
+        vin = 4.0 * dof
+    elem = vin + state + nfields * E * Nfp * s + 48 * K + 12 * K + (8 * K if alg1 else 0)
+    return edge, elem
+
+
+def edge_flops(K, Np, Nfp, N, E_int, E_bdy, alg1, nfields=1):
+    """Algorithmic FLOPs of the edge kernel per launch: nodal->Bernstein and
+    de Casteljau on both sides, the constant operator(s), the gamma/D combine."""
+    dec = 3 * N * (N + 1) * (N + 2) // 6 * 2
+    per_side = 2 * Np * Np + dec
+    c = 2 if alg1 else 1
+    per_edge = 2 * per_side + 2 * 2 * Nfp * 2 * Np * c + 6 * Nfp
+    per_bdy = per_side + 2 * 2 * Nfp * Np + 6 * Nfp
+    return nfields * (E_int * per_edge + E_bdy * per_bdy)
+
+
+def cpu_baseline(spec, mesh, D, u, budget_s=12.0):
+    from oracle.rhs import Problem
+    t0 = time.time()
+    pr = Problem(mesh.vxy, mesh.etov, spec["N"], D, D_mode="element", build_edges=False)
+    setup = time.time() - t0
+    # calibrate on 50 elements, then run a sample sized to the budget
+    t0 = time.time()
+    pr.rhs_elements(u, list(range(50)))
+    per = (time.time() - t0) / 50
+    S = int(max(200, min(mesh.K, budget_s / max(per, 1e-6))))
+    t0 = time.time()
+    pr.rhs_elements(u, list(range(S)))
+    dt = time.time() - t0
+    Np = pr.ops.Np
+    return {"value": S * Np / dt, "unit": "DOF*stage/s", "cores": 1, "kind": "oracle",
+            "sample": f"one RHS stage (literal per-edge aRDG / Algorithm 1 operators) on the first "
+                      f"{S} of {mesh.K} elements of the same workload; {dt:.1f} s; geometry setup "
+                      f"{setup:.1f} s excluded; single-threaded NumPy"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="contrast_256x256_N4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              f"(multi-GPU sharding is design-only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1912_06221_amd import ardg
+
+    dev = torch.device("cuda:0")
+    spec, mesh = build_workload(args.workload)
+    N = spec["N"]
+    cfg = spec["config"]
+    log(f"bench: workload {args.workload} K={mesh.K} N={N}")
+    ops = ardg.Ops(N)
+    lm = ardg.Mesh(ops, mesh.vxy, mesh.etov, device=0)
+    alg1 = spec["D"] in ("circle", "loguniform")
+    if spec["D"] == "circle":
+        D = W.circle_contrast_D(mesh)
+    elif spec["D"] == "loguniform":
+        D = W.loguniform_per_element(mesh.K, spec["Dlo"], spec["Dhi"], W.seed_for(cfg, "D"))
+    else:
+        D = np.array(spec.get("Dfield", [spec.get("Dval", 1.0)]))
+    nf = spec["fields"]
+    if alg1:
+        lm.set_diffusion_element(D)
+    else:
+        lm.set_diffusion_const(D)
+    if spec.get("velocity") == "rotation":
+        lm.set_velocity([0.0, 0.0, 0.0, -1.0, 1.0, 0.0])
+    rs = ops.export(ardg.OPS_NODES).reshape(-1, 2)
+    x, y = nodal_xy(mesh, rs)
+    u0 = np.stack([W.fourier_modes(x, y, seed=W.seed_for(cfg, "IC") + 10 * f) for f in range(nf)])
+    K, Np, Nfp = mesh.K, ops.Np, ops.Nfp
+    dof = nf * K * Np
+
+    # time step from a power-iteration estimate of the spectral radius (setup)
+    v = torch.from_numpy(W.random_nodal((nf, K, Np), seed=7)).to(dev)
+    w = torch.empty_like(v)
+    rho = 0.0
+    for _ in range(30):
+        lm.rhs_eval(v, w, nfields=nf)
+        nrm = float(torch.linalg.vector_norm(w))
+        rho = nrm / float(torch.linalg.vector_norm(v))
+        v = w / nrm
+    dt = 1.0 / rho
+    log(f"bench: spectral radius ~{rho:.3e}, dt={dt:.3e}")
+
+    results = {}
+    for prec_name, prec in (("fp64", ardg.FP64), ("fp32", ardg.FP32)):
+        if prec_name == "fp32" and args.skip_fp32:
+            continue
+        u = torch.from_numpy(u0.copy()).to(dev)
+        work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, prec, nf), dev)
+        for _ in range(args.warmup):
+            lm.rk_step(u, work, dt, 1, scheme=ardg.RK4, precision=prec, nfields=nf)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(args.steps):
+            lm.rk_step(u, work, dt, 1, scheme=ardg.RK4, precision=prec, nfields=nf)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        # per-kernel durations (HIP events around each launch, same stream)
+        t_edge, t_elem = lm.stage_timing(u, work, dt, 40, scheme=ardg.RK4, precision=prec, nfields=nf)
+        lm.check(u, nfields=nf)
+        results[prec_name] = dict(ms=ms, t_edge=t_edge, t_elem=t_elem, u=u.detach().cpu().numpy())
+        log(f"bench: {prec_name}: {ms:.3f} ms/step, edge {t_edge*1e3:.1f} us, elem {t_elem*1e3:.1f} us")
+
+    r64 = results["fp64"]
+    value = dof * 4 / (r64["ms"] * 1e-3)
+    s64 = 8
+    b_edge, b_elem = algorithmic_bytes(K, Np, Nfp, lm.E_int, lm.E_bdy, s64, alg1, nf)
+    bw_edge = b_edge / (r64["t_edge"] * 1e-3) / 1e9
+    bw_elem = b_elem / (r64["t_elem"] * 1e-3) / 1e9
+    dom = "element" if r64["t_elem"] >= r64["t_edge"] else "edge"
+    bw = bw_elem if dom == "element" else bw_edge
+    fl = edge_flops(K, Np, Nfp, N, lm.E_int, lm.E_bdy, alg1, nf)
+    line = {
+        "metric": "DOF*RK-stage/s per MI355X (FP64 path; mixed FP32 path beside it with L2 difference)",
+        "value": value,
+        "unit": "DOF*stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms"],
+        "step": "one classic RK4 time step = 4 RHS stages (edge kernel + element kernel each)",
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded jittered mesh, seeded D field and Fourier initial data)",
+        "config": {"workload": args.workload, "K": K, "N": N, "Np": Np, "DOF": dof,
+                   "E_int": lm.E_int, "E_bdy": lm.E_bdy, "D": spec["D"], "scheme": "RK4",
+                   "dt": dt, "fields": nf},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": bw, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": bw / HBM_PEAK_GBS, "traffic": None,
+                     "edge_kernel_us": r64["t_edge"] * 1e3, "element_kernel_us": r64["t_elem"] * 1e3,
+                     "edge_GBps": bw_edge, "element_GBps": bw_elem,
+                     "edge_algorithmic_bytes": b_edge, "element_algorithmic_bytes": b_elem,
+                     "edge_TFLOPs": fl / (r64["t_edge"] * 1e-3) / 1e12,
+                     "edge_fp64_frac": fl / (r64["t_edge"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+    }
+    if "fp32" in results:
+        r32 = results["fp32"]
+        d = r32["u"] - r64["u"]
+        l2 = float(np.sqrt(np.sum(d * d) / np.sum(r64["u"] ** 2)))
+        b_edge32, b_elem32 = algorithmic_bytes(K, Np, Nfp, lm.E_int, lm.E_bdy, 4, alg1, nf)
+        line["mixed_fp32"] = {
+            "value": dof * 4 / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"],
+            "speedup_vs_fp64": r64["ms"] / r32["ms"],
+            "rel_l2_diff_vs_fp64_after_steps": l2,
+            "edge_kernel_us": r32["t_edge"] * 1e3, "element_kernel_us": r32["t_elem"] * 1e3,
+            "edge_GBps": b_edge32 / (r32["t_edge"] * 1e-3) / 1e9,
+            "element_GBps": b_elem32 / (r32["t_elem"] * 1e-3) / 1e9,
+        }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on a bounded sample (cpu_baseline)")
+        line["cpu_baseline"] = cpu_baseline(spec, mesh, D, u0[0])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * ardg.h -- C ABI of the MI355X (gfx950) affine-reconstructed nodal DG library.
+ *
+ * The library evaluates the semi-discrete convection-diffusion right-hand side
+ * on unstructured triangles (the paper's eq. convection_diffusion with s = 0),
+ * in the fully reference form of eq.
+ * NDG_diffusion_once_matrixForm_Fullyreference: per element the Dr/Ds volume
+ * term with the element's affine factors and (J_f/J) LIFT_f of the face fluxes;
+ * per interior edge the diffusive flux n . grad(u~) (or n . (D grad u~)~ for
+ * element-wise D, Algorithm 1) sampled at the LGL nodes of the diagonal of the
+ * enclosed parallelogram, u~ being the least-squares reconstruction of
+ * Algorithm aRDG.  Time stepping: classic RK4, or the five-stage fourth-order
+ * low-storage Runge-Kutta the paper integrates with.
+ *
+ * Conventions shared by every call:
+ *  - Reference triangle I = {r,s >= -1, r+s <= 0}, vertices a1=(-1,-1),
+ *    a2=(1,-1), a3=(-1,1); element map of eq. mapping_tri with the element's
+ *    CCW vertices (v1, v2, v3).  Faces f1=(v1,v2), f2=(v2,v3), f3=(v3,v1).
+ *  - Nodes: warp-and-blend nodes (blend parameter 0) whose edge nodes are the
+ *    LGL points.  Order: lattice rows of increasing s, each row in increasing
+ *    r (ardg_ops_export(ARDG_OPS_NODES)).  Np = (N+1)(N+2)/2, Nfp = N+1.
+ *  - State layout: [F][K][Np] contiguous, node fastest, F fields.
+ *  - Edge flux layout: [F][E][Nfp] with E = E_int + E_bdy; interior edges
+ *    first, ordered by their side-1 element (the lower element index) and
+ *    its face, then boundary faces ordered by element and face.  Values are
+ *    given in side 1's counter-clockwise face order (A -> B) with side 1's
+ *    outward normal; side 2 sees the negated values in reverse order.
+ *  - Boundary faces: zero Dirichlet data through a mirror ghost element (the
+ *    element reflected across the face carrying -u at mirrored points); the
+ *    paper specifies no boundary treatment.
+ *  - Device pointers are caller-owned device memory on the mesh's device.
+ *    Host pointers are only read during the call (the library copies them).
+ *  - Every call returns an ardg_status; 0 is success, negative values are
+ *    errors, and ardg_last_error() gives a thread-local message.  No call
+ *    aborts the process or throws across the ABI.
+ *  - Handles are not thread-safe; distinct handles may be used concurrently.
+ */
+#ifndef ARDG_H
+#define ARDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ardg_status;
+
+enum {
+  ARDG_OK = 0,
+  ARDG_E_INVALID_ARG = -1,
+  ARDG_E_MESH_ORIENTATION = -2,      /* an element with J <= 0 (not CCW) */
+  ARDG_E_MESH_TOPOLOGY = -3,         /* non-manifold or inconsistently oriented edge */
+  ARDG_E_DEGENERATE_PARALLELOGRAM = -4,
+  ARDG_E_RECON_RANK = -5,            /* reconstruction system not of full column rank */
+  ARDG_E_UNSUPPORTED = -6,           /* order or precision not built */
+  ARDG_E_HIP = -7,                   /* a HIP runtime call failed */
+  ARDG_E_OOM = -8,
+  ARDG_E_NONFINITE = -9              /* non-finite value found by ardg_check */
+};
+
+enum { ARDG_FP64 = 0, ARDG_FP32 = 1, ARDG_BF16X3 = 2 };
+enum { ARDG_RK4 = 0, ARDG_LSERK54 = 1 };
+enum { ARDG_D_CONST = 0, ARDG_D_ELEMENT = 1 };
+enum { ARDG_VEL_NONE = 0, ARDG_VEL_AFFINE = 1 };
+
+/* ardg_ops_export selectors (row-major double arrays). */
+enum {
+  ARDG_OPS_NODES = 0,        /* [Np][2] reference coordinates (r, s)                      */
+  ARDG_OPS_V = 1,            /* [Np][Np] Vandermonde of the library's orthonormal basis   */
+  ARDG_OPS_DR = 2,           /* [Np][Np] d/dr on nodal values                              */
+  ARDG_OPS_DS = 3,           /* [Np][Np] d/ds                                              */
+  ARDG_OPS_MASS = 4,         /* [Np][Np] reference mass matrix                             */
+  ARDG_OPS_LIFT = 5,         /* [Np][3*Nfp] reference LIFT (1D mass on [-1,1] per face)    */
+  ARDG_OPS_FACE_NODES = 6,   /* [3][Nfp] node index of each face node, CCW                 */
+  ARDG_OPS_ROT_PERM = 7,     /* [3][Np] (Pi_f u)_i = u[perm[f][i]]: face f -> hypotenuse   */
+  ARDG_OPS_RECON_A = 8,      /* [2Np][Mp] least-squares system (library basis)             */
+  ARDG_OPS_RECON_R = 9,      /* [Mp][2Np] its pseudo-inverse                               */
+  ARDG_OPS_RECON_GRAD = 10,  /* [2Nfp][2Np] nodal data on the two sub-triangles (each in its
+                                own frame) -> (d/dR, d/dS) of u~ at the diagonal nodes     */
+  ARDG_OPS_ALG1_GRAD = 11,   /* [4Nfp][2Np] Algorithm 1 blocks U1R, U1S, U2R, U2S on the same
+                                nodal sub-triangle data (flux = D1 (gR U1R + gS U1S)
+                                - D2 (gR U2R + gS U2S))                                    */
+  ARDG_OPS_N2B = 12          /* [Np][Np] nodal values -> Bernstein coefficients on I       */
+};
+
+/* ardg_mesh_export selectors. */
+enum {
+  ARDG_MESH_EDGES = 0,       /* int32 [E_int][4]: e1, f1, e2, f2 (faces 0..2)             */
+  ARDG_MESH_BFACES = 1,      /* int32 [E_bdy][2]: element, face                            */
+  ARDG_MESH_EDGE_GEOM = 2,   /* double [E_int][8]: P1x, P1y, mu1_A, mu1_B, mu2_B, mu2_A,
+                                gamma_R, gamma_S                                            */
+  ARDG_MESH_BFACE_GEOM = 3,  /* double [E_bdy][6]: P1x, P1y, mu_A, mu_B, gamma_R, gamma_S  */
+  ARDG_MESH_ELEM_FACES = 4   /* int32 [K][3]: (edge index << 1) | side (0: side 1)         */
+};
+
+typedef struct ardg_ops_s* ardg_ops;
+typedef struct ardg_mesh_s* ardg_mesh;
+typedef struct ardg_batch_s* ardg_batch;
+
+typedef struct {
+  int64_t K, Np, Nfp, E_int, E_bdy;
+  int32_t N, device;
+  double min_J;                /* smallest element Jacobian                              */
+  double min_area_ratio;       /* smallest parallelogram area / quadrilateral area       */
+} ardg_mesh_info_t;
+
+/* Reference operators of order N (sections "Nodal discontinuous Galerkin
+ * method" and "Reconstruction"): nodes, orthonormal basis, Dr, Ds, M, LIFT, the
+ * three node orderings, the (N+1)^2-unknown least-squares reconstruction and
+ * the constant per-edge operators that follow from the parallelogram map being
+ * affine (Algorithm aRDG).  Built in FP64 on the host.
+ * N: 1..6.  node_family: 0 (warp-and-blend, blend parameter 0).
+ * Errors: E_INVALID_ARG (null out), E_UNSUPPORTED (N or family), E_RECON_RANK. */
+ardg_status ardg_ops_create(int32_t N, int32_t node_family, ardg_ops* out);
+
+/* Copy one reference operator (selector ARDG_OPS_*) into dst[cap] as doubles.
+ * n_written receives the element count (also when cap is too small, in which
+ * case E_INVALID_ARG is returned and nothing is written). */
+ardg_status ardg_ops_export(ardg_ops ops, int32_t which, double* dst, int64_t cap,
+                            int64_t* n_written);
+void ardg_ops_destroy(ardg_ops ops);
+
+/* Build a mesh: connectivity, element geometry (eqs. mapping_tri_diff,
+ * triangle_jacobian_a/b), the enclosed parallelogram of every interior edge
+ * (section "Enclosed parallelogram": the maximum-area parallelogram whose
+ * diagonal is the shared edge), the apex coordinates in each element's rotated
+ * frame (section "Reordering nodes in the reference domain") and the two
+ * constant factors gamma = n1 . (r'_x, r'_y), n1 . (s'_x, s'_y) of the
+ * parallelogram; boundary faces get the mirror-ghost rhombus.
+ * vxy: host [Nv][2] doubles; etov: host [K][3] int32, counter-clockwise.
+ * face_bc: reserved, must be NULL (all boundary faces are zero Dirichlet).
+ * device: HIP device ordinal, or -1 for a host-only mesh (setup and export
+ * only; kernels refuse it).  Errors: E_INVALID_ARG, E_MESH_ORIENTATION,
+ * E_MESH_TOPOLOGY, E_DEGENERATE_PARALLELOGRAM, E_HIP, E_OOM. */
+ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const int32_t* etov,
+                             int64_t K, const int32_t* face_bc, int32_t device, ardg_mesh* out);
+ardg_status ardg_mesh_info(ardg_mesh mesh, ardg_mesh_info_t* out);
+/* Export a mesh table (selector ARDG_MESH_*); dst is host memory of cap bytes. */
+ardg_status ardg_mesh_export(ardg_mesh mesh, int32_t which, void* dst, int64_t cap,
+                             int64_t* n_written);
+void ardg_mesh_destroy(ardg_mesh mesh);
+
+/* Diffusion coefficient (eq. diffusion; element-wise form of eq.
+ * NDG_diffusion_once_matrixForm_reference_general with Algorithm 1).
+ * mode ARDG_D_CONST: D[nfields] host doubles, one constant per field.
+ * mode ARDG_D_ELEMENT: D[K] host doubles (nfields must be 1); the flux is then
+ * Algorithm 1's reconstruction of D grad u~.  All values must be finite > 0. */
+ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfields,
+                                    const double* D);
+
+/* Velocity of the convective term of eq. convection_diffusion, for every
+ * field: ARDG_VEL_NONE, or ARDG_VEL_AFFINE with v(x,y) = (p0 + p2 x + p3 y,
+ * p1 + p4 x + p5 y), params[6] on the host (v = (-y, x) is {0,0,0,-1,1,0}).
+ * Nodal collocation of v u, strong form, upwind flux; u+ = 0 outside. */
+ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* params);
+
+/* du/dt for nfields fields (one RHS evaluation = one Runge-Kutta stage).
+ * precision ARDG_FP64: u_dev, rhs_dev are double [F][K][Np];
+ * ARDG_FP32: float [F][K][Np] (operators and arithmetic in FP32, operators
+ * built in FP64).  Enqueued on hip_stream (hipStream_t, NULL = default);
+ * uses a flux buffer owned by the mesh.  t is accepted for API symmetry (no
+ * term depends on time).  Errors: E_INVALID_ARG, E_UNSUPPORTED, E_HIP. */
+ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
+                          void* rhs_dev, double t, void* hip_stream);
+
+/* Edge fluxes only (the interior and boundary loop of Algorithm aRDG with the
+ * diagonal flux; Algorithm 1 for element-wise D): flux_dev [F][E][Nfp] in the
+ * precision's type, D included.  A parity hook for the edge kernel. */
+ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfields,
+                                const void* u_dev, void* flux_dev, void* hip_stream);
+
+/* Bytes of device workspace ardg_rk_step needs for (scheme, precision, nfields). */
+ardg_status ardg_rk_workspace_bytes(ardg_mesh mesh, int32_t scheme, int32_t precision,
+                                    int32_t nfields, int64_t* bytes);
+
+/* Advance the FP64 state u_dev [F][K][Np] by nsteps steps of size dt with the
+ * classic RK4 (4 stages) or the five-stage low-storage RK (paper's integrator).
+ * The state update is FP64 in every precision; in ARDG_FP32 the operators act
+ * on an FP32 copy of each stage's input.  work_dev: caller-owned device memory
+ * of ardg_rk_workspace_bytes bytes, 256-byte aligned.  The step loop is
+ * captured once per (scheme, precision, nfields, buffers, nsteps, dt) into a
+ * HIP graph and replayed.  Errors: E_INVALID_ARG, E_UNSUPPORTED, E_HIP. */
+ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
+                         double* u_dev, void* work_dev, double t0, double dt, int32_t nsteps,
+                         void* hip_stream);
+
+/* Kernel timing hook (profiling): run `reps` Runge-Kutta stages of the same
+ * configuration as ardg_rk_step with plain launches (no graph), recording HIP
+ * events on hip_stream around each kernel, and return the average duration
+ * in milliseconds of the edge kernel (out_ms[0]) and of the element kernel
+ * with its fused update (out_ms[1]).  Advances u_dev like ardg_rk_step
+ * (reps must be a multiple of the scheme's stage count).  Synchronises the
+ * stream.  Errors as ardg_rk_step. */
+ardg_status ardg_stage_timing(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
+                              double* u_dev, void* work_dev, double dt, int32_t reps,
+                              void* hip_stream, float* out_ms);
+
+/* Synchronise the stream and scan the FP64 state for non-finite values
+ * (E_NONFINITE if any).  u_dev: double [F][K][Np]. */
+ardg_status ardg_check(ardg_mesh mesh, int32_t nfields, const double* u_dev, void* hip_stream);
+
+const char* ardg_status_string(ardg_status s);
+const char* ardg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARDG_H */

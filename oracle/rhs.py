@@ -37,7 +37,7 @@ class Problem:
     """
 
     def __init__(self, vxy, etov, N: int, D, D_mode: str = "const",
-                 velocity=None, nfields: int = 1):
+                 velocity=None, nfields: int = 1, build_edges: bool = True):
         self.geom = Geometry(vxy, etov)
         self.ops = RefOps(N)
         self.N = N
@@ -55,7 +55,8 @@ class Problem:
         else:
             raise ValueError(D_mode)
         self.velocity = velocity   # None or (v0x, v0y, W11, W12, W21, W22)
-        self._build_edges()
+        if build_edges:
+            self._build_edges()
 
     # -- per-edge operators (literal Algorithm aRDG / Algorithm 1) -----------
     def _build_edges(self):
@@ -188,6 +189,100 @@ class Problem:
             scale = (g.sJ[:, f] / g.J)[:, None]
             surf += scale * (fs[:, f, :] @ ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp].T)
         return vol - surf
+
+    # -- RHS of a few elements only (sampled checks on large meshes) ---------
+    def _face_flux_one(self, u, k, f, field):
+        """Flux seen by face f of element k (CCW order), computed for that one
+        edge with the same steps as the full assembly."""
+        g, ops = self.geom, self.ops
+        k2 = int(g.EToE[k, f])
+        if k2 < 0:
+            eg = ardg.boundary_edge_geometry(g, k, f)
+            if self.D_mode == "element":
+                W = ardg.boundary_edge_operator_alg1(ops, g, k, f, eg, self.Delem[k])
+                F = W @ u[k]
+            else:
+                F = self.Dfield[field] * (ardg.boundary_edge_operator(ops, g, k, f, eg) @ u[k])
+            return F
+        f2 = int(g.EToF[k, f])
+        k1, fa, kb, fb = (k, f, k2, f2) if k < k2 else (k2, f2, k, f)
+        eg = ardg.interior_edge_geometry(g, k1, fa, kb, fb)
+        if self.D_mode == "element":
+            W1, W2 = ardg.edge_operator_alg1(ops, eg, fa, fb, self.Delem[k1], self.Delem[kb])
+            F = W1 @ u[k1] + W2 @ u[kb]
+        else:
+            W1, W2 = ardg.edge_operator(ops, eg, fa, fb)
+            F = self.Dfield[field] * (W1 @ u[k1] + W2 @ u[kb])
+        return F if k == k1 else -F[::-1]
+
+    def rhs_elements(self, u, elements, field: int = 0):
+        """du/dt on the listed elements only, [len(elements), Np]; u [K, Np]
+        needs valid values on the listed elements and their face neighbours."""
+        ops, g = self.ops, self.geom
+        out = np.zeros((len(elements), ops.Np))
+        xyn = g.physical(ops.rs) if self.velocity is not None else None
+        for n, k in enumerate(elements):
+            rx, ry, sx, sy = g.rx[k], g.ry[k], g.sx[k], g.sy[k]
+            uk = u[k]
+            qx = rx * (ops.Dr @ uk) + sx * (ops.Ds @ uk)
+            qy = ry * (ops.Dr @ uk) + sy * (ops.Ds @ uk)
+            Dk = self.Delem[k] if self.D_mode == "element" else self.Dfield[field]
+            r = -Dk * (rx * (ops.Drw @ qx) + sx * (ops.Dsw @ qx) + ry * (ops.Drw @ qy) + sy * (ops.Dsw @ qy))
+            for f in range(3):
+                F = self._face_flux_one(u, k, f, field)
+                Lf = ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp]
+                r = r + g.sJ[k, f] / g.J[k] * (Lf @ F)
+            if self.velocity is not None:
+                vx, vy = self.velocity_at(xyn[k])
+                fx, fy = vx * uk, vy * uk
+                r = r + rx * (ops.Drw @ fx) + sx * (ops.Dsw @ fx) + ry * (ops.Drw @ fy) + sy * (ops.Dsw @ fy)
+                for f in range(3):
+                    idx = ops.fmask[f]
+                    vn = g.nx[k, f] * vx[idx] + g.ny[k, f] * vy[idx]
+                    k2 = g.EToE[k, f]
+                    up = np.zeros(ops.Nfp) if k2 < 0 else u[k2, ops.fmask[g.EToF[k, f]]][::-1]
+                    fs = np.maximum(vn, 0.0) * uk[idx] + np.minimum(vn, 0.0) * up
+                    Lf = ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp]
+                    r = r - g.sJ[k, f] / g.J[k] * (Lf @ fs)
+            out[n] = r
+        return out
+
+    def neighbourhood(self, elements, layers: int):
+        """Elements within `layers` face-neighbour hops of the given ones."""
+        cur = set(int(k) for k in elements)
+        for _ in range(layers):
+            nxt = set(cur)
+            for k in cur:
+                for k2 in self.geom.EToE[k]:
+                    if k2 >= 0:
+                        nxt.add(int(k2))
+            cur = nxt
+        return sorted(cur)
+
+    def rk4_step_elements(self, u, dt, elements, field: int = 0):
+        """One classic RK4 step evaluated on the listed elements only, using
+        the patches of neighbours each stage needs.  Returns [len, Np]."""
+        P = [sorted(set(int(k) for k in elements))]
+        for _ in range(4):
+            P.append(self.neighbourhood(P[-1], 1))
+        K, Np = u.shape
+        stage_in = u
+        acc = {}
+        ks = []
+        for s in range(4):
+            patch = P[3 - s]
+            r = self.rhs_elements(stage_in, patch, field)
+            ks.append(dict(zip(patch, r)))
+            if s < 3:
+                c = 0.5 if s < 2 else 1.0
+                nxt = np.full((K, Np), np.nan)
+                for k, rk in zip(patch, r):
+                    nxt[k] = u[k] + c * dt * rk
+                stage_in = nxt
+        out = np.zeros((len(elements), Np))
+        for n, k in enumerate(elements):
+            out[n] = u[k] + dt / 6.0 * (ks[0][k] + 2 * ks[1][k] + 2 * ks[2][k] + ks[3][k])
+        return out
 
     # -- nodal coordinates ------------------------------------------------------
     def nodal_xy(self):

@@ -1,0 +1,694 @@
+// C ABI of the library: handles, validation, device uploads, launch sequences
+// and the HIP-graph-captured Runge-Kutta loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ardg.h"
+#include "device.hpp"
+#include "meshsetup.hpp"
+#include "refops.hpp"
+
+using namespace ardg;
+
+namespace {
+
+thread_local std::string g_err;
+
+ardg_status fail(ardg_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+ardg_status hip_fail(hipError_t e, const char* what) {
+  return fail(ARDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                         \
+  do {                                              \
+    hipError_t _e = (expr);                         \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+void pack_into(const RefOps& o, std::vector<double>& out) {
+  const OpLayout L(o.N);
+  out.assign(L.total, 0.0);
+  auto put = [&](int off, const Mat& M) { std::copy(M.a.begin(), M.a.end(), out.begin() + off); };
+  put(L.n2b, o.N2B);
+  put(L.kr, o.KR);
+  put(L.ks, o.KS);
+  put(L.kbr, o.KBR);
+  put(L.kbs, o.KBS);
+  put(L.u1r, o.U1R);
+  put(L.u1s, o.U1S);
+  put(L.u2r, o.U2R);
+  put(L.u2s, o.U2S);
+  put(L.ubr, o.UBR);
+  put(L.ubs, o.UBS);
+  put(L.dr, o.Dr);
+  put(L.ds, o.Ds);
+  put(L.lift, o.LIFT);
+  for (int j = 0; j < o.Nfp; ++j) out[L.tau + j] = 0.5 * (o.lgl[j] + 1.0);
+  for (int n = 0; n < o.Np; ++n) {
+    out[L.nr + n] = o.r[n];
+    out[L.ns + n] = o.s[n];
+  }
+}
+
+template <typename T>
+ardg_status upload(const T* src, size_t n, T** dst) {
+  if (n == 0) { *dst = nullptr; return ARDG_OK; }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) return fail(ARDG_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = hipMemcpy(p, src, n * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_fail(e, "hipMemcpy");
+  }
+  *dst = (T*)p;
+  return ARDG_OK;
+}
+
+}  // namespace
+
+struct ardg_ops_s {
+  RefOps ro;
+  std::vector<double> packed;
+};
+
+struct GraphKey {
+  int scheme, precision, nfields, nsteps;
+  const void* u;
+  const void* work;
+  double dt;
+  uint64_t version;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(scheme, precision, nfields, nsteps, u, work, dt, version) <
+           std::tie(o.scheme, o.precision, o.nfields, o.nsteps, o.u, o.work, o.dt, o.version);
+  }
+};
+
+struct ardg_mesh_s {
+  int N = 0, device = -1;
+  RefOps ro;
+  std::vector<double> packed;
+  HostMesh hm;
+  DevMesh dm;
+  std::vector<void*> allocs;      // device allocations owned by the mesh
+  double* Delem_dev = nullptr;
+  double2* vn_dev = nullptr;
+  int nfields_D = 1;
+  void* flux_scratch = nullptr;
+  size_t flux_scratch_bytes = 0;
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  uint64_t version = 0;
+
+  ~ardg_mesh_s() {
+    if (device >= 0) {
+      DeviceGuard g(device);
+      for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+      if (cap_stream) (void)hipStreamDestroy(cap_stream);
+      for (void* p : allocs) (void)hipFree(p);
+      if (Delem_dev) (void)hipFree(Delem_dev);
+      if (vn_dev) (void)hipFree(vn_dev);
+      if (flux_scratch) (void)hipFree(flux_scratch);
+    }
+  }
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    ++version;
+  }
+};
+
+extern "C" {
+
+const char* ardg_last_error(void) { return g_err.c_str(); }
+
+const char* ardg_status_string(ardg_status s) {
+  switch (s) {
+    case ARDG_OK: return "ok";
+    case ARDG_E_INVALID_ARG: return "invalid argument";
+    case ARDG_E_MESH_ORIENTATION: return "element not counter-clockwise (J <= 0)";
+    case ARDG_E_MESH_TOPOLOGY: return "non-manifold or inconsistently oriented mesh";
+    case ARDG_E_DEGENERATE_PARALLELOGRAM: return "degenerate enclosed parallelogram";
+    case ARDG_E_RECON_RANK: return "reconstruction system rank deficient";
+    case ARDG_E_UNSUPPORTED: return "unsupported order or precision";
+    case ARDG_E_HIP: return "HIP runtime error";
+    case ARDG_E_OOM: return "out of device memory";
+    case ARDG_E_NONFINITE: return "non-finite value in state";
+    default: return "unknown status";
+  }
+}
+
+ardg_status ardg_ops_create(int32_t N, int32_t node_family, ardg_ops* out) {
+  if (!out) return fail(ARDG_E_INVALID_ARG, "ops_create: null out");
+  *out = nullptr;
+  if (N < 1 || N > 6) return fail(ARDG_E_UNSUPPORTED, "ops_create: N must be in 1..6");
+  if (node_family != 0) return fail(ARDG_E_UNSUPPORTED, "ops_create: node_family must be 0");
+  try {
+    auto o = std::make_unique<ardg_ops_s>();
+    bool rank_ok = true;
+    o->ro = build_refops(N, &rank_ok);
+    if (!rank_ok) return fail(ARDG_E_RECON_RANK, "ops_create: reconstruction system rank deficient");
+    pack_into(o->ro, o->packed);
+    *out = o.release();
+    return ARDG_OK;
+  } catch (const std::exception& ex) {
+    return fail(ARDG_E_INVALID_ARG, std::string("ops_create: ") + ex.what());
+  }
+}
+
+void ardg_ops_destroy(ardg_ops ops) { delete ops; }
+
+ardg_status ardg_ops_export(ardg_ops ops, int32_t which, double* dst, int64_t cap, int64_t* n_written) {
+  if (!ops) return fail(ARDG_E_INVALID_ARG, "ops_export: null handle");
+  const RefOps& o = ops->ro;
+  std::vector<double> v;
+  auto mat = [&](const Mat& M) { v = M.a; };
+  switch (which) {
+    case ARDG_OPS_NODES:
+      for (int n = 0; n < o.Np; ++n) { v.push_back(o.r[n]); v.push_back(o.s[n]); }
+      break;
+    case ARDG_OPS_V: mat(o.V); break;
+    case ARDG_OPS_DR: mat(o.Dr); break;
+    case ARDG_OPS_DS: mat(o.Ds); break;
+    case ARDG_OPS_MASS: mat(o.M); break;
+    case ARDG_OPS_LIFT: mat(o.LIFT); break;
+    case ARDG_OPS_FACE_NODES:
+      for (int f = 0; f < 3; ++f)
+        for (int j = 0; j < o.Nfp; ++j) v.push_back(o.fmask[f][j]);
+      break;
+    case ARDG_OPS_ROT_PERM:
+      for (int f = 0; f < 3; ++f)
+        for (int n = 0; n < o.Np; ++n) v.push_back(o.rot[f][n]);
+      break;
+    case ARDG_OPS_RECON_A: mat(o.A); break;
+    case ARDG_OPS_RECON_R: mat(o.Rop); break;
+    case ARDG_OPS_RECON_GRAD: mat(o.recon_grad_nodal); break;
+    case ARDG_OPS_ALG1_GRAD: mat(o.alg1_nodal); break;
+    case ARDG_OPS_N2B: mat(o.N2B); break;
+    default: return fail(ARDG_E_INVALID_ARG, "ops_export: unknown selector");
+  }
+  if (n_written) *n_written = (int64_t)v.size();
+  if (!dst || cap < (int64_t)v.size()) return fail(ARDG_E_INVALID_ARG, "ops_export: buffer too small");
+  std::copy(v.begin(), v.end(), dst);
+  return ARDG_OK;
+}
+
+ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const int32_t* etov,
+                             int64_t K, const int32_t* face_bc, int32_t device, ardg_mesh* out) {
+  if (!out) return fail(ARDG_E_INVALID_ARG, "mesh_create: null out");
+  *out = nullptr;
+  if (!ops) return fail(ARDG_E_INVALID_ARG, "mesh_create: null ops");
+  if (face_bc) return fail(ARDG_E_INVALID_ARG, "mesh_create: face_bc is reserved and must be NULL");
+  try {
+    auto m = std::make_unique<ardg_mesh_s>();
+    m->N = ops->ro.N;
+    m->ro = ops->ro;
+    m->packed = ops->packed;
+    std::string err;
+    int st = build_host_mesh(vxy, Nv, etov, K, m->hm, err);
+    if (st != ARDG_OK) return fail(st, err);
+    m->dm.N = m->N;
+    m->dm.K = m->hm.K;
+    m->dm.E_int = m->hm.E_int;
+    m->dm.E_bdy = m->hm.E_bdy;
+    for (int f = 0; f < kMaxFields; ++f) m->dm.Dfield[f] = 1.0;
+    if (device < 0) {
+      m->device = -1;
+      *out = m.release();
+      return ARDG_OK;
+    }
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device >= ndev) return fail(ARDG_E_INVALID_ARG, "mesh_create: no such device");
+    DeviceGuard g(device);
+    if (!g.ok) return fail(ARDG_E_HIP, "mesh_create: hipSetDevice failed");
+    m->device = device;
+    const HostMesh& h = m->hm;
+    // device tables
+    std::vector<int2> ef(h.E_int);
+    std::vector<double2> mu1(h.E_int), mu2(h.E_int), gam(h.E_int);
+    for (int64_t e = 0; e < h.E_int; ++e) {
+      ef[e].x = h.e1[e] | (h.f1[e] << 30);
+      ef[e].y = h.e2[e] | (h.f2[e] << 30);
+      mu1[e] = make_double2(h.mu1[2 * e], h.mu1[2 * e + 1]);
+      mu2[e] = make_double2(h.mu2[2 * e], h.mu2[2 * e + 1]);
+      gam[e] = make_double2(h.gam[2 * e], h.gam[2 * e + 1]);
+    }
+    std::vector<int> bk(h.E_bdy);
+    std::vector<double2> bmu(h.E_bdy), bgam(h.E_bdy);
+    for (int64_t b = 0; b < h.E_bdy; ++b) {
+      bk[b] = h.bk[b] | (h.bf[b] << 30);
+      bmu[b] = make_double2(h.bmu[2 * b], h.bmu[2 * b + 1]);
+      bgam[b] = make_double2(h.bgam[2 * b], h.bgam[2 * b + 1]);
+    }
+    std::vector<double2> vert(3 * h.K);
+    for (int64_t k = 0; k < h.K; ++k)
+      for (int c = 0; c < 3; ++c) {
+        const int v = h.etov[3 * k + c];
+        vert[3 * k + c] = make_double2(h.vxy[2 * v], h.vxy[2 * v + 1]);
+      }
+    std::vector<int> efc(3 * h.K);
+    for (int64_t k = 0; k < h.K; ++k)
+      for (int f = 0; f < 3; ++f) efc[f * h.K + k] = h.elem_face[3 * k + f];
+    std::vector<float> packed32(m->packed.begin(), m->packed.end());
+
+    int2* d_ef; double2 *d_mu1, *d_mu2, *d_gam, *d_bmu, *d_bgam, *d_vert;
+    int *d_bk, *d_efc;
+    double* d_ops64;
+    float* d_ops32;
+    ardg_status s;
+#define UP(vec, ptr)                                           \
+    s = upload(vec.data(), vec.size(), &ptr);                  \
+    if (s != ARDG_OK) return s;                                \
+    if (ptr) m->allocs.push_back((void*)ptr);
+    UP(ef, d_ef) UP(mu1, d_mu1) UP(mu2, d_mu2) UP(gam, d_gam) UP(bk, d_bk) UP(bmu, d_bmu)
+    UP(bgam, d_bgam) UP(vert, d_vert) UP(efc, d_efc) UP(m->packed, d_ops64) UP(packed32, d_ops32)
+#undef UP
+    m->dm.ef = d_ef;
+    m->dm.mu1 = d_mu1;
+    m->dm.mu2 = d_mu2;
+    m->dm.gam = d_gam;
+    m->dm.bk = d_bk;
+    m->dm.bmu = d_bmu;
+    m->dm.bgam = d_bgam;
+    m->dm.vert = d_vert;
+    m->dm.elem_face = d_efc;
+    m->dm.ops64 = d_ops64;
+    m->dm.ops32 = d_ops32;
+    *out = m.release();
+    return ARDG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ARDG_E_OOM, "mesh_create: host allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(ARDG_E_INVALID_ARG, std::string("mesh_create: ") + ex.what());
+  }
+}
+
+void ardg_mesh_destroy(ardg_mesh mesh) { delete mesh; }
+
+ardg_status ardg_mesh_info(ardg_mesh mesh, ardg_mesh_info_t* out) {
+  if (!mesh || !out) return fail(ARDG_E_INVALID_ARG, "mesh_info: null argument");
+  out->K = mesh->hm.K;
+  out->Np = mesh->ro.Np;
+  out->Nfp = mesh->ro.Nfp;
+  out->E_int = mesh->hm.E_int;
+  out->E_bdy = mesh->hm.E_bdy;
+  out->N = mesh->N;
+  out->device = mesh->device;
+  out->min_J = mesh->hm.min_J;
+  out->min_area_ratio = mesh->hm.min_area_ratio;
+  return ARDG_OK;
+}
+
+ardg_status ardg_mesh_export(ardg_mesh mesh, int32_t which, void* dst, int64_t cap, int64_t* n_written) {
+  if (!mesh) return fail(ARDG_E_INVALID_ARG, "mesh_export: null handle");
+  const HostMesh& h = mesh->hm;
+  std::vector<int32_t> iv;
+  std::vector<double> dv;
+  bool is_int = true;
+  switch (which) {
+    case ARDG_MESH_EDGES:
+      for (int64_t e = 0; e < h.E_int; ++e) {
+        iv.push_back(h.e1[e]); iv.push_back(h.f1[e]); iv.push_back(h.e2[e]); iv.push_back(h.f2[e]);
+      }
+      break;
+    case ARDG_MESH_BFACES:
+      for (int64_t b = 0; b < h.E_bdy; ++b) { iv.push_back(h.bk[b]); iv.push_back(h.bf[b]); }
+      break;
+    case ARDG_MESH_ELEM_FACES: iv = h.elem_face; break;
+    case ARDG_MESH_EDGE_GEOM:
+      is_int = false;
+      for (int64_t e = 0; e < h.E_int; ++e) {
+        const double row[8] = {h.P1[2 * e], h.P1[2 * e + 1], h.mu1[2 * e], h.mu1[2 * e + 1],
+                               h.mu2[2 * e], h.mu2[2 * e + 1], h.gam[2 * e], h.gam[2 * e + 1]};
+        dv.insert(dv.end(), row, row + 8);
+      }
+      break;
+    case ARDG_MESH_BFACE_GEOM:
+      is_int = false;
+      for (int64_t b = 0; b < h.E_bdy; ++b) {
+        const double row[6] = {h.bP1[2 * b], h.bP1[2 * b + 1], h.bmu[2 * b], h.bmu[2 * b + 1],
+                               h.bgam[2 * b], h.bgam[2 * b + 1]};
+        dv.insert(dv.end(), row, row + 6);
+      }
+      break;
+    default: return fail(ARDG_E_INVALID_ARG, "mesh_export: unknown selector");
+  }
+  const int64_t bytes = is_int ? (int64_t)(iv.size() * 4) : (int64_t)(dv.size() * 8);
+  if (n_written) *n_written = is_int ? (int64_t)iv.size() : (int64_t)dv.size();
+  if (!dst || cap < bytes) return fail(ARDG_E_INVALID_ARG, "mesh_export: buffer too small");
+  if (bytes) std::memcpy(dst, is_int ? (const void*)iv.data() : (const void*)dv.data(), bytes);
+  return ARDG_OK;
+}
+
+ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfields, const double* D) {
+  if (!mesh || !D) return fail(ARDG_E_INVALID_ARG, "set_diffusion: null argument");
+  if (mode == ARDG_D_CONST) {
+    if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "set_diffusion: nfields");
+    for (int f = 0; f < nfields; ++f)
+      if (!(std::isfinite(D[f]) && D[f] > 0)) return fail(ARDG_E_INVALID_ARG, "set_diffusion: D must be finite > 0");
+    for (int f = 0; f < kMaxFields; ++f) mesh->dm.Dfield[f] = D[std::min(f, nfields - 1)];
+    mesh->dm.alg1 = 0;
+    mesh->nfields_D = nfields;
+  } else if (mode == ARDG_D_ELEMENT) {
+    if (nfields != 1) return fail(ARDG_E_INVALID_ARG, "set_diffusion: element-wise D needs nfields == 1");
+    const int64_t K = mesh->hm.K;
+    for (int64_t k = 0; k < K; ++k)
+      if (!(std::isfinite(D[k]) && D[k] > 0)) return fail(ARDG_E_INVALID_ARG, "set_diffusion: D must be finite > 0");
+    if (mesh->device >= 0) {
+      DeviceGuard g(mesh->device);
+      if (mesh->Delem_dev) { (void)hipFree(mesh->Delem_dev); mesh->Delem_dev = nullptr; }
+      ardg_status s = upload(D, (size_t)K, &mesh->Delem_dev);
+      if (s != ARDG_OK) return s;
+      mesh->dm.Delem = mesh->Delem_dev;
+    }
+    mesh->dm.alg1 = 1;
+    mesh->nfields_D = 1;
+  } else {
+    return fail(ARDG_E_INVALID_ARG, "set_diffusion: unknown mode");
+  }
+  mesh->drop_graphs();
+  return ARDG_OK;
+}
+
+ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* params) {
+  if (!mesh) return fail(ARDG_E_INVALID_ARG, "set_velocity: null handle");
+  if (kind == ARDG_VEL_NONE) {
+    mesh->dm.conv = 0;
+    mesh->drop_graphs();
+    return ARDG_OK;
+  }
+  if (kind != ARDG_VEL_AFFINE || !params) return fail(ARDG_E_INVALID_ARG, "set_velocity: bad kind or params");
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(params[i])) return fail(ARDG_E_INVALID_ARG, "set_velocity: non-finite parameter");
+  const HostMesh& h = mesh->hm;
+  const int rotv[3][3] = {{2, 0, 1}, {0, 1, 2}, {1, 2, 0}};
+  auto vel = [&](double x, double y, double* v) {
+    v[0] = params[0] + params[2] * x + params[3] * y;
+    v[1] = params[1] + params[4] * x + params[5] * y;
+  };
+  std::vector<double2> vn(h.E_int + h.E_bdy);
+  auto edge_vn = [&](int64_t k, int f) {
+    const int a = h.etov[3 * k + rotv[f][1]], b = h.etov[3 * k + rotv[f][2]];
+    const double ax = h.vxy[2 * a], ay = h.vxy[2 * a + 1], bx = h.vxy[2 * b], by = h.vxy[2 * b + 1];
+    const double tx = bx - ax, ty = by - ay, L = std::sqrt(tx * tx + ty * ty);
+    const double nx = ty / L, ny = -tx / L;
+    double va[2], vb[2];
+    vel(ax, ay, va);
+    vel(bx, by, vb);
+    return make_double2(nx * va[0] + ny * va[1], nx * vb[0] + ny * vb[1]);
+  };
+  for (int64_t e = 0; e < h.E_int; ++e) vn[e] = edge_vn(h.e1[e], h.f1[e]);
+  for (int64_t b = 0; b < h.E_bdy; ++b) vn[h.E_int + b] = edge_vn(h.bk[b], h.bf[b]);
+  if (mesh->device >= 0) {
+    DeviceGuard g(mesh->device);
+    if (mesh->vn_dev) { (void)hipFree(mesh->vn_dev); mesh->vn_dev = nullptr; }
+    ardg_status s = upload(vn.data(), vn.size(), &mesh->vn_dev);
+    if (s != ARDG_OK) return s;
+    mesh->dm.vn = mesh->vn_dev;
+  }
+  for (int i = 0; i < 6; ++i) mesh->dm.vel[i] = params[i];
+  mesh->dm.conv = 1;
+  mesh->drop_graphs();
+  return ARDG_OK;
+}
+
+static ardg_status check_compute(ardg_mesh mesh, int32_t precision, int32_t nfields) {
+  if (!mesh) return fail(ARDG_E_INVALID_ARG, "null mesh");
+  if (mesh->device < 0) return fail(ARDG_E_INVALID_ARG, "mesh was created host-only (device -1)");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32)
+    return fail(ARDG_E_UNSUPPORTED, "precision not built (FP64 and FP32 are)");
+  if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "nfields out of range");
+  if (mesh->dm.alg1 && nfields != 1) return fail(ARDG_E_INVALID_ARG, "element-wise D is for one field");
+  if (!mesh->dm.alg1 && nfields > mesh->nfields_D && mesh->nfields_D != 1)
+    return fail(ARDG_E_INVALID_ARG, "more fields than diffusion coefficients");
+  return ARDG_OK;
+}
+
+static ardg_status ensure_scratch(ardg_mesh mesh, size_t bytes) {
+  if (mesh->flux_scratch_bytes >= bytes) return ARDG_OK;
+  if (mesh->flux_scratch) (void)hipFree(mesh->flux_scratch);
+  mesh->flux_scratch = nullptr;
+  mesh->flux_scratch_bytes = 0;
+  hipError_t e = hipMalloc(&mesh->flux_scratch, bytes);
+  if (e != hipSuccess) return fail(ARDG_E_OOM, "flux scratch allocation failed");
+  mesh->flux_scratch_bytes = bytes;
+  return ARDG_OK;
+}
+
+ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
+                                void* flux_dev, void* hip_stream) {
+  ardg_status s = check_compute(mesh, precision, nfields);
+  if (s != ARDG_OK) return s;
+  if (!u_dev || !flux_dev) return fail(ARDG_E_INVALID_ARG, "edge_flux_eval: null buffer");
+  DeviceGuard g(mesh->device);
+  HIP_TRY(launch_edge_flux(mesh->dm, precision == ARDG_FP64, nfields, u_dev, flux_dev,
+                           (hipStream_t)hip_stream), "edge flux launch");
+  return ARDG_OK;
+}
+
+ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
+                          void* rhs_dev, double t, void* hip_stream) {
+  (void)t;
+  ardg_status s = check_compute(mesh, precision, nfields);
+  if (s != ARDG_OK) return s;
+  if (!u_dev || !rhs_dev) return fail(ARDG_E_INVALID_ARG, "rhs_eval: null buffer");
+  DeviceGuard g(mesh->device);
+  const size_t ts = precision == ARDG_FP64 ? 8 : 4;
+  const size_t fb = (size_t)nfields * (mesh->hm.E_int + mesh->hm.E_bdy) * mesh->ro.Nfp * ts;
+  s = ensure_scratch(mesh, fb);
+  if (s != ARDG_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool f64 = precision == ARDG_FP64;
+  HIP_TRY(launch_edge_flux(mesh->dm, f64, nfields, u_dev, mesh->flux_scratch, st), "edge flux launch");
+  Epilogue epi;
+  epi.kind = EPI_RHS;
+  epi.rhs_out = rhs_dev;
+  HIP_TRY(launch_element(mesh->dm, f64, nfields, u_dev, mesh->flux_scratch, epi, st), "element launch");
+  return ARDG_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Work {
+  double* acc;
+  void* v;
+  void* flux;
+};
+
+static void work_layout(ardg_mesh mesh, int precision, int nfields, size_t* total, Work* w, void* base) {
+  const size_t ts = precision == ARDG_FP64 ? 8 : 4;
+  const size_t n = (size_t)nfields * mesh->hm.K * mesh->ro.Np;
+  const size_t nf = (size_t)nfields * (mesh->hm.E_int + mesh->hm.E_bdy) * mesh->ro.Nfp;
+  const size_t b_acc = align256(n * 8), b_v = align256(n * ts), b_f = align256(nf * ts);
+  if (total) *total = b_acc + b_v + b_f;
+  if (w) {
+    char* p = (char*)base;
+    w->acc = (double*)p;
+    w->v = p + b_acc;
+    w->flux = p + b_acc + b_v;
+  }
+}
+
+ardg_status ardg_rk_workspace_bytes(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
+                                    int64_t* bytes) {
+  if (!mesh || !bytes) return fail(ARDG_E_INVALID_ARG, "rk_workspace_bytes: null argument");
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  size_t t = 0;
+  work_layout(mesh, precision, nfields, &t, nullptr, nullptr);
+  *bytes = (int64_t)t;
+  return ARDG_OK;
+}
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
+static const double kLsA[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                               -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0,
+                               -1275806237668.0 / 842570457699.0};
+static const double kLsB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+static hipError_t enqueue_steps(ardg_mesh mesh, int scheme, int precision, int nfields, double* u,
+                                const Work& w, double dt, int nsteps, hipStream_t st) {
+  const bool f64 = precision == ARDG_FP64;
+  const int64_t n = (int64_t)nfields * mesh->hm.K * mesh->ro.Np;
+  hipError_t e;
+  if (!f64) {
+    e = launch_to_f32(u, (float*)w.v, n, st);
+    if (e != hipSuccess) return e;
+  }
+  Epilogue epi;
+  epi.u = u;
+  epi.acc = w.acc;
+  epi.dt = dt;
+  for (int step = 0; step < nsteps; ++step) {
+    const int nst = scheme == ARDG_RK4 ? 4 : 5;
+    for (int s = 0; s < nst; ++s) {
+      const void* vin;
+      if (f64)
+        vin = (scheme == ARDG_LSERK54 || s == 0) ? (const void*)u : w.v;
+      else
+        vin = w.v;
+      e = launch_edge_flux(mesh->dm, f64, nfields, vin, w.flux, st);
+      if (e != hipSuccess) return e;
+      epi.stage = s;
+      if (scheme == ARDG_RK4) {
+        epi.kind = EPI_RK4;
+        epi.vnext = (s < 3) ? w.v : (f64 ? nullptr : w.v);
+      } else {
+        epi.kind = EPI_LSERK;
+        epi.a = kLsA[s];
+        epi.b = kLsB[s];
+        epi.vnext = f64 ? nullptr : w.v;
+      }
+      e = launch_element(mesh->dm, f64, nfields, vin, w.flux, epi, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields, double* u_dev,
+                         void* work_dev, double t0, double dt, int32_t nsteps, void* hip_stream) {
+  (void)t0;
+  ardg_status s = check_compute(mesh, precision, nfields);
+  if (s != ARDG_OK) return s;
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  if (!u_dev || !work_dev) return fail(ARDG_E_INVALID_ARG, "rk_step: null buffer");
+  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "rk_step: work_dev not 256-byte aligned");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(ARDG_E_INVALID_ARG, "rk_step: bad nsteps or dt");
+  if (nsteps == 0) return ARDG_OK;
+  DeviceGuard g(mesh->device);
+  Work w;
+  work_layout(mesh, precision, nfields, nullptr, &w, work_dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  GraphKey key{scheme, precision, nfields, nsteps, u_dev, work_dev, dt, mesh->version};
+  auto it = mesh->graphs.find(key);
+  if (it == mesh->graphs.end()) {
+    if (!mesh->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&mesh->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRY(hipStreamBeginCapture(mesh->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e = enqueue_steps(mesh, scheme, precision, nfields, u_dev, w, dt, nsteps, mesh->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(mesh->cap_stream, &graph);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(e, "rk_step: launch during capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
+    if (mesh->graphs.size() >= 8) mesh->drop_graphs();
+    it = mesh->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, st), "hipGraphLaunch");
+  return ARDG_OK;
+}
+
+ardg_status ardg_stage_timing(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
+                              double* u_dev, void* work_dev, double dt, int32_t reps, void* hip_stream,
+                              float* out_ms) {
+  ardg_status s = check_compute(mesh, precision, nfields);
+  if (s != ARDG_OK) return s;
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  const int nst = scheme == ARDG_RK4 ? 4 : 5;
+  if (!u_dev || !work_dev || !out_ms || reps <= 0 || reps % nst != 0)
+    return fail(ARDG_E_INVALID_ARG, "stage_timing: bad arguments (reps must be a multiple of the stage count)");
+  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "stage_timing: work_dev not 256-byte aligned");
+  DeviceGuard g(mesh->device);
+  Work w;
+  work_layout(mesh, precision, nfields, nullptr, &w, work_dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool f64 = precision == ARDG_FP64;
+  std::vector<hipEvent_t> ev(3 * reps);
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+  hipError_t e = hipSuccess;
+  if (!f64) e = launch_to_f32(u_dev, (float*)w.v, (int64_t)nfields * mesh->hm.K * mesh->ro.Np, st);
+  Epilogue epi;
+  epi.u = u_dev;
+  epi.acc = w.acc;
+  epi.dt = dt;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    const int sidx = r % nst;
+    const void* vin = f64 ? ((scheme == ARDG_LSERK54 || sidx == 0) ? (const void*)u_dev : w.v) : w.v;
+    epi.stage = sidx;
+    if (scheme == ARDG_RK4) {
+      epi.kind = EPI_RK4;
+      epi.vnext = (sidx < 3) ? w.v : (f64 ? nullptr : w.v);
+    } else {
+      epi.kind = EPI_LSERK;
+      epi.a = kLsA[sidx];
+      epi.b = kLsB[sidx];
+      epi.vnext = f64 ? nullptr : w.v;
+    }
+    (void)hipEventRecord(ev[3 * r], st);
+    e = launch_edge_flux(mesh->dm, f64, nfields, vin, w.flux, st);
+    (void)hipEventRecord(ev[3 * r + 1], st);
+    if (e == hipSuccess) e = launch_element(mesh->dm, f64, nfields, vin, w.flux, epi, st);
+    (void)hipEventRecord(ev[3 * r + 2], st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  double te = 0.0, tl = 0.0;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    float a = 0.f, b = 0.f;
+    e = hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * r + 1], ev[3 * r + 2]);
+    te += a;
+    tl += b;
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(e, "stage_timing");
+  out_ms[0] = (float)(te / reps);
+  out_ms[1] = (float)(tl / reps);
+  return ARDG_OK;
+}
+
+ardg_status ardg_check(ardg_mesh mesh, int32_t nfields, const double* u_dev, void* hip_stream) {
+  if (!mesh || !u_dev) return fail(ARDG_E_INVALID_ARG, "check: null argument");
+  if (mesh->device < 0) return fail(ARDG_E_INVALID_ARG, "check: host-only mesh");
+  if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "check: nfields");
+  DeviceGuard g(mesh->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  int* cnt = nullptr;
+  HIP_TRY(hipMalloc(&cnt, sizeof(int)), "hipMalloc");
+  hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
+  if (e == hipSuccess) e = launch_nonfinite(u_dev, (int64_t)nfields * mesh->hm.K * mesh->ro.Np, cnt, st);
+  int host = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&host, cnt, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(cnt);
+  if (e != hipSuccess) return hip_fail(e, "check");
+  if (host) return fail(ARDG_E_NONFINITE, "check: " + std::to_string(host) + " non-finite values");
+  return ARDG_OK;
+}
+
+}  // extern "C"

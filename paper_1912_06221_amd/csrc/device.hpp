@@ -1,0 +1,86 @@
+// Device-side mesh description and kernel launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ardg {
+
+constexpr int kMaxFields = 16;
+
+// Offsets of the packed constant operators (same layout in FP64 and FP32).
+struct OpLayout {
+  int Np, Nfp;
+  int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, ubr, ubs, dr, ds, lift, tau, nr, ns, total;
+  __host__ __device__ constexpr OpLayout(int N)
+      : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
+        n2b(0),
+        kr(Np * Np),
+        ks(kr + Nfp * 2 * Np),
+        kbr(ks + Nfp * 2 * Np),
+        kbs(kbr + Nfp * Np),
+        u1r(kbs + Nfp * Np),
+        u1s(u1r + Nfp * 2 * Np),
+        u2r(u1s + Nfp * 2 * Np),
+        u2s(u2r + Nfp * 2 * Np),
+        ubr(u2s + Nfp * 2 * Np),
+        ubs(ubr + Nfp * Np),
+        dr(ubs + Nfp * Np),
+        ds(dr + Np * Np),
+        lift(ds + Np * Np),
+        tau(lift + Np * 3 * Nfp),
+        nr(tau + Nfp),
+        ns(nr + Np),
+        total(ns + Np) {}
+};
+
+struct DevMesh {
+  int N = 0;
+  int64_t K = 0, E_int = 0, E_bdy = 0;
+  // interior edges: element index in bits 0..29, face in bits 30..31
+  const int2* ef = nullptr;
+  const double2* mu1 = nullptr;   // apex weights (lambda_w2, lambda_w3), side 1
+  const double2* mu2 = nullptr;   // side 2
+  const double2* gam = nullptr;   // gamma_R, gamma_S
+  const int* bk = nullptr;        // boundary faces: element | face << 30
+  const double2* bmu = nullptr;
+  const double2* bgam = nullptr;
+  const double2* vert = nullptr;  // [K][3] vertex coordinates
+  const int* elem_face = nullptr; // [3][K] (edge << 1) | side
+  const double* Delem = nullptr;  // [K] when D is element-wise
+  const double2* vn = nullptr;    // [E] n1.v at A and at B (affine velocity)
+  const double* ops64 = nullptr;
+  const float* ops32 = nullptr;
+  int alg1 = 0;                   // element-wise D (Algorithm 1)
+  int conv = 0;                   // convective term on
+  double Dfield[kMaxFields] = {};
+  double vel[6] = {};             // v = (p0 + p2 x + p3 y, p1 + p4 x + p5 y)
+};
+
+// What the element kernel does after forming du/dt for its element.
+enum EpilogueKind { EPI_RHS = 0, EPI_RK4 = 1, EPI_LSERK = 2 };
+
+struct Epilogue {
+  int kind = EPI_RHS;
+  int stage = 0;
+  double dt = 0.0;
+  double a = 0.0, b = 0.0;        // LSERK stage coefficients
+  void* rhs_out = nullptr;        // EPI_RHS: [F][K][Np] in the compute type
+  double* u = nullptr;            // FP64 state
+  double* acc = nullptr;          // RK4 accumulator / LSERK residual (FP64)
+  void* vnext = nullptr;          // next stage input in the compute type (may be null)
+};
+
+// Edge fluxes of all interior and boundary edges for nfields fields.
+hipError_t launch_edge_flux(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
+                            hipStream_t st);
+// Element volume + LIFT of the fluxes + epilogue.
+hipError_t launch_element(const DevMesh& m, bool fp64, int nfields, const void* vin,
+                          const void* flux, const Epilogue& epi, hipStream_t st);
+// Copy an FP64 state into an FP32 copy (stage input of the FP32 mode).
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+// Count non-finite values of an FP64 array into *count_dev (int).
+hipError_t launch_nonfinite(const double* x, int64_t n, int* count_dev, hipStream_t st);
+
+}  // namespace ardg

@@ -1,0 +1,201 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances:
+* FP64: relative 1e-12.  On seeded uniform random data the measure is
+  max|rhs_gpu - rhs_oracle| / max|rhs_oracle|.  On smooth data the
+  difference is measured against the scale of the operator's terms,
+  max|L u_r| for random data u_r of the same amplitude, because the discrete
+  Laplacian's individual terms exceed its result by about N^4/h^2.  The RK
+  state after k steps: ||du||_M / ||u||_M.
+* FP32 (operators and arithmetic in FP32, built from FP64): the same
+  measures with 2e-4 (FP32 rounding ~6e-8 amplified by the operator norm, up
+  to ~1e3 at N=6).  The FP64 RK update keeps state errors at that level.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import library_mesh, make_case, oracle_problem, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-4
+
+
+def _flux_oracle(pr, u, nfields):
+    out = []
+    for f in range(nfields):
+        Fi, Fb = pr.diffusive_flux(u[f], f)
+        if pr.velocity is not None:
+            fs = pr.upwind_face_flux(u[f])
+            ie = pr.int_edges
+            Fi = Fi - np.array([fs[k1, f1] for (k1, f1, _, _) in ie]).reshape(Fi.shape)
+            Fb = Fb - np.array([fs[k, fb] for (k, fb) in pr.bdy_edges]).reshape(Fb.shape)
+        out.append(np.vstack([Fi, Fb]))
+    return np.stack(out)
+
+
+CASES = [
+    # m, jitter, N, D_mode, velocity, nfields
+    (12, 0.2, 1, "const", None, 1),
+    (12, 0.2, 2, "const", None, 1),
+    (11, 0.2, 3, "const", None, 1),
+    (12, 0.25, 4, "const", None, 1),
+    (9, 0.2, 5, "const", None, 1),
+    (9, 0.2, 6, "const", None, 1),
+    (12, 0.2, 2, "element", None, 1),
+    (11, 0.2, 4, "element", None, 1),
+    (8, 0.2, 6, "element", None, 1),
+    (12, 0.2, 3, "const", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0), 3),
+    (10, 0.2, 2, "const", (0.6, -0.4, 0.2, -1.0, 1.0, 0.1), 2),
+]
+
+
+def _ids(c):
+    return f"m{c[0]}-N{c[2]}-{c[3]}-{'conv' if c[4] else 'diff'}-F{c[5]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_edge_flux_and_rhs_parity_random(case, prec):
+    import torch
+    from paper_1912_06221_amd import ardg
+    m, jit, N, D_mode, vel, nf = case
+    print(f"case {_ids(case)} {prec}", flush=True)
+    mesh, D = make_case(m, jit, N, D_mode, velocity=vel, nfields=nf, seed=10 * m + N)
+    if D_mode == "const":
+        D = [0.3 + f for f in range(nf)]
+    ops, lm = library_mesh(mesh, N, D_mode, D, vel, nf)
+    pr = oracle_problem(mesh, N, D_mode, D, vel, nf)
+    u = W.random_nodal((nf, mesh.K, ops.Np), seed=m + N)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    p = ardg.FP64 if prec == "fp64" else ardg.FP32
+    tol = TOL64 if prec == "fp64" else TOL32
+    ud = to_dev(u, dt)
+    flux = torch.empty((nf, lm.E, ops.Nfp), dtype=dt, device=ud.device)
+    lm.edge_flux_eval(ud, flux, precision=p, nfields=nf)
+    Fo = _flux_oracle(pr, u, nf)
+    Fg = to_np(flux)
+    assert np.abs(Fg - Fo).max() <= tol * np.abs(Fo).max()
+    rhs = torch.empty_like(ud)
+    lm.rhs_eval(ud, rhs, precision=p, nfields=nf)
+    ro = pr.rhs(u)
+    rg = to_np(rhs)
+    err = np.abs(rg - ro).max() / np.abs(ro).max()
+    print(f"  rhs rel err {err:.2e}", flush=True)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_rhs_parity_smooth_data(N):
+    import torch
+    from paper_1912_06221_amd import ardg
+    print(f"smooth N={N}", flush=True)
+    mesh = W.split_square_mesh(16, 0.2, seed=N)
+    D = W.circle_contrast_D(mesh)
+    ops, lm = library_mesh(mesh, N, "element", D, None, 1)
+    pr = oracle_problem(mesh, N, "element", D, None, 1)
+    xy = pr.nodal_xy()
+    u = W.fourier_modes(xy[..., 0], xy[..., 1], seed=3)
+    ur = W.random_nodal(u.shape, seed=4) * np.abs(u).max()
+    scale = np.abs(pr.rhs(ur)).max()
+    ud = to_dev(u)
+    rhs = torch.empty_like(ud)
+    lm.rhs_eval(ud, rhs, precision=ardg.FP64)
+    assert np.abs(to_np(rhs) - pr.rhs(u)).max() <= TOL64 * scale
+
+
+def test_empty_and_tiny_meshes():
+    """One element (only boundary faces) and two elements (one interior edge)."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    print("tiny meshes", flush=True)
+    for vxy, etov in ((np.array([[0, 0], [1, 0], [0, 1.0]]), np.array([[0, 1, 2]], dtype=np.int32)),
+                      (np.array([[0, 0], [1, 0], [1, 1], [0, 1.0]]),
+                       np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32))):
+        for N in (1, 3):
+            ops = ardg.Ops(N)
+            lm = ardg.Mesh(ops, vxy, etov, device=0)
+            lm.set_diffusion_const([0.7])
+            from oracle.rhs import Problem
+            pr = Problem(vxy, etov, N, 0.7)
+            u = W.random_nodal((1, len(etov), ops.Np), seed=N)
+            ud = to_dev(u)
+            rhs = torch.empty_like(ud)
+            lm.rhs_eval(ud, rhs)
+            ro = pr.rhs(u)
+            assert np.abs(to_np(rhs) - ro).max() <= TOL64 * np.abs(ro).max()
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "lserk"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_time_stepping_heat_8x8(scheme, prec):
+    """The plain heat problem: 8x8x2 unjittered, N=2, D=1,
+    u0 = sin(pi x) sin(pi y), 100 steps; state parity with the oracle and the
+    error against the exact solution."""
+    import torch
+    from oracle.rhs import lserk_step, mass_norm, rk4_step
+    from paper_1912_06221_amd import ardg
+    print(f"heat 8x8 {scheme} {prec}", flush=True)
+    mesh = W.split_square_mesh(8, 0.0)
+    N = 2
+    ops, lm = library_mesh(mesh, N, "const", 1.0, None, 1)
+    pr = oracle_problem(mesh, N, "const", 1.0, None, 1)
+    xy = pr.nodal_xy()
+    u0 = W.manufactured(xy[..., 0], xy[..., 1])
+    dt, nsteps = 2e-4, 100
+    uo = u0.copy()
+    step = rk4_step if scheme == "rk4" else lserk_step
+    for _ in range(nsteps):
+        uo = step(pr.rhs, uo, dt)
+    sch = ardg.RK4 if scheme == "rk4" else ardg.LSERK54
+    p = ardg.FP64 if prec == "fp64" else ardg.FP32
+    ud = to_dev(u0[None])
+    work = ardg.alloc_workspace(lm.workspace_bytes(sch, p, 1), ud.device)
+    lm.rk_step(ud, work, dt, nsteps, scheme=sch, precision=p)
+    ug = to_np(ud)[0]
+    rel = mass_norm(pr, ug - uo) / mass_norm(pr, uo)
+    print(f"  state rel err {rel:.2e}", flush=True)
+    assert rel <= (TOL64 if prec == "fp64" else TOL32)
+    # graph replay: a second call continues from the new state
+    lm.rk_step(ud, work, dt, nsteps, scheme=sch, precision=p)
+    for _ in range(nsteps):
+        uo = step(pr.rhs, uo, dt)
+    rel2 = mass_norm(pr, to_np(ud)[0] - uo) / mass_norm(pr, uo)
+    assert rel2 <= (TOL64 if prec == "fp64" else TOL32)
+    from oracle.rhs import error_norms
+    l2, _ = error_norms(pr, to_np(ud)[0], lambda x, y: W.manufactured(x, y, 2 * nsteps * dt))
+    assert l2 < 2e-3
+
+
+def test_determinism():
+    import torch
+    from paper_1912_06221_amd import ardg
+    print("determinism", flush=True)
+    mesh = W.split_square_mesh(20, 0.2, seed=1)
+    D = W.circle_contrast_D(mesh)
+    ops, lm = library_mesh(mesh, 4, "element", D, None, 1)
+    u = to_dev(W.random_nodal((1, mesh.K, ops.Np), seed=5))
+    a = torch.empty_like(u)
+    b = torch.empty_like(u)
+    lm.rhs_eval(u, a)
+    lm.rhs_eval(u, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_check_detects_nonfinite():
+    import torch
+    from paper_1912_06221_amd import ardg
+    print("nonfinite check", flush=True)
+    mesh = W.split_square_mesh(4, 0.0)
+    ops, lm = library_mesh(mesh, 2, "const", 1.0, None, 1)
+    u = to_dev(W.random_nodal((1, mesh.K, ops.Np), seed=1))
+    lm.check(u)
+    u[0, 3, 2] = float("nan")
+    with pytest.raises(ardg.ArdgError) as ei:
+        lm.check(u)
+    assert ei.value.status == -9
