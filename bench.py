@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--workload", default="contrast_256x256_N4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--power-iters", type=int, default=30)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one device copy of 512 MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -157,11 +160,20 @@ def main():
     K, Np, Nfp = mesh.K, ops.Np, ops.Nfp
     dof = nf * K * Np
 
+    if args.calib_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {a.numel() * 8} bytes done")
+        del a, b
+
     # time step from a power-iteration estimate of the spectral radius (setup)
     v = torch.from_numpy(W.random_nodal((nf, K, Np), seed=7)).to(dev)
     w = torch.empty_like(v)
     rho = 0.0
-    for _ in range(30):
+    for _ in range(args.power_iters):
         lm.rhs_eval(v, w, nfields=nf)
         nrm = float(torch.linalg.vector_norm(w))
         rho = nrm / float(torch.linalg.vector_norm(v))

@@ -64,6 +64,8 @@ void pack_into(const RefOps& o, std::vector<double>& out) {
   put(L.u1s, o.U1S);
   put(L.u2r, o.U2R);
   put(L.u2s, o.U2S);
+  put(L.udr, add(o.U1R, o.U2R, -1.0));
+  put(L.uds, add(o.U1S, o.U2S, -1.0));
   put(L.ubr, o.UBR);
   put(L.ubs, o.UBS);
   put(L.dr, o.Dr);

@@ -12,7 +12,7 @@ constexpr int kMaxFields = 16;
 // Offsets of the packed constant operators (same layout in FP64 and FP32).
 struct OpLayout {
   int Np, Nfp;
-  int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, ubr, ubs, dr, ds, lift, tau, nr, ns, total;
+  int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, lift, tau, nr, ns, total;
   __host__ __device__ constexpr OpLayout(int N)
       : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
         n2b(0),
@@ -24,7 +24,9 @@ struct OpLayout {
         u1s(u1r + Nfp * 2 * Np),
         u2r(u1s + Nfp * 2 * Np),
         u2s(u2r + Nfp * 2 * Np),
-        ubr(u2s + Nfp * 2 * Np),
+        udr(u2s + Nfp * 2 * Np),
+        uds(udr + Nfp * 2 * Np),
+        ubr(uds + Nfp * 2 * Np),
         ubs(ubr + Nfp * Np),
         dr(ubs + Nfp * Np),
         ds(dr + Np * Np),

@@ -18,9 +18,10 @@
 //      element-wise D, Algorithm 1's four constant blocks weighted by D1, D2;
 //   4. optionally subtract the upwind convective flux;
 //   5. write Nfp values per edge (no atomics: each edge owns its slot).
-// element_kernel (one thread per element): strong-form volume term with the
-// element's affine factors, (J_f/J) LIFT_f of the face jumps, optional
-// convective volume term, and a fused Runge-Kutta update in FP64.
+// element_kernel (one thread per element, the block's elements staged through
+// LDS): strong-form volume term with the element's affine factors,
+// (J_f/J) LIFT_f of the face jumps, optional convective volume term, and a
+// fused Runge-Kutta update in FP64 over the block's degrees of freedom.
 //
 // Constant operators are read through the constant address space with
 // compile-time offsets, so every matrix entry is a wave-uniform scalar load
@@ -140,14 +141,23 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
     subtriangle_coeffs<N, T>(uf + (int64_t)k2 * Np, fb, m.mu2[e], op + L.n2b, c + Np, tr2);
     const T gR = (T)g.x, gS = (T)g.y;
     if (ALG1) {
-      const T D1 = (T)m.Delem[k1], D2 = (T)m.Delem[k2];
+      const double D1d = m.Delem[k1], D2d = m.Delem[k2];
+      const T D1 = (T)D1d, D2 = (T)D2d;
+      if (D1d == D2d) {
+        // equal coefficients: Algorithm 1 reduces exactly to D (U1 - U2) c
 #pragma unroll
-      for (int j = 0; j < Nfp; ++j) {
-        const T a = gR * rowdot<Nfp, 2 * Np, T>(op + L.u1r, j, c) +
-                    gS * rowdot<Nfp, 2 * Np, T>(op + L.u1s, j, c);
-        const T b = gR * rowdot<Nfp, 2 * Np, T>(op + L.u2r, j, c) +
-                    gS * rowdot<Nfp, 2 * Np, T>(op + L.u2s, j, c);
-        F[j] = D1 * a - D2 * b;
+        for (int j = 0; j < Nfp; ++j)
+          F[j] = D1 * (gR * rowdot<Nfp, 2 * Np, T>(op + L.udr, j, c) +
+                       gS * rowdot<Nfp, 2 * Np, T>(op + L.uds, j, c));
+      } else {
+#pragma unroll
+        for (int j = 0; j < Nfp; ++j) {
+          const T a = gR * rowdot<Nfp, 2 * Np, T>(op + L.u1r, j, c) +
+                      gS * rowdot<Nfp, 2 * Np, T>(op + L.u1s, j, c);
+          const T b = gR * rowdot<Nfp, 2 * Np, T>(op + L.u2r, j, c) +
+                      gS * rowdot<Nfp, 2 * Np, T>(op + L.u2s, j, c);
+          F[j] = D1 * a - D2 * b;
+        }
       }
     } else {
       const T D = (T)m.Dfield[field];
@@ -191,22 +201,16 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
   for (int j = 0; j < Nfp; ++j) out[j] = F[j];
 }
 
+constexpr int kElemBlock = 256;
+
+// du/dt of one element from its nodal values u (registers).
 template <int N, typename T, bool CONV>
-__global__ __launch_bounds__(256) void element_kernel(DevMesh m, const T* __restrict__ vin,
-                                                      const T* __restrict__ flux, Epilogue epi) {
+__device__ inline void element_rhs(const DevMesh& m, int64_t k, int field, const T* u,
+                                   const T* __restrict__ flux, T* rhs) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m.K) return;
-  const int field = blockIdx.y;
   const int64_t E = m.E_int + m.E_bdy;
   const cptr<T> op = opbase<T>(m);
-  const int64_t base = ((int64_t)field * m.K + k) * Np;
-
-  T u[Np];
-#pragma unroll
-  for (int n = 0; n < Np; ++n) u[n] = vin[base + n];
-
   // affine factors of this element (eqs. mapping_tri_diff, triangle_jacobian_a/b)
   const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
   const double xr = 0.5 * (p2.x - p1.x), yr = 0.5 * (p2.y - p1.y);
@@ -223,7 +227,6 @@ __global__ __launch_bounds__(256) void element_kernel(DevMesh m, const T* __rest
     qy[i] = ry * ur + sy * us;
   }
   const T D = m.alg1 ? (T)m.Delem[k] : (T)m.Dfield[field];
-  T rhs[Np];
   {
     T wr[Np], ws[Np];
 #pragma unroll
@@ -299,11 +302,44 @@ __global__ __launch_bounds__(256) void element_kernel(DevMesh m, const T* __rest
       rhs[i] -= rx * dxr + sx * dxs + ry * dyr + sy * dys;
     }
   }
+}
+
+// One block = kElemBlock consecutive elements.  Their nodal values form one
+// contiguous chunk of the [F][K][Np] array: it is staged through LDS with
+// coalesced loads, each thread computes one element from registers, the
+// element results go back to LDS, and the Runge-Kutta update runs over the
+// chunk's degrees of freedom with coalesced global traffic.
+template <int N, typename T, bool CONV>
+__global__ __launch_bounds__(kElemBlock) void element_kernel(DevMesh m, const T* __restrict__ vin,
+                                                             const T* __restrict__ flux, Epilogue epi) {
+  constexpr int Np = (N + 1) * (N + 2) / 2;
+  __shared__ T sh[kElemBlock * Np];
+  const int64_t k0 = (int64_t)blockIdx.x * kElemBlock;
+  const int field = blockIdx.y;
+  const int nel = (int)((m.K - k0) < kElemBlock ? (m.K - k0) : kElemBlock);
+  const int ndof = nel * Np;
+  const int64_t base = ((int64_t)field * m.K + k0) * Np;
+  const int t = threadIdx.x;
+
+  for (int i = t; i < ndof; i += kElemBlock) sh[i] = vin[base + i];
+  __syncthreads();
+  T u[Np];
+  if (t < nel) {
+#pragma unroll
+    for (int n = 0; n < Np; ++n) u[n] = sh[t * Np + n];
+  }
+  __syncthreads();
+  if (t < nel) {
+    T rhs[Np];
+    element_rhs<N, T, CONV>(m, k0 + t, field, u, flux, rhs);
+#pragma unroll
+    for (int n = 0; n < Np; ++n) sh[t * Np + n] = rhs[n];
+  }
+  __syncthreads();
 
   if (epi.kind == EPI_RHS) {
     T* o = (T*)epi.rhs_out + base;
-#pragma unroll
-    for (int i = 0; i < Np; ++i) o[i] = rhs[i];
+    for (int i = t; i < ndof; i += kElemBlock) o[i] = sh[i];
     return;
   }
   double* U = epi.u + base;
@@ -314,24 +350,21 @@ __global__ __launch_bounds__(256) void element_kernel(DevMesh m, const T* __rest
     const int s = epi.stage;
     if (s < 3) {
       const double c = (s < 2) ? 0.5 * dt : dt;
-#pragma unroll
-      for (int i = 0; i < Np; ++i) {
-        const double r = (double)rhs[i];
+      for (int i = t; i < ndof; i += kElemBlock) {
+        const double r = (double)sh[i];
         A[i] = (s == 0) ? r : A[i] + 2.0 * r;
         vn[i] = (T)(U[i] + c * r);
       }
     } else {
-#pragma unroll
-      for (int i = 0; i < Np; ++i) {
-        const double un = U[i] + dt / 6.0 * (A[i] + (double)rhs[i]);
+      for (int i = t; i < ndof; i += kElemBlock) {
+        const double un = U[i] + dt / 6.0 * (A[i] + (double)sh[i]);
         U[i] = un;
         if (vn) vn[i] = (T)un;
       }
     }
   } else {
-#pragma unroll
-    for (int i = 0; i < Np; ++i) {
-      const double r = dt * (double)rhs[i];
+    for (int i = t; i < ndof; i += kElemBlock) {
+      const double r = dt * (double)sh[i];
       const double res = (epi.stage == 0) ? r : epi.a * A[i] + r;
       A[i] = res;
       const double un = U[i] + epi.b * res;
@@ -373,13 +406,13 @@ hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flu
 template <int N, typename T>
 hipError_t elem_launch_t(const DevMesh& m, int nfields, const void* vin, const void* flux,
                          const Epilogue& epi, hipStream_t st) {
-  dim3 grid((unsigned)((m.K + 255) / 256), (unsigned)nfields);
+  dim3 grid((unsigned)((m.K + kElemBlock - 1) / kElemBlock), (unsigned)nfields);
   if (m.conv)
-    hipLaunchKernelGGL((element_kernel<N, T, true>), grid, dim3(256), 0, st, m, (const T*)vin,
-                       (const T*)flux, epi);
+    hipLaunchKernelGGL((element_kernel<N, T, true>), grid, dim3(kElemBlock), 0, st, m,
+                       (const T*)vin, (const T*)flux, epi);
   else
-    hipLaunchKernelGGL((element_kernel<N, T, false>), grid, dim3(256), 0, st, m, (const T*)vin,
-                       (const T*)flux, epi);
+    hipLaunchKernelGGL((element_kernel<N, T, false>), grid, dim3(kElemBlock), 0, st, m,
+                       (const T*)vin, (const T*)flux, epi);
   return hipGetLastError();
 }
 

@@ -1,0 +1,105 @@
+"""Parity at the full workload sizes, in the benchmark's launch configuration,
+on sampled outputs that the oracle computes one by one.
+
+The oracle evaluates the RHS of sampled elements (each with its three
+literal per-edge reconstructions) and one classic RK4 step on sampled
+elements through the four neighbour layers each stage needs.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-4
+
+
+def _setup(name):
+    from oracle.rhs import Problem
+    from paper_1912_06221_amd import ardg
+    spec = W.WORKLOADS[name]
+    cfg = spec["config"]
+    mesh = W.split_square_mesh(spec["m"], spec["jitter"], seed=W.seed_for(cfg, "mesh"))
+    N, nf = spec["N"], spec["fields"]
+    vel = (0.0, 0.0, 0.0, -1.0, 1.0, 0.0) if spec.get("velocity") == "rotation" else None
+    if spec["D"] == "circle":
+        D, mode = W.circle_contrast_D(mesh), "element"
+    elif spec["D"] == "loguniform":
+        D, mode = W.loguniform_per_element(mesh.K, spec["Dlo"], spec["Dhi"], W.seed_for(cfg, "D")), "element"
+    else:
+        D, mode = np.array(spec["Dfield"], dtype=float), "const"
+    ops = ardg.Ops(N)
+    lm = ardg.Mesh(ops, mesh.vxy, mesh.etov, device=0)
+    if mode == "element":
+        lm.set_diffusion_element(D)
+    else:
+        lm.set_diffusion_const(D)
+    if vel is not None:
+        lm.set_velocity(vel)
+    pr = Problem(mesh.vxy, mesh.etov, N, D, D_mode=mode, velocity=vel, nfields=nf,
+                 build_edges=False)
+    xy = pr.nodal_xy()
+    u0 = np.stack([W.fourier_modes(xy[..., 0], xy[..., 1], seed=W.seed_for(cfg, "IC") + 10 * f)
+                   for f in range(nf)])
+    return spec, mesh, ops, lm, pr, u0
+
+
+def _sample(K, n, seed):
+    rng = np.random.default_rng(seed)
+    s = set(rng.choice(K, size=n, replace=False).tolist())
+    s.update([0, K - 1])          # first and last element (boundary, ragged tail)
+    return sorted(s)
+
+
+@pytest.mark.parametrize("name", ["contrast_256x256_N4", "convdiff_708x708_N3_4f",
+                                  "loguniformD_512x512_N6"])
+def test_fullsize_rhs_sampled(name):
+    import torch
+    from paper_1912_06221_amd import ardg
+    print(f"full-size rhs {name}", flush=True)
+    spec, mesh, ops, lm, pr, u0 = _setup(name)
+    nf = spec["fields"]
+    els = _sample(mesh.K, 24, seed=1)
+    ur = W.random_nodal(u0.shape, seed=9)
+    for data, label in ((u0, "smooth"), (ur, "random")):
+        ud = to_dev(data)
+        for prec, dt, tol in ((ardg.FP64, torch.float64, TOL64), (ardg.FP32, torch.float32, TOL32)):
+            x = ud.to(dt)
+            out = torch.empty_like(x)
+            lm.rhs_eval(x, out, precision=prec, nfields=nf)
+            got = to_np(out)
+            for f in range(nf):
+                ref = pr.rhs_elements(data[f], els, field=f)
+                scale = np.abs(pr.rhs_elements(ur[f] * np.abs(data[f]).max(), els, field=f)).max()
+                err = np.abs(got[f, els] - ref).max() / scale
+                print(f"  {label} prec={prec} field={f} err/scale={err:.2e}", flush=True)
+                assert err <= tol
+
+
+def test_fullsize_rk4_step_sampled():
+    """One RK4 step of the benchmark workload through ardg_rk_step (the
+    graph-captured path the benchmark times), FP64 and mixed FP32."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    print("full-size rk4 step contrast_256x256_N4", flush=True)
+    spec, mesh, ops, lm, pr, u0 = _setup("contrast_256x256_N4")
+    els = _sample(mesh.K, 6, seed=2)
+    # random data and a step of the order of the inverse spectral radius, so
+    # that the increment is of the size of the state (no cancellation)
+    u0 = W.random_nodal(u0.shape, seed=11)
+    dt = 2e-11
+    ref = pr.rk4_step_elements(u0[0], dt, els)
+    for prec, tol in ((ardg.FP64, TOL64), (ardg.FP32, TOL32)):
+        ud = to_dev(u0)
+        work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, prec, 1), ud.device)
+        lm.rk_step(ud, work, dt, 1, scheme=ardg.RK4, precision=prec)
+        got = to_np(ud)[0, els]
+        # compare the increment u1 - u0 (the state itself is O(1))
+        inc_ref = ref - u0[0, els]
+        inc_got = got - u0[0, els]
+        err = np.abs(inc_got - inc_ref).max() / np.abs(inc_ref).max()
+        print(f"  prec={prec} increment rel err {err:.2e}", flush=True)
+        assert err <= tol
