@@ -93,6 +93,70 @@ def edge_flops(K, Np, Nfp, N, E_int, E_bdy, alg1, nfields=1):
     return nfields * (E_int * per_edge + E_bdy * per_bdy)
 
 
+def bench_batch(args, dev):
+    """512 independent heat problems of 200-20000 triangles, N in {2,3,4},
+    constant D per problem: one graph launch per step for all of them (FP64 and
+    FP32 operators with FP64 state) against the plain per-mesh path (one
+    ardg_rk_step graph per mesh)."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    specs = W.batch_problems()
+    meshes, states, dts, dof = [], [], [], 0
+    for sp in specs:
+        mesh = W.split_square_mesh(sp["m"], 0.2, seed=sp["mesh_seed"])
+        ops = ardg.Ops(sp["N"])
+        lm = ardg.Mesh(ops, mesh.vxy, mesh.etov, device=0)
+        lm.set_diffusion_const([sp["D"]])
+        rs = ops.export(ardg.OPS_NODES).reshape(-1, 2)
+        x, y = nodal_xy(mesh, rs)
+        states.append(W.fourier_modes(x, y, seed=sp["ic_seed"])[None])
+        h = 1.0 / sp["m"]
+        dts.append(0.02 * h * h / (sp["D"] * (sp["N"] + 1) ** 4))
+        meshes.append(lm)
+        dof += mesh.K * ops.Np
+    out = {"workload": "512 heat problems, K_i 200-20000 (log-uniform), N in {2,3,4}, D per problem",
+           "problems": len(specs), "DOF": dof}
+    b = ardg.Batch(meshes)
+    for name, prec in (("fp64", ardg.FP64), ("fp32", ardg.FP32)):
+        us = [torch.from_numpy(u.copy()).to(dev) for u in states]
+        work = ardg.alloc_workspace(b.workspace_bytes(ardg.RK4, prec), dev)
+        for _ in range(max(1, args.warmup)):
+            b.step(us, work, dts, 1, scheme=ardg.RK4, precision=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = max(5, args.steps // 2)
+        e0.record()
+        for _ in range(steps):
+            b.step(us, work, dts, 1, scheme=ardg.RK4, precision=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"batched_{name}"] = {"ms_per_step": ms, "value": dof * 4 / (ms * 1e-3)}
+        tiles = {}
+        for N in (2, 3, 4):
+            et, lt, gm = b.tiles(prec, N)
+            tiles[f"N{N}"] = {"edge_tile": et, "elem_tile": lt, "grid_per_cu": gm}
+        out[f"batched_{name}"]["tiles"] = tiles
+    # plain path: one graph launch per mesh per step, FP64
+    us = [torch.from_numpy(u.copy()).to(dev) for u in states]
+    works = [ardg.alloc_workspace(m.workspace_bytes(ardg.RK4, ardg.FP64, 1), dev) for m in meshes]
+    for m, u, w, dt in zip(meshes, us, works, dts):
+        m.rk_step(u, w, dt, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = 3
+    e0.record()
+    for _ in range(steps):
+        for m, u, w, dt in zip(meshes, us, works, dts):
+            m.rk_step(u, w, dt, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out["per_mesh_fp64"] = {"ms_per_step": ms, "value": dof * 4 / (ms * 1e-3)}
+    out["speedup_batched_fp32_vs_per_mesh_fp64"] = ms / out["batched_fp32"]["ms_per_step"]
+    return out
+
+
 def cpu_baseline(spec, mesh, D, u, budget_s=12.0):
     from oracle.rhs import Problem
     t0 = time.time()
@@ -122,6 +186,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--power-iters", type=int, default=30)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of 512 MiB first (counter calibration)")
     args = ap.parse_args()
@@ -251,6 +316,12 @@ def main():
             "edge_GBps": b_edge32 / (r32["t_edge"] * 1e-3) / 1e9,
             "element_GBps": b_elem32 / (r32["t_elem"] * 1e-3) / 1e9,
         }
+    if not args.no_batch:
+        log("bench: batched workload (512 problems)")
+        line["batch"] = bench_batch(args, dev)
+        bb = line["batch"]
+        log(f"bench: batch fp64 {bb['batched_fp64']['ms_per_step']:.3f} ms, fp32 "
+            f"{bb['batched_fp32']['ms_per_step']:.3f} ms, per-mesh fp64 {bb['per_mesh_fp64']['ms_per_step']:.3f} ms")
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(spec, mesh, D, u0[0])

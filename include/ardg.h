@@ -196,6 +196,36 @@ ardg_status ardg_stage_timing(ardg_mesh mesh, int32_t scheme, int32_t precision,
                               double* u_dev, void* work_dev, double dt, int32_t reps,
                               void* hip_stream, float* out_ms);
 
+/* Batching: many independent meshes of uneven size and order advanced
+ * together.  Each mesh must live on the same device, carry one field with a
+ * constant diffusion coefficient (ardg_mesh_set_diffusion with ARDG_D_CONST)
+ * and no velocity; the meshes are referenced, not copied, and must outlive the
+ * batch.  Work is split into tiles (edges or elements of one mesh); per order
+ * N, persistent kernels walk the tiles of all meshes of that order, and a whole
+ * ardg_batch_step is one HIP graph launch.  Tile sizes and persistent grid
+ * sizes are chosen per (device, order, precision) by timing candidates on
+ * first use; tune_cache names a text file where the choices are kept across
+ * processes (NULL: no file).  Errors: E_INVALID_ARG, E_UNSUPPORTED (a mesh with
+ * element-wise D or a velocity), E_HIP, E_OOM. */
+ardg_status ardg_batch_create(const ardg_mesh* meshes, int32_t n, const char* tune_cache,
+                              ardg_batch* out);
+/* Device workspace for ardg_batch_step (per mesh: RK accumulator, stage vector,
+ * edge fluxes), 256-byte aligned. */
+ardg_status ardg_batch_workspace_bytes(ardg_batch batch, int32_t scheme, int32_t precision,
+                                       int64_t* bytes);
+/* Advance every mesh i by nsteps steps of size dt[i] (host array): u_devs[i]
+ * is mesh i's FP64 state [K_i][Np_i] on the device (host array of n device
+ * pointers).  Same schemes and precisions as ardg_rk_step; results equal the
+ * per-mesh ardg_rk_step up to rounding. */
+ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
+                            double* const* u_devs, void* work_dev, const double* dt,
+                            int32_t nsteps, void* hip_stream);
+/* The tile shapes in use for order N and a precision (tuning them first if
+ * needed): edges per edge tile, elements per element tile, persistent blocks. */
+ardg_status ardg_batch_tiles(ardg_batch batch, int32_t precision, int32_t N, int32_t* edge_tile,
+                             int32_t* elem_tile, int32_t* grid);
+void ardg_batch_destroy(ardg_batch batch);
+
 /* Synchronise the stream and scan the FP64 state for non-finite values
  * (E_NONFINITE if any).  u_dev: double [F][K][Np]. */
 ardg_status ardg_check(ardg_mesh mesh, int32_t nfields, const double* u_dev, void* hip_stream);

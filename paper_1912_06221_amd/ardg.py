@@ -13,7 +13,9 @@ from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libardg.so")
+# ARDG_LIB may point at another build of the same library (A/B timing).
+LIB_PATH = os.environ.get("ARDG_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                      "libardg.so")
 
 OK = 0
 FP64, FP32, BF16X3 = 0, 1, 2
@@ -61,6 +63,13 @@ SIGNATURES = {
     "ardg_stage_timing": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
                                     c_int32, c_void_p, POINTER(ctypes.c_float)]),
     "ardg_check": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "ardg_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_char_p, POINTER(c_void_p)]),
+    "ardg_batch_workspace_bytes": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int64)]),
+    "ardg_batch_step": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_void_p), c_void_p,
+                                  POINTER(c_double), c_int32, c_void_p]),
+    "ardg_batch_tiles": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                   POINTER(c_int32)]),
+    "ardg_batch_destroy": (None, [c_void_p]),
     "ardg_status_string": (c_char_p, [c_int32]),
     "ardg_last_error": (c_char_p, []),
 }
@@ -212,6 +221,40 @@ class Mesh:
 
     def check(self, u, nfields: int = 1, stream=None):
         _check(lib().ardg_check(self.handle, nfields, _ptr(u), _stream(stream)))
+
+
+class Batch:
+    """Many independent meshes advanced together (ardg_batch_*)."""
+
+    def __init__(self, meshes, tune_cache: str | None = None):
+        self.meshes = list(meshes)          # keeps the handles alive
+        arr = (c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = c_void_p()
+        _check(lib().ardg_batch_create(arr, len(self.meshes),
+                                       tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ardg_batch_destroy(self.handle)
+            self.handle = None
+
+    def workspace_bytes(self, scheme: int = RK4, precision: int = FP64) -> int:
+        n = c_int64()
+        _check(lib().ardg_batch_workspace_bytes(self.handle, scheme, precision, ctypes.byref(n)))
+        return n.value
+
+    def tiles(self, precision: int, N: int):
+        a, b, c = c_int32(), c_int32(), c_int32()
+        _check(lib().ardg_batch_tiles(self.handle, precision, N, ctypes.byref(a), ctypes.byref(b),
+                                      ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def step(self, us, work, dts, nsteps: int, scheme: int = RK4, precision: int = FP64, stream=None):
+        ptrs = (c_void_p * len(us))(*[u.data_ptr() for u in us])
+        dt = np.ascontiguousarray(dts, dtype=np.float64)
+        _check(lib().ardg_batch_step(self.handle, scheme, precision, ptrs, _ptr(work), _dptr(dt),
+                                     nsteps, _stream(stream)))
 
 
 def alloc_workspace(nbytes: int, device):

@@ -46,10 +46,11 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         cmds.append(host + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    kobj = os.path.join(BUILD, "kernels.o")
-    cmds.append([hipcc, f"--offload-arch={ARCH}"] + common + HIP_DEVICE_FLAGS +
-                ["-c", os.path.join(CSRC, "kernels.hip"), "-o", kobj])
-    objs.append(kobj)
+    for src in ("kernels.hip", "kernels_mfma.hip"):
+        kobj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        cmds.append([hipcc, f"--offload-arch={ARCH}"] + common + HIP_DEVICE_FLAGS +
+                    ["-c", os.path.join(CSRC, src), "-o", kobj])
+        objs.append(kobj)
     _run(cmds)
     tmp = LIB + ".tmp"
     _run([[hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs +

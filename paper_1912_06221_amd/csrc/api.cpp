@@ -4,7 +4,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <exception>
 #include <map>
 #include <memory>
@@ -70,6 +74,7 @@ void pack_into(const RefOps& o, std::vector<double>& out) {
   put(L.ubs, o.UBS);
   put(L.dr, o.Dr);
   put(L.ds, o.Ds);
+  put(L.drsh, hcat(o.Dr, o.Ds));
   put(L.lift, o.LIFT);
   for (int j = 0; j < o.Nfp; ++j) out[L.tau + j] = 0.5 * (o.lgl[j] + 1.0);
   for (int n = 0; n < o.Np; ++n) {
@@ -236,6 +241,12 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
     int st = build_host_mesh(vxy, Nv, etov, K, m->hm, err);
     if (st != ARDG_OK) return fail(st, err);
     m->dm.N = m->N;
+    {
+      // element kernel implementation: matrix cores (default) or thread per
+      // element with scalar-broadcast operators (ARDG_ELEMENT_KERNEL=valu)
+      const char* ek = std::getenv("ARDG_ELEMENT_KERNEL");
+      m->dm.elem_mfma = (ek && std::string(ek) == "valu") ? 0 : 1;
+    }
     m->dm.K = m->hm.K;
     m->dm.E_int = m->hm.E_int;
     m->dm.E_bdy = m->hm.E_bdy;
@@ -690,6 +701,438 @@ ardg_status ardg_check(ardg_mesh mesh, int32_t nfields, const double* u_dev, voi
   (void)hipFree(cnt);
   if (e != hipSuccess) return hip_fail(e, "check");
   if (host) return fail(ARDG_E_NONFINITE, "check: " + std::to_string(host) + " non-finite values");
+  return ARDG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batching
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Tiles {
+  int edge_tile = 256, elem_tile = 256, grid_mult = 4;
+};
+
+struct GroupItems {
+  int tile_e = 0, tile_l = 0;
+  std::vector<int2> eitems, litems;
+  int2* d_eitems = nullptr;
+  int2* d_litems = nullptr;
+};
+
+struct BatchGroup {
+  int N = 0;
+  std::vector<int> probs;           // problem indices, largest first
+  GroupItems items[2];              // per precision (0: FP64, 1: FP32)
+  Tiles tiles[2];
+  bool tuned[2] = {false, false};
+};
+
+}  // namespace
+
+struct ardg_batch_s {
+  int device = -1;
+  int ncu = 0;
+  std::string arch;
+  std::vector<ardg_mesh> meshes;
+  std::string cache;
+  std::vector<BatchGroup> groups;
+  std::vector<BatchProb> hprobs;
+  BatchProb* dprobs = nullptr;
+  uint64_t version = 0;
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  ~ardg_batch_s() {
+    DeviceGuard g(device);
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto& gr : groups)
+      for (auto& it : gr.items) {
+        if (it.d_eitems) (void)hipFree(it.d_eitems);
+        if (it.d_litems) (void)hipFree(it.d_litems);
+      }
+    if (dprobs) (void)hipFree(dprobs);
+  }
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    ++version;
+  }
+};
+
+namespace {
+
+void batch_layout(ardg_batch b, int precision, std::vector<size_t>* offs, size_t* total) {
+  const size_t ts = precision == ARDG_FP64 ? 8 : 4;
+  size_t off = 0;
+  if (offs) offs->clear();
+  for (ardg_mesh m : b->meshes) {
+    const size_t n = (size_t)m->hm.K * m->ro.Np;
+    const size_t nf = (size_t)(m->hm.E_int + m->hm.E_bdy) * m->ro.Nfp;
+    const size_t a = align256(n * 8), v = align256(n * ts), f = align256(nf * ts);
+    if (offs) {
+      offs->push_back(off);
+      offs->push_back(off + a);
+      offs->push_back(off + a + v);
+    }
+    off += a + v + f;
+  }
+  if (total) *total = off;
+}
+
+ardg_status build_items(ardg_batch b, BatchGroup& g, int pi, int tile_e, int tile_l) {
+  GroupItems& it = g.items[pi];
+  if (it.tile_e == tile_e && it.tile_l == tile_l && it.d_eitems) return ARDG_OK;
+  it.eitems.clear();
+  it.litems.clear();
+  for (int p : g.probs) {
+    ardg_mesh m = b->meshes[p];
+    const int64_t E = m->hm.E_int + m->hm.E_bdy, K = m->hm.K;
+    for (int64_t t = 0; t * tile_e < E; ++t) it.eitems.push_back(make_int2(p, (int)t));
+    for (int64_t t = 0; t * tile_l < K; ++t) it.litems.push_back(make_int2(p, (int)t));
+  }
+  if (it.d_eitems) (void)hipFree(it.d_eitems);
+  if (it.d_litems) (void)hipFree(it.d_litems);
+  it.d_eitems = it.d_litems = nullptr;
+  ardg_status s = upload(it.eitems.data(), it.eitems.size(), &it.d_eitems);
+  if (s != ARDG_OK) return s;
+  s = upload(it.litems.data(), it.litems.size(), &it.d_litems);
+  if (s != ARDG_OK) return s;
+  it.tile_e = tile_e;
+  it.tile_l = tile_l;
+  return ARDG_OK;
+}
+
+int grid_for(ardg_batch b, int nitems, int mult) {
+  const int g = std::max(1, b->ncu * mult);
+  return std::max(1, std::min(nitems, g));
+}
+
+// One Runge-Kutta stage of one group.
+hipError_t group_stage(ardg_batch b, BatchGroup& g, int pi, bool f64, int scheme, int s,
+                       hipStream_t st) {
+  GroupItems& it = g.items[pi];
+  const Tiles& t = g.tiles[pi];
+  const int in_u = f64 && (scheme == ARDG_LSERK54 || s == 0);
+  hipError_t e = launch_batch_edge(g.N, f64, it.tile_e, grid_for(b, (int)it.eitems.size(), t.grid_mult),
+                                   b->dprobs, it.d_eitems, (int)it.eitems.size(), in_u, st);
+  if (e != hipSuccess) return e;
+  Epilogue epi;
+  epi.stage = s;
+  int write_v;
+  if (scheme == ARDG_RK4) {
+    epi.kind = EPI_RK4;
+    write_v = (s < 3) || !f64;
+  } else {
+    epi.kind = EPI_LSERK;
+    epi.a = kLsA[s];
+    epi.b = kLsB[s];
+    write_v = !f64;
+  }
+  return launch_batch_element(g.N, f64, it.tile_l, grid_for(b, (int)it.litems.size(), t.grid_mult),
+                              b->dprobs, it.d_litems, (int)it.litems.size(), epi, in_u, write_v, st);
+}
+
+std::string cache_key(ardg_batch b, int precision, int N) {
+  return b->arch + " " + (precision == ARDG_FP64 ? "fp64" : "fp32") + " N=" + std::to_string(N);
+}
+
+bool cache_lookup(ardg_batch b, int precision, int N, Tiles& t) {
+  if (b->cache.empty()) return false;
+  std::ifstream in(b->cache);
+  if (!in) return false;
+  const std::string key = cache_key(b, precision, N);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ')
+      continue;
+    std::istringstream ss(line.substr(key.size()));
+    Tiles c;
+    if (ss >> c.edge_tile >> c.elem_tile >> c.grid_mult) {
+      t = c;
+      found = true;   // the last matching line wins
+    }
+  }
+  return found;
+}
+
+void cache_store(ardg_batch b, int precision, int N, const Tiles& t) {
+  if (b->cache.empty()) return;
+  std::ofstream out(b->cache, std::ios::app);
+  if (out) out << cache_key(b, precision, N) << " " << t.edge_tile << " " << t.elem_tile << " "
+               << t.grid_mult << "\n";
+}
+
+// Time one RK4 stage of group g (mean of reps) with the given tiles; the
+// problems' buffers must be set up in dprobs.
+ardg_status time_group(ardg_batch b, BatchGroup& g, int pi, bool f64, const Tiles& t, float* ms) {
+  g.tiles[pi] = t;
+  ardg_status s = build_items(b, g, pi, t.edge_tile, t.elem_tile);
+  if (s != ARDG_OK) return s;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < 4 && e == hipSuccess; ++r) e = group_stage(b, g, pi, f64, ARDG_RK4, r, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  const int reps = 8;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = group_stage(b, g, pi, f64, ARDG_RK4, r % 4, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t_ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "batch tuning");
+  *ms = t_ms / reps;
+  return ARDG_OK;
+}
+
+// Choose tiles for every group of a precision: coordinate search over the
+// edge tile, the element tile and the persistent grid size, each candidate
+// timed on scratch buffers (zero state, dt = 0) of the real problems.
+ardg_status tune(ardg_batch b, int precision) {
+  const int pi = precision == ARDG_FP64 ? 0 : 1;
+  const bool f64 = precision == ARDG_FP64;
+  std::vector<BatchGroup*> todo;
+  for (auto& g : b->groups) {
+    if (g.tuned[pi]) continue;
+    Tiles t;
+    if (cache_lookup(b, precision, g.N, t)) {
+      g.tiles[pi] = t;
+      g.tuned[pi] = true;
+      ardg_status s = build_items(b, g, pi, t.edge_tile, t.elem_tile);
+      if (s != ARDG_OK) return s;
+    } else {
+      todo.push_back(&g);
+    }
+  }
+  if (todo.empty()) return ARDG_OK;
+  // the descriptors are about to be overwritten: no earlier step may still read them
+  HIP_TRY(hipDeviceSynchronize(), "batch tuning: synchronise");
+  // scratch state and workspace for every problem
+  std::vector<size_t> offs;
+  size_t wbytes = 0;
+  batch_layout(b, precision, &offs, &wbytes);
+  size_t ubytes = 0;
+  std::vector<size_t> uoffs;
+  for (ardg_mesh m : b->meshes) {
+    uoffs.push_back(ubytes);
+    ubytes += align256((size_t)m->hm.K * m->ro.Np * 8);
+  }
+  char* scratch = nullptr;
+  hipError_t e = hipMalloc((void**)&scratch, ubytes + wbytes);
+  if (e != hipSuccess) return fail(ARDG_E_OOM, "batch tuning: scratch allocation failed");
+  e = hipMemset(scratch, 0, ubytes + wbytes);
+  std::vector<BatchProb> hp(b->meshes.size());
+  for (size_t i = 0; i < b->meshes.size(); ++i) {
+    hp[i].m = b->meshes[i]->dm;
+    hp[i].u = (double*)(scratch + uoffs[i]);
+    hp[i].acc = (double*)(scratch + ubytes + offs[3 * i]);
+    hp[i].v = scratch + ubytes + offs[3 * i + 1];
+    hp[i].flux = scratch + ubytes + offs[3 * i + 2];
+    hp[i].dt = 0.0;
+  }
+  if (e == hipSuccess) e = hipMemcpy(b->dprobs, hp.data(), hp.size() * sizeof(BatchProb), hipMemcpyHostToDevice);
+  ardg_status st = (e == hipSuccess) ? ARDG_OK : hip_fail(e, "batch tuning setup");
+  const int cand_tile[3] = {64, 128, 256};
+  const int cand_grid[4] = {1, 2, 4, 8};
+  for (BatchGroup* g : todo) {
+    if (st != ARDG_OK) break;
+    Tiles best;
+    float best_ms = 1e30f, ms = 0.f;
+    for (int c : cand_tile) {
+      Tiles t = best;
+      t.edge_tile = c;
+      if ((st = time_group(b, *g, pi, f64, t, &ms)) != ARDG_OK) break;
+      if (ms < best_ms) { best_ms = ms; best.edge_tile = c; }
+    }
+    best_ms = 1e30f;
+    for (int c : cand_tile) {
+      if (st != ARDG_OK) break;
+      Tiles t = best;
+      t.elem_tile = c;
+      if ((st = time_group(b, *g, pi, f64, t, &ms)) != ARDG_OK) break;
+      if (ms < best_ms) { best_ms = ms; best.elem_tile = c; }
+    }
+    best_ms = 1e30f;
+    for (int c : cand_grid) {
+      if (st != ARDG_OK) break;
+      Tiles t = best;
+      t.grid_mult = c;
+      if ((st = time_group(b, *g, pi, f64, t, &ms)) != ARDG_OK) break;
+      if (ms < best_ms) { best_ms = ms; best.grid_mult = c; }
+    }
+    if (st != ARDG_OK) break;
+    g->tiles[pi] = best;
+    st = build_items(b, *g, pi, best.edge_tile, best.elem_tile);
+    g->tuned[pi] = true;
+    cache_store(b, precision, g->N, best);
+  }
+  (void)hipFree(scratch);
+  b->hprobs.clear();   // descriptors on the device now point at scratch
+  b->drop_graphs();
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+ardg_status ardg_batch_create(const ardg_mesh* meshes, int32_t n, const char* tune_cache, ardg_batch* out) {
+  if (!out) return fail(ARDG_E_INVALID_ARG, "batch_create: null out");
+  *out = nullptr;
+  if (!meshes || n < 1) return fail(ARDG_E_INVALID_ARG, "batch_create: no meshes");
+  const int dev = meshes[0] ? meshes[0]->device : -1;
+  for (int i = 0; i < n; ++i) {
+    ardg_mesh m = meshes[i];
+    if (!m) return fail(ARDG_E_INVALID_ARG, "batch_create: null mesh");
+    if (m->device < 0 || m->device != dev)
+      return fail(ARDG_E_INVALID_ARG, "batch_create: meshes must live on one device");
+    if (m->dm.alg1 || m->dm.conv || m->nfields_D != 1)
+      return fail(ARDG_E_UNSUPPORTED, "batch_create: meshes need one field, constant D and no velocity");
+  }
+  try {
+    auto b = std::make_unique<ardg_batch_s>();
+    b->device = dev;
+    b->meshes.assign(meshes, meshes + n);
+    if (tune_cache) b->cache = tune_cache;
+    DeviceGuard g(dev);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    b->ncu = prop.multiProcessorCount;
+    b->arch = prop.gcnArchName;
+    const size_t sp = b->arch.find(':');
+    if (sp != std::string::npos) b->arch = b->arch.substr(0, sp);
+    std::map<int, std::vector<int>> byN;
+    for (int i = 0; i < n; ++i) byN[meshes[i]->N].push_back(i);
+    for (auto& kv : byN) {
+      BatchGroup gr;
+      gr.N = kv.first;
+      gr.probs = kv.second;
+      std::stable_sort(gr.probs.begin(), gr.probs.end(), [&](int a, int c) {
+        return meshes[a]->hm.K > meshes[c]->hm.K;
+      });
+      b->groups.push_back(gr);
+    }
+    void* p = nullptr;
+    HIP_TRY(hipMalloc(&p, sizeof(BatchProb) * n), "hipMalloc");
+    b->dprobs = (BatchProb*)p;
+    *out = b.release();
+    return ARDG_OK;
+  } catch (const std::exception& ex) {
+    return fail(ARDG_E_INVALID_ARG, std::string("batch_create: ") + ex.what());
+  }
+}
+
+void ardg_batch_destroy(ardg_batch batch) { delete batch; }
+
+ardg_status ardg_batch_workspace_bytes(ardg_batch batch, int32_t scheme, int32_t precision, int64_t* bytes) {
+  if (!batch || !bytes) return fail(ARDG_E_INVALID_ARG, "batch_workspace_bytes: null argument");
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  size_t t = 0;
+  batch_layout(batch, precision, nullptr, &t);
+  *bytes = (int64_t)t;
+  return ARDG_OK;
+}
+
+ardg_status ardg_batch_tiles(ardg_batch batch, int32_t precision, int32_t N, int32_t* edge_tile,
+                             int32_t* elem_tile, int32_t* grid) {
+  if (!batch) return fail(ARDG_E_INVALID_ARG, "batch_tiles: null batch");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  DeviceGuard g(batch->device);
+  ardg_status s = tune(batch, precision);
+  if (s != ARDG_OK) return s;
+  const int pi = precision == ARDG_FP64 ? 0 : 1;
+  for (auto& gr : batch->groups)
+    if (gr.N == N) {
+      if (edge_tile) *edge_tile = gr.tiles[pi].edge_tile;
+      if (elem_tile) *elem_tile = gr.tiles[pi].elem_tile;
+      if (grid) *grid = gr.tiles[pi].grid_mult;
+      return ARDG_OK;
+    }
+  return fail(ARDG_E_INVALID_ARG, "batch_tiles: no mesh of that order in the batch");
+}
+
+ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision, double* const* u_devs,
+                            void* work_dev, const double* dt, int32_t nsteps, void* hip_stream) {
+  if (!batch || !u_devs || !work_dev || !dt) return fail(ARDG_E_INVALID_ARG, "batch_step: null argument");
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "batch_step: work_dev not 256-byte aligned");
+  if (nsteps < 0) return fail(ARDG_E_INVALID_ARG, "batch_step: nsteps < 0");
+  const size_t n = batch->meshes.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!u_devs[i] || !std::isfinite(dt[i])) return fail(ARDG_E_INVALID_ARG, "batch_step: bad state pointer or dt");
+  if (nsteps == 0) return ARDG_OK;
+  DeviceGuard g(batch->device);
+  ardg_status s = tune(batch, precision);
+  if (s != ARDG_OK) return s;
+  std::vector<size_t> offs;
+  batch_layout(batch, precision, &offs, nullptr);
+  std::vector<BatchProb> hp(n);
+  char* w = (char*)work_dev;
+  for (size_t i = 0; i < n; ++i) {
+    hp[i].m = batch->meshes[i]->dm;
+    hp[i].u = u_devs[i];
+    hp[i].acc = (double*)(w + offs[3 * i]);
+    hp[i].v = w + offs[3 * i + 1];
+    hp[i].flux = w + offs[3 * i + 2];
+    hp[i].dt = dt[i];
+  }
+  if (batch->hprobs.size() != n ||
+      std::memcmp(batch->hprobs.data(), hp.data(), n * sizeof(BatchProb)) != 0) {
+    // earlier graph launches may still read the descriptors being replaced
+    HIP_TRY(hipDeviceSynchronize(), "batch_step: synchronise");
+    HIP_TRY(hipMemcpy(batch->dprobs, hp.data(), n * sizeof(BatchProb), hipMemcpyHostToDevice),
+            "batch_step: descriptor upload");
+    batch->hprobs = hp;
+    batch->drop_graphs();
+  }
+  const int pi = precision == ARDG_FP64 ? 0 : 1;
+  const bool f64 = precision == ARDG_FP64;
+  GraphKey key{scheme, precision, 1, nsteps, nullptr, work_dev, 0.0, batch->version};
+  auto it = batch->graphs.find(key);
+  if (it == batch->graphs.end()) {
+    if (!batch->cap_stream)
+      HIP_TRY(hipStreamCreateWithFlags(&batch->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRY(hipStreamBeginCapture(batch->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e = hipSuccess;
+    if (!f64)
+      for (auto& gr : batch->groups) {
+        if (e != hipSuccess) break;
+        GroupItems& gi = gr.items[pi];
+        const int Np = (gr.N + 1) * (gr.N + 2) / 2;
+        e = launch_batch_to_f32(batch->dprobs, gi.d_litems, (int)gi.litems.size(), gi.tile_l, Np,
+                                grid_for(batch, (int)gi.litems.size(), gr.tiles[pi].grid_mult), batch->cap_stream);
+      }
+    const int nst = scheme == ARDG_RK4 ? 4 : 5;
+    for (int step = 0; step < nsteps && e == hipSuccess; ++step)
+      for (int st = 0; st < nst && e == hipSuccess; ++st)
+        for (auto& gr : batch->groups) {
+          e = group_stage(batch, gr, pi, f64, scheme, st, batch->cap_stream);
+          if (e != hipSuccess) break;
+        }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(batch->cap_stream, &graph);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(e, "batch_step: launch during capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
+    if (batch->graphs.size() >= 8) batch->drop_graphs();
+    it = batch->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, (hipStream_t)hip_stream), "hipGraphLaunch");
   return ARDG_OK;
 }
 

@@ -12,7 +12,7 @@ constexpr int kMaxFields = 16;
 // Offsets of the packed constant operators (same layout in FP64 and FP32).
 struct OpLayout {
   int Np, Nfp;
-  int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, lift, tau, nr, ns, total;
+  int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, drsh, lift, tau, nr, ns, total;
   __host__ __device__ constexpr OpLayout(int N)
       : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
         n2b(0),
@@ -30,7 +30,8 @@ struct OpLayout {
         ubs(ubr + Nfp * Np),
         dr(ubs + Nfp * Np),
         ds(dr + Np * Np),
-        lift(ds + Np * Np),
+        drsh(ds + Np * Np),
+        lift(drsh + Np * 2 * Np),
         tau(lift + Np * 3 * Nfp),
         nr(tau + Nfp),
         ns(nr + Np),
@@ -55,6 +56,7 @@ struct DevMesh {
   const double* ops64 = nullptr;
   const float* ops32 = nullptr;
   int alg1 = 0;                   // element-wise D (Algorithm 1)
+  int elem_mfma = 1;              // element kernel on the matrix cores
   int conv = 0;                   // convective term on
   double Dfield[kMaxFields] = {};
   double vel[6] = {};             // v = (p0 + p2 x + p3 y, p1 + p4 x + p5 y)
@@ -74,12 +76,40 @@ struct Epilogue {
   void* vnext = nullptr;          // next stage input in the compute type (may be null)
 };
 
+// One problem of a batch: its mesh tables and its buffers (one field).
+struct BatchProb {
+  DevMesh m;
+  double* u = nullptr;      // FP64 state [K][Np] (caller-owned)
+  double* acc = nullptr;    // RK accumulator (workspace)
+  void* v = nullptr;        // stage vector in the compute type (workspace)
+  void* flux = nullptr;     // edge fluxes in the compute type (workspace)
+  double dt = 0.0;
+};
+
 // Edge fluxes of all interior and boundary edges for nfields fields.
 hipError_t launch_edge_flux(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
                             hipStream_t st);
 // Element volume + LIFT of the fluxes + epilogue.
 hipError_t launch_element(const DevMesh& m, bool fp64, int nfields, const void* vin,
                           const void* flux, const Epilogue& epi, hipStream_t st);
+// Batched (persistent) kernels over work items (problem, tile).  tile is the
+// number of edges / elements per item and the block size (64, 128 or 256);
+// grid is the number of persistent blocks.  in_u: the stage input is the
+// FP64 state itself (FP64 stage 0 or LSERK); write_v: the element kernel
+// writes the next stage input.
+hipError_t launch_batch_edge(int N, bool fp64, int tile, int grid, const BatchProb* probs,
+                             const int2* items, int nitems, int in_u, hipStream_t st);
+hipError_t launch_batch_element(int N, bool fp64, int tile, int grid, const BatchProb* probs,
+                                const int2* items, int nitems, const Epilogue& epi, int in_u,
+                                int write_v, hipStream_t st);
+// FP64 state -> FP32 stage vector for every problem of the items.
+hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int nitems, int tile,
+                               int Np, int grid, hipStream_t st);
+
+// Element kernel on the matrix cores (same contract as launch_element).
+hipError_t launch_element_mfma(const DevMesh& m, bool fp64, int nfields, const void* vin,
+                               const void* flux, const Epilogue& epi, hipStream_t st);
+
 // Copy an FP64 state into an FP32 copy (stage input of the FP32 mode).
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // Count non-finite values of an FP64 array into *count_dev (int).

@@ -32,38 +32,11 @@
 #include <cstdint>
 
 #include "device.hpp"
+#include "kernel_common.hpp"
 
 namespace ardg {
-
-template <typename T>
-using cptr = const T __attribute__((address_space(4)))*;
-
-__host__ __device__ constexpr int lat(int N, int i, int j) { return j * (N + 1) - (j * (j - 1)) / 2 + i; }
-
-// node index of face f's j-th node (counter-clockwise)
-__host__ __device__ constexpr int fnode(int N, int f, int j) {
-  return f == 0 ? lat(N, j, 0) : (f == 1 ? lat(N, N - j, j) : lat(N, 0, N - j));
-}
-
-// Keeps the scalar loads of one operator row next to the FMAs that use them:
-// without it the scheduler hoists whole matrices into SGPRs and spills.
-// The operator pointer is also passed through an empty asm so that repeated
-// uses of the same matrix are loaded again instead of being kept live.
-__device__ inline void row_fence() { __builtin_amdgcn_sched_barrier(0); }
-
-template <typename T>
-__device__ inline cptr<T> fresh(cptr<T> p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-
-template <typename T> __device__ inline cptr<T> opbase(const DevMesh& m);
-template <> __device__ inline cptr<double> opbase<double>(const DevMesh& m) {
-  return (cptr<double>)(m.ops64);
-}
-template <> __device__ inline cptr<float> opbase<float>(const DevMesh& m) {
-  return (cptr<float>)(m.ops32);
-}
+template <int ROWS, int COLS, typename T>
+__device__ inline void matvec(cptr<T> A0, const T* x, T* y);
 
 // Load one element, rotate so that face f is the hypotenuse, convert to
 // Bernstein coefficients and subdivide at the apex (mu = weights of w2, w3).
@@ -87,15 +60,7 @@ __device__ inline void subtriangle_coeffs(const T* __restrict__ ue, int f, doubl
     }
 #pragma unroll
   for (int j = 0; j <= N; ++j) trace[j] = t[lat(N, N - j, j)];
-#pragma unroll
-  for (int r = 0; r < Np; ++r) {
-    row_fence();
-    const cptr<T> a = fresh(n2b);
-    T s = 0;
-#pragma unroll
-    for (int q = 0; q < Np; ++q) s = fma(a[r * Np + q], t[q], s);
-    c[r] = s;
-  }
+  matvec<Np, Np, T>(n2b, t, c);
   const T m2 = (T)mu.x, m3 = (T)mu.y;
   const T m1 = (T)(1.0 - mu.x - mu.y);
 #pragma unroll
@@ -107,26 +72,29 @@ __device__ inline void subtriangle_coeffs(const T* __restrict__ ue, int f, doubl
         c[lat(N, i, j)] = m1 * c[lat(N, i, j)] + m2 * c[lat(N, i + 1, j)] + m3 * c[lat(N, i, j + 1)];
 }
 
+// y = A x for a constant row-major ROWS x COLS operator A.  Each row's entries
+// are wave-uniform scalar loads feeding scalar-operand FMAs; the row fence and
+// the fresh pointer keep one row in flight at a time (without them the whole
+// operator is hoisted into SGPRs and spilled).
 template <int ROWS, int COLS, typename T>
-__device__ inline T rowdot(cptr<T> A0, int row, const T* x) {
-  row_fence();
-  const cptr<T> A = fresh(A0);
-  T s = 0;
+__device__ inline void matvec(cptr<T> A0, const T* x, T* y) {
 #pragma unroll
-  for (int q = 0; q < COLS; ++q) s = fma(A[row * COLS + q], x[q], s);
-  return s;
+  for (int r = 0; r < ROWS; ++r) {
+    row_fence();
+    const cptr<T> A = fresh(A0);
+    T s = A[r * COLS] * x[0];
+#pragma unroll
+    for (int q = 1; q < COLS; ++q) s = fma(A[r * COLS + q], x[q], s);
+    y[r] = s;
+  }
 }
 
 template <int N, typename T, bool ALG1>
-__global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __restrict__ u,
-                                                        T* __restrict__ flux) {
+__device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
+                                 const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
   const int64_t E = m.E_int + m.E_bdy;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
-  const int field = blockIdx.y;
-  const cptr<T> op = opbase<T>(m);
   const T* uf = u + (int64_t)field * m.K * Np;
   T F[Nfp];
   T tr1[Nfp], tr2[Nfp];
@@ -145,26 +113,23 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
       const T D1 = (T)D1d, D2 = (T)D2d;
       if (D1d == D2d) {
         // equal coefficients: Algorithm 1 reduces exactly to D (U1 - U2) c
+        T g[2 * Nfp];
+        matvec<2 * Nfp, 2 * Np, T>(op + L.udr, c, g);
+#pragma unroll
+        for (int j = 0; j < Nfp; ++j) F[j] = D1 * (gR * g[j] + gS * g[Nfp + j]);
+      } else {
+        T g[4 * Nfp];
+        matvec<4 * Nfp, 2 * Np, T>(op + L.u1r, c, g);
 #pragma unroll
         for (int j = 0; j < Nfp; ++j)
-          F[j] = D1 * (gR * rowdot<Nfp, 2 * Np, T>(op + L.udr, j, c) +
-                       gS * rowdot<Nfp, 2 * Np, T>(op + L.uds, j, c));
-      } else {
-#pragma unroll
-        for (int j = 0; j < Nfp; ++j) {
-          const T a = gR * rowdot<Nfp, 2 * Np, T>(op + L.u1r, j, c) +
-                      gS * rowdot<Nfp, 2 * Np, T>(op + L.u1s, j, c);
-          const T b = gR * rowdot<Nfp, 2 * Np, T>(op + L.u2r, j, c) +
-                      gS * rowdot<Nfp, 2 * Np, T>(op + L.u2s, j, c);
-          F[j] = D1 * a - D2 * b;
-        }
+          F[j] = D1 * (gR * g[j] + gS * g[Nfp + j]) - D2 * (gR * g[2 * Nfp + j] + gS * g[3 * Nfp + j]);
       }
     } else {
       const T D = (T)m.Dfield[field];
+      T g[2 * Nfp];
+      matvec<2 * Nfp, 2 * Np, T>(op + L.kr, c, g);
 #pragma unroll
-      for (int j = 0; j < Nfp; ++j)
-        F[j] = D * (gR * rowdot<Nfp, 2 * Np, T>(op + L.kr, j, c) +
-                    gS * rowdot<Nfp, 2 * Np, T>(op + L.ks, j, c));
+      for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * g[j] + gS * g[Nfp + j]);
     }
     if (m.conv) vn = m.vn[e];
   } else {
@@ -176,10 +141,10 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
     subtriangle_coeffs<N, T>(uf + (int64_t)k * Np, fa, m.bmu[b], op + L.n2b, c, tr1);
     const T gR = (T)g.x, gS = (T)g.y;
     const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
-    const int orow = ALG1 ? L.ubr : L.kbr, srow = ALG1 ? L.ubs : L.kbs;
+    T gb[2 * Nfp];
+    matvec<2 * Nfp, Np, T>(op + (ALG1 ? L.ubr : L.kbr), c, gb);
 #pragma unroll
-    for (int j = 0; j < Nfp; ++j)
-      F[j] = D * (gR * rowdot<Nfp, Np, T>(op + orow, j, c) + gS * rowdot<Nfp, Np, T>(op + srow, j, c));
+    for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gb[j] + gS * gb[Nfp + j]);
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
     if (m.conv) vn = m.vn[e];
@@ -201,42 +166,81 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
   for (int j = 0; j < Nfp; ++j) out[j] = F[j];
 }
 
+template <int N, typename T, bool ALG1>
+__global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __restrict__ u,
+                                                        T* __restrict__ flux) {
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (e >= m.E_int + m.E_bdy) return;
+  edge_body<N, T, ALG1>(m, opbase<T>(m), e, blockIdx.y, u, flux);
+}
+
 constexpr int kElemBlock = 256;
+
+// Per-element inputs besides the nodal values, loaded ahead of the compute.
+template <int Nfp, typename T>
+struct ElemIn {
+  double2 p1, p2, p3;     // vertices
+  T fv[3][Nfp];           // face fluxes, already in this element's CCW order and sign
+  double D;
+};
+
+template <int N, typename T>
+__device__ inline void load_elem_in(const DevMesh& m, int64_t k, int field,
+                                    const T* __restrict__ flux, ElemIn<N + 1, T>& in) {
+  constexpr int Nfp = N + 1;
+  const int64_t E = m.E_int + m.E_bdy;
+  in.p1 = m.vert[3 * k];
+  in.p2 = m.vert[3 * k + 1];
+  in.p3 = m.vert[3 * k + 2];
+  in.D = m.alg1 ? m.Delem[k] : m.Dfield[field];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int code = m.elem_face[f * m.K + k];
+    const T* fe = flux + ((int64_t)field * E + (code >> 1)) * Nfp;
+    const bool side2 = code & 1;
+    T v[Nfp];
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) v[j] = fe[j];
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) in.fv[f][j] = side2 ? -v[Nfp - 1 - j] : v[j];
+  }
+}
 
 // du/dt of one element from its nodal values u (registers).
 template <int N, typename T, bool CONV>
-__device__ inline void element_rhs(const DevMesh& m, int64_t k, int field, const T* u,
-                                   const T* __restrict__ flux, T* rhs) {
+__device__ inline void element_rhs(const DevMesh& m, cptr<T> op, const T* u,
+                                   const ElemIn<N + 1, T>& in, T* rhs) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
-  const int64_t E = m.E_int + m.E_bdy;
-  const cptr<T> op = opbase<T>(m);
   // affine factors of this element (eqs. mapping_tri_diff, triangle_jacobian_a/b)
-  const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
+  const double2 p1 = in.p1, p2 = in.p2, p3 = in.p3;
   const double xr = 0.5 * (p2.x - p1.x), yr = 0.5 * (p2.y - p1.y);
   const double xs = 0.5 * (p3.x - p1.x), ys = 0.5 * (p3.y - p1.y);
   const double J = xr * ys - xs * yr;
   const T rx = (T)(ys / J), ry = (T)(-xs / J), sx = (T)(-yr / J), sy = (T)(xr / J);
 
   T qx[Np], qy[Np];
-#pragma unroll
-  for (int i = 0; i < Np; ++i) {
-    const T ur = rowdot<Np, Np, T>(op + L.dr, i, u);
-    const T us = rowdot<Np, Np, T>(op + L.ds, i, u);
-    qx[i] = rx * ur + sx * us;
-    qy[i] = ry * ur + sy * us;
-  }
-  const T D = m.alg1 ? (T)m.Delem[k] : (T)m.Dfield[field];
   {
-    T wr[Np], ws[Np];
+    T urs[2 * Np];
+    matvec<2 * Np, Np, T>(op + L.dr, u, urs);          // [Dr; Ds] u
 #pragma unroll
     for (int i = 0; i < Np; ++i) {
-      wr[i] = rx * qx[i] + ry * qy[i];
-      ws[i] = sx * qx[i] + sy * qy[i];
+      qx[i] = rx * urs[i] + sx * urs[Np + i];
+      qy[i] = ry * urs[i] + sy * urs[Np + i];
     }
+  }
+  const T D = (T)in.D;
+  {
+    T w[2 * Np];
 #pragma unroll
-    for (int i = 0; i < Np; ++i)
-      rhs[i] = D * (rowdot<Np, Np, T>(op + L.dr, i, wr) + rowdot<Np, Np, T>(op + L.ds, i, ws));
+    for (int i = 0; i < Np; ++i) {
+      w[i] = rx * qx[i] + ry * qy[i];
+      w[Np + i] = sx * qx[i] + sy * qy[i];
+    }
+    T div[Np];
+    matvec<Np, 2 * Np, T>(op + L.drsh, w, div);        // [Dr Ds] [wr; ws]
+#pragma unroll
+    for (int i = 0; i < Np; ++i) rhs[i] = D * div[i];
   }
 
   T vx[Np], vy[Np];
@@ -251,7 +255,8 @@ __device__ inline void element_rhs(const DevMesh& m, int64_t k, int field, const
     }
   }
 
-  // surface terms: (J_f / J) LIFT_f (F_f - D n.q + [n.v u-])
+  // surface terms: (J_f / J) LIFT_f (F_f - D n.q + [n.v u-]), one LIFT pass
+  T jump[3 * Nfp];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const double2 a = (f == 0) ? p1 : (f == 1 ? p2 : p3);
@@ -260,31 +265,20 @@ __device__ inline void element_rhs(const DevMesh& m, int64_t k, int field, const
     const double len = sqrt(tx * tx + ty * ty);
     const T nx = (T)(ty / len), ny = (T)(-tx / len);
     const T scale = (T)(0.5 * len / J);
-    const int code = m.elem_face[f * m.K + k];
-    const int64_t e = code >> 1;
-    const bool side2 = code & 1;
-    const T* fe = flux + ((int64_t)field * E + e) * Nfp;
-    T fv[Nfp];
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) fv[j] = fe[j];
-    T jump[Nfp];
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
-      const T G = side2 ? -fv[Nfp - 1 - j] : fv[j];
+      const T G = in.fv[f][j];
       const int nd = fnode(N, f, j);
       T jv = G - D * (nx * qx[nd] + ny * qy[nd]);
       if (CONV) jv += (nx * vx[nd] + ny * vy[nd]) * u[nd];
-      jump[j] = scale * jv;
+      jump[f * Nfp + j] = scale * jv;
     }
+  }
+  {
+    T lifted[Np];
+    matvec<Np, 3 * Nfp, T>(op + L.lift, jump, lifted);
 #pragma unroll
-    for (int i = 0; i < Np; ++i) {
-      row_fence();
-      const cptr<T> lf = fresh(op);
-      T s = 0;
-#pragma unroll
-      for (int j = 0; j < Nfp; ++j) s = fma(lf[L.lift + i * 3 * Nfp + f * Nfp + j], jump[j], s);
-      rhs[i] += s;
-    }
+    for (int i = 0; i < Np; ++i) rhs[i] += lifted[i];
   }
 
   if (CONV) {
@@ -295,82 +289,105 @@ __device__ inline void element_rhs(const DevMesh& m, int64_t k, int field, const
       fx[n] = vx[n] * u[n];
       fy[n] = vy[n] * u[n];
     }
+    T dfx[2 * Np], dfy[2 * Np];
+    matvec<2 * Np, Np, T>(op + L.dr, fx, dfx);
+    matvec<2 * Np, Np, T>(op + L.dr, fy, dfy);
 #pragma unroll
-    for (int i = 0; i < Np; ++i) {
-      const T dxr = rowdot<Np, Np, T>(op + L.dr, i, fx), dxs = rowdot<Np, Np, T>(op + L.ds, i, fx);
-      const T dyr = rowdot<Np, Np, T>(op + L.dr, i, fy), dys = rowdot<Np, Np, T>(op + L.ds, i, fy);
-      rhs[i] -= rx * dxr + sx * dxs + ry * dyr + sy * dys;
-    }
+    for (int i = 0; i < Np; ++i)
+      rhs[i] -= rx * dfx[i] + sx * dfx[Np + i] + ry * dfy[i] + sy * dfy[Np + i];
   }
 }
 
-// One block = kElemBlock consecutive elements.  Their nodal values form one
-// contiguous chunk of the [F][K][Np] array: it is staged through LDS with
-// coalesced loads, each thread computes one element from registers, the
-// element results go back to LDS, and the Runge-Kutta update runs over the
-// chunk's degrees of freedom with coalesced global traffic.
-template <int N, typename T, bool CONV>
-__global__ __launch_bounds__(kElemBlock) void element_kernel(DevMesh m, const T* __restrict__ vin,
-                                                             const T* __restrict__ flux, Epilogue epi) {
+// Thread-per-element tile (VALU, scalar-broadcast operators).
+template <int N, typename T, bool CONV, int TILE>
+__device__ inline void element_tile(const DevMesh& m, cptr<T> op, int64_t k0, int field,
+                                    const T* __restrict__ vin, const T* __restrict__ flux,
+                                    const Epilogue& epi, T* sh) {
   constexpr int Np = (N + 1) * (N + 2) / 2;
-  __shared__ T sh[kElemBlock * Np];
-  const int64_t k0 = (int64_t)blockIdx.x * kElemBlock;
-  const int field = blockIdx.y;
-  const int nel = (int)((m.K - k0) < kElemBlock ? (m.K - k0) : kElemBlock);
-  const int ndof = nel * Np;
-  const int64_t base = ((int64_t)field * m.K + k0) * Np;
+  constexpr bool kPre = ElemTune<N>::prefetch;
   const int t = threadIdx.x;
-
-  for (int i = t; i < ndof; i += kElemBlock) sh[i] = vin[base + i];
+  TileIO<Np> io;
+  tile_begin<N, T, TILE>(m, k0, field, vin, epi, sh, io, kPre);
+  ElemIn<N + 1, T> in;
+  if (t < io.nel) load_elem_in<N, T>(m, k0 + t, field, flux, in);
   __syncthreads();
   T u[Np];
-  if (t < nel) {
+  if (t < io.nel) {
 #pragma unroll
     for (int n = 0; n < Np; ++n) u[n] = sh[t * Np + n];
   }
   __syncthreads();
-  if (t < nel) {
+  if (t < io.nel) {
     T rhs[Np];
-    element_rhs<N, T, CONV>(m, k0 + t, field, u, flux, rhs);
+    element_rhs<N, T, CONV>(m, op, u, in, rhs);
 #pragma unroll
     for (int n = 0; n < Np; ++n) sh[t * Np + n] = rhs[n];
   }
   __syncthreads();
+  tile_end<N, T, TILE>(epi, sh, io, kPre);
+}
 
-  if (epi.kind == EPI_RHS) {
-    T* o = (T*)epi.rhs_out + base;
-    for (int i = t; i < ndof; i += kElemBlock) o[i] = sh[i];
-    return;
+template <int N, typename T, bool CONV>
+__global__ __launch_bounds__(kElemBlock) __attribute__((amdgpu_waves_per_eu(ElemTune<N>::waves)))
+void element_kernel(DevMesh m, const T* __restrict__ vin, const T* __restrict__ flux, Epilogue epi) {
+  constexpr int Np = (N + 1) * (N + 2) / 2;
+  __shared__ T sh[kElemBlock * Np];
+  const int64_t k0 = xcd_block(blockIdx.x, gridDim.x) * kElemBlock;
+  element_tile<N, T, CONV, kElemBlock>(m, opbase<T>(m), k0, blockIdx.y, vin, flux, epi, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Batching: many independent meshes.  Persistent blocks walk a list of work
+// items (problem, tile); every item reads its problem's descriptor (tables,
+// buffers, D, dt) through wave-uniform loads and runs the same edge and
+// element bodies as the single-mesh kernels.
+// ---------------------------------------------------------------------------
+
+template <int N, typename T, int TILE>
+__global__ __launch_bounds__(TILE) void batch_edge_kernel(const BatchProb* __restrict__ probs,
+                                                          const int2* __restrict__ items, int nitems,
+                                                          int in_u) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchProb* P = probs + __builtin_amdgcn_readfirstlane(w.x);
+    const int64_t e = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * TILE + threadIdx.x;
+    if (e < P->m.E_int + P->m.E_bdy) {
+      const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
+      edge_body<N, T, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+    }
   }
-  double* U = epi.u + base;
-  double* A = epi.acc + base;
-  T* vn = epi.vnext ? (T*)epi.vnext + base : nullptr;
-  const double dt = epi.dt;
-  if (epi.kind == EPI_RK4) {
-    const int s = epi.stage;
-    if (s < 3) {
-      const double c = (s < 2) ? 0.5 * dt : dt;
-      for (int i = t; i < ndof; i += kElemBlock) {
-        const double r = (double)sh[i];
-        A[i] = (s == 0) ? r : A[i] + 2.0 * r;
-        vn[i] = (T)(U[i] + c * r);
-      }
-    } else {
-      for (int i = t; i < ndof; i += kElemBlock) {
-        const double un = U[i] + dt / 6.0 * (A[i] + (double)sh[i]);
-        U[i] = un;
-        if (vn) vn[i] = (T)un;
-      }
-    }
-  } else {
-    for (int i = t; i < ndof; i += kElemBlock) {
-      const double r = dt * (double)sh[i];
-      const double res = (epi.stage == 0) ? r : epi.a * A[i] + r;
-      A[i] = res;
-      const double un = U[i] + epi.b * res;
-      U[i] = un;
-      if (vn) vn[i] = (T)un;
-    }
+}
+
+template <int N, typename T, int TILE>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(ElemTune<N>::waves)))
+void batch_element_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ items,
+                          int nitems, Epilogue epi0, int in_u, int write_v) {
+  constexpr int Np = (N + 1) * (N + 2) / 2;
+  __shared__ T sh[TILE * Np];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchProb* P = probs + __builtin_amdgcn_readfirstlane(w.x);
+    Epilogue epi = epi0;
+    epi.u = P->u;
+    epi.acc = P->acc;
+    epi.vnext = write_v ? P->v : nullptr;
+    epi.dt = P->dt;
+    const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
+    const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * TILE;
+    element_tile<N, T, false, TILE>(P->m, opbase<T>(P->m), k0, 0, vin, (const T*)P->flux, epi, sh);
+    __syncthreads();
+  }
+}
+
+__global__ void batch_to_f32_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ items,
+                                    int nitems, int tile, int Np) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchProb* P = probs + w.x;
+    const int64_t k0 = (int64_t)w.y * tile;
+    const int64_t k1 = (k0 + tile < P->m.K) ? k0 + tile : P->m.K;
+    float* v = (float*)P->v;
+    for (int64_t i = k0 * Np + threadIdx.x; i < k1 * Np; i += blockDim.x) v[i] = (float)P->u[i];
   }
 }
 
@@ -446,8 +463,78 @@ hipError_t launch_edge_flux(const DevMesh& m, bool fp64, int nfields, const void
 
 hipError_t launch_element(const DevMesh& m, bool fp64, int nfields, const void* vin,
                           const void* flux, const Epilogue& epi, hipStream_t st) {
+  if (m.elem_mfma) return launch_element_mfma(m, fp64, nfields, vin, flux, epi, st);
   return fp64 ? elem_dispatch<double>(m, nfields, vin, flux, epi, st)
               : elem_dispatch<float>(m, nfields, vin, flux, epi, st);
+}
+
+template <int N, typename T>
+hipError_t batch_edge_t(int tile, int grid, const BatchProb* probs, const int2* items, int nitems,
+                        int in_u, hipStream_t st) {
+  switch (tile) {
+    case 64: hipLaunchKernelGGL((batch_edge_kernel<N, T, 64>), dim3(grid), dim3(64), 0, st, probs, items, nitems, in_u); break;
+    case 128: hipLaunchKernelGGL((batch_edge_kernel<N, T, 128>), dim3(grid), dim3(128), 0, st, probs, items, nitems, in_u); break;
+    case 256: hipLaunchKernelGGL((batch_edge_kernel<N, T, 256>), dim3(grid), dim3(256), 0, st, probs, items, nitems, in_u); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t batch_elem_t(int tile, int grid, const BatchProb* probs, const int2* items, int nitems,
+                        const Epilogue& epi, int in_u, int write_v, hipStream_t st) {
+  switch (tile) {
+    case 64: hipLaunchKernelGGL((batch_element_kernel<N, T, 64>), dim3(grid), dim3(64), 0, st, probs, items, nitems, epi, in_u, write_v); break;
+    case 128: hipLaunchKernelGGL((batch_element_kernel<N, T, 128>), dim3(grid), dim3(128), 0, st, probs, items, nitems, epi, in_u, write_v); break;
+    case 256: hipLaunchKernelGGL((batch_element_kernel<N, T, 256>), dim3(grid), dim3(256), 0, st, probs, items, nitems, epi, in_u, write_v); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define ARDG_BATCH_N(FN, N, ...)                   \
+  switch (N) {                                     \
+    case 1: return FN<1, T>(__VA_ARGS__);          \
+    case 2: return FN<2, T>(__VA_ARGS__);          \
+    case 3: return FN<3, T>(__VA_ARGS__);          \
+    case 4: return FN<4, T>(__VA_ARGS__);          \
+    case 5: return FN<5, T>(__VA_ARGS__);          \
+    case 6: return FN<6, T>(__VA_ARGS__);          \
+    default: return hipErrorInvalidValue;          \
+  }
+
+template <typename T>
+hipError_t batch_edge_dispatch(int N, int tile, int grid, const BatchProb* probs, const int2* items,
+                               int nitems, int in_u, hipStream_t st) {
+  ARDG_BATCH_N(batch_edge_t, N, tile, grid, probs, items, nitems, in_u, st)
+}
+
+template <typename T>
+hipError_t batch_elem_dispatch(int N, int tile, int grid, const BatchProb* probs, const int2* items,
+                               int nitems, const Epilogue& epi, int in_u, int write_v, hipStream_t st) {
+  ARDG_BATCH_N(batch_elem_t, N, tile, grid, probs, items, nitems, epi, in_u, write_v, st)
+}
+
+hipError_t launch_batch_edge(int N, bool fp64, int tile, int grid, const BatchProb* probs,
+                             const int2* items, int nitems, int in_u, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  return fp64 ? batch_edge_dispatch<double>(N, tile, grid, probs, items, nitems, in_u, st)
+              : batch_edge_dispatch<float>(N, tile, grid, probs, items, nitems, 0, st);
+}
+
+hipError_t launch_batch_element(int N, bool fp64, int tile, int grid, const BatchProb* probs,
+                                const int2* items, int nitems, const Epilogue& epi, int in_u,
+                                int write_v, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  return fp64 ? batch_elem_dispatch<double>(N, tile, grid, probs, items, nitems, epi, in_u, write_v, st)
+              : batch_elem_dispatch<float>(N, tile, grid, probs, items, nitems, epi, 0, write_v, st);
+}
+
+hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int nitems, int tile,
+                               int Np, int grid, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_to_f32_kernel, dim3(grid), dim3(256), 0, st, probs, items, nitems, tile, Np);
+  return hipGetLastError();
 }
 
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st) {

@@ -174,3 +174,14 @@ def test_error_paths(L):
     with pytest.raises(ardg.ArdgError):
         lm.rhs_eval(1, 1, stream=0)
     assert L.ardg_status_string(-4).decode().startswith("degenerate")
+
+
+def test_batch_refuses_host_only_meshes(L):
+    o = ardg.Ops(2)
+    mesh = W.split_square_mesh(3, 0.0)
+    lm = ardg.Mesh(o, mesh.vxy, mesh.etov, device=-1)
+    with pytest.raises(ardg.ArdgError) as ei:
+        ardg.Batch([lm])
+    assert ei.value.status == -1
+    with pytest.raises(ardg.ArdgError):
+        ardg.Batch([])
