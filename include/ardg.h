@@ -166,7 +166,12 @@ ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, co
 
 /* Edge fluxes only (the interior and boundary loop of Algorithm aRDG with the
  * diagonal flux; Algorithm 1 for element-wise D): flux_dev [F][E][Nfp] in the
- * precision's type, D included.  A parity hook for the edge kernel. */
+ * precision's type, D included, each edge's values multiplied by its surface
+ * factor sJ = |edge| / 2 (the factor the surface integral of the weak form
+ * applies, so that the element kernel needs no edge lengths).  Interior edges
+ * first in ardg_mesh_export(EDGES) order, then boundary faces; values at the
+ * edge's LGL nodes in element 1's counter-clockwise order, the sign of element
+ * 1's outward normal.  A parity hook for the edge kernel. */
 ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfields,
                                 const void* u_dev, void* flux_dev, void* hip_stream);
 

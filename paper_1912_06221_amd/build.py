@@ -1,7 +1,7 @@
 """Build the HIP/C++ library libardg.so in-tree for gfx950.
 
 Host setup code (refops.cpp, meshsetup.cpp) and the C ABI (api.cpp) are plain
-C++ compiled with g++; the kernels (kernels.hip) are compiled by hipcc for
+C++ compiled with g++; the kernels (kernels*.hip) are compiled by hipcc for
 gfx950 with packed FP32 instructions disabled.  Everything is linked by hipcc
 into one shared library next to this file.
 """
@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         cmds.append(host + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("kernels.hip", "kernels_mfma.hip"):
+    for src in ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip"):
         kobj = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmds.append([hipcc, f"--offload-arch={ARCH}"] + common + HIP_DEVICE_FLAGS +
                     ["-c", os.path.join(CSRC, src), "-o", kobj])

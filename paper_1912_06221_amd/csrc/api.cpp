@@ -242,10 +242,14 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
     if (st != ARDG_OK) return fail(st, err);
     m->dm.N = m->N;
     {
-      // element kernel implementation: matrix cores (default) or thread per
-      // element with scalar-broadcast operators (ARDG_ELEMENT_KERNEL=valu)
+      // kernel implementations.  Element kernel: matrix cores (default) or one
+      // thread per element (ARDG_ELEMENT_KERNEL=valu).  Edge kernel: one
+      // thread per edge (default) or interior edges on the matrix cores
+      // (ARDG_EDGE_KERNEL=mfma).
       const char* ek = std::getenv("ARDG_ELEMENT_KERNEL");
       m->dm.elem_mfma = (ek && std::string(ek) == "valu") ? 0 : 1;
+      const char* ed = std::getenv("ARDG_EDGE_KERNEL");
+      m->dm.edge_mfma = (ed && std::string(ed) == "mfma") ? 1 : 0;
     }
     m->dm.K = m->hm.K;
     m->dm.E_int = m->hm.E_int;
@@ -263,7 +267,15 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
     if (!g.ok) return fail(ARDG_E_HIP, "mesh_create: hipSetDevice failed");
     m->device = device;
     const HostMesh& h = m->hm;
-    // device tables
+    // device tables.  gamma (and below n.v) are stored times the edge's
+    // surface factor sJ = |edge| / 2: the edge kernels then emit sJ * flux,
+    // which is what the element's surface term lifts.
+    const int rotv[3][3] = {{2, 0, 1}, {0, 1, 2}, {1, 2, 0}};
+    auto half_len = [&](int64_t k, int f) {
+      const int a = h.etov[3 * k + rotv[f][1]], b = h.etov[3 * k + rotv[f][2]];
+      const double tx = h.vxy[2 * b] - h.vxy[2 * a], ty = h.vxy[2 * b + 1] - h.vxy[2 * a + 1];
+      return 0.5 * std::sqrt(tx * tx + ty * ty);
+    };
     std::vector<int2> ef(h.E_int);
     std::vector<double2> mu1(h.E_int), mu2(h.E_int), gam(h.E_int);
     for (int64_t e = 0; e < h.E_int; ++e) {
@@ -271,14 +283,16 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
       ef[e].y = h.e2[e] | (h.f2[e] << 30);
       mu1[e] = make_double2(h.mu1[2 * e], h.mu1[2 * e + 1]);
       mu2[e] = make_double2(h.mu2[2 * e], h.mu2[2 * e + 1]);
-      gam[e] = make_double2(h.gam[2 * e], h.gam[2 * e + 1]);
+      const double sj = half_len(h.e1[e], h.f1[e]);
+      gam[e] = make_double2(sj * h.gam[2 * e], sj * h.gam[2 * e + 1]);
     }
     std::vector<int> bk(h.E_bdy);
     std::vector<double2> bmu(h.E_bdy), bgam(h.E_bdy);
     for (int64_t b = 0; b < h.E_bdy; ++b) {
       bk[b] = h.bk[b] | (h.bf[b] << 30);
       bmu[b] = make_double2(h.bmu[2 * b], h.bmu[2 * b + 1]);
-      bgam[b] = make_double2(h.bgam[2 * b], h.bgam[2 * b + 1]);
+      const double sj = half_len(h.bk[b], h.bf[b]);
+      bgam[b] = make_double2(sj * h.bgam[2 * b], sj * h.bgam[2 * b + 1]);
     }
     std::vector<double2> vert(3 * h.K);
     for (int64_t k = 0; k < h.K; ++k)
@@ -430,8 +444,10 @@ ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* p
   auto edge_vn = [&](int64_t k, int f) {
     const int a = h.etov[3 * k + rotv[f][1]], b = h.etov[3 * k + rotv[f][2]];
     const double ax = h.vxy[2 * a], ay = h.vxy[2 * a + 1], bx = h.vxy[2 * b], by = h.vxy[2 * b + 1];
-    const double tx = bx - ax, ty = by - ay, L = std::sqrt(tx * tx + ty * ty);
-    const double nx = ty / L, ny = -tx / L;
+    // sJ n = (ty, -tx) / 2 with sJ = |edge| / 2: the stored n.v carries the
+    // edge's surface factor like gamma
+    const double tx = bx - ax, ty = by - ay;
+    const double nx = 0.5 * ty, ny = -0.5 * tx;
     double va[2], vb[2];
     vel(ax, ay, va);
     vel(bx, by, vb);

@@ -57,6 +57,7 @@ struct DevMesh {
   const float* ops32 = nullptr;
   int alg1 = 0;                   // element-wise D (Algorithm 1)
   int elem_mfma = 1;              // element kernel on the matrix cores
+  int edge_mfma = 0;              // interior edges on the matrix cores
   int conv = 0;                   // convective term on
   double Dfield[kMaxFields] = {};
   double vel[6] = {};             // v = (p0 + p2 x + p3 y, p1 + p4 x + p5 y)
@@ -106,6 +107,10 @@ hipError_t launch_batch_element(int N, bool fp64, int tile, int grid, const Batc
 hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int nitems, int tile,
                                int Np, int grid, hipStream_t st);
 
+// Edge kernel with interior edges on the matrix cores (same contract as
+// launch_edge_flux).
+hipError_t launch_edge_mfma(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
+                            hipStream_t st);
 // Element kernel on the matrix cores (same contract as launch_element).
 hipError_t launch_element_mfma(const DevMesh& m, bool fp64, int nfields, const void* vin,
                                const void* flux, const Epilogue& epi, hipStream_t st);

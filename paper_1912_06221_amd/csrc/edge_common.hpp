@@ -1,0 +1,250 @@
+// Per-edge aRDG flux on the vector unit (one lane per edge), shared by the
+// thread-per-edge kernels, the batched kernels and the boundary faces of the
+// matrix-core edge kernel, and the scalar-operand matrix-vector product used
+// by the thread-per-element kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+#include "kernel_common.hpp"
+
+namespace ardg {
+
+// y_v = A x_v (v < NV) for a constant row-major ROWS x COLS operator A.  The
+// entries are wave-uniform scalar loads feeding scalar-operand FMAs, taken in
+// chunks of at most CH entries walked row by row: the loads of the next chunk
+// are issued before the FMAs of the current one, so their latency is covered
+// by arithmetic, while the fence between chunks keeps at most two chunks in
+// SGPRs (without it the whole operator is hoisted into SGPRs and spilled).
+// With NV = 2 every loaded entry feeds two vectors.
+template <int ROWS, int COLS, int NV, typename T, typename XA, typename YA>
+__device__ inline void matvec_n(cptr<T> A0, XA x, YA y) {
+  constexpr int CH = sizeof(T) == 8 ? 12 : 16;
+  constexpr int NCH = (COLS + CH - 1) / CH;
+  constexpr int NSTEP = ROWS * NCH;
+  T buf[2][CH];
+  {
+    const cptr<T> A = fresh(A0);
+#pragma unroll
+    for (int q = 0; q < CH && q < COLS; ++q) buf[0][q] = A[q];
+  }
+  T acc[NV];
+#pragma unroll
+  for (int st = 0; st < NSTEP; ++st) {
+    const int r = st / NCH, ch = st % NCH;
+    const int q0 = ch * CH;
+    const int qn = (COLS - q0) < CH ? (COLS - q0) : CH;
+    row_fence();
+    if (st + 1 < NSTEP) {
+      const int r1 = (st + 1) / NCH, c1 = (st + 1) % NCH;
+      const int p0 = c1 * CH;
+      const int pn = (COLS - p0) < CH ? (COLS - p0) : CH;
+      const cptr<T> A = fresh(A0);
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (q < pn) buf[(st + 1) & 1][q] = A[r1 * COLS + p0 + q];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      T s = (ch == 0) ? buf[st & 1][0] * x[v][q0] : fma(buf[st & 1][0], x[v][q0], acc[v]);
+#pragma unroll
+      for (int q = 1; q < CH; ++q)
+        if (q < qn) s = fma(buf[st & 1][q], x[v][q0 + q], s);
+      acc[v] = s;
+      if (ch == NCH - 1) y[v][r] = s;
+    }
+  }
+}
+
+// single-vector views for matvec_n: v[0][q] == p[q]
+template <typename P>
+struct OneVec {
+  P p;
+  __device__ P operator[](int) const { return p; }
+};
+
+template <int ROWS, int COLS, typename T>
+__device__ inline void matvec_pf(cptr<T> A0, const T* x, T* y) {
+  matvec_n<ROWS, COLS, 1, T>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
+}
+
+// y = A x with one operator row in flight at a time (no prefetch): the row
+// fence and the fresh pointer keep the row's scalar loads next to its FMAs.
+// Used where many other values are live (the thread-per-element kernels).
+template <int ROWS, int COLS, typename T>
+__device__ inline void matvec(cptr<T> A0, const T* x, T* y) {
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    row_fence();
+    const cptr<T> A = fresh(A0);
+    T s = A[r * COLS] * x[0];
+#pragma unroll
+    for (int q = 1; q < COLS; ++q) s = fma(A[r * COLS + q], x[q], s);
+    y[r] = s;
+  }
+}
+
+// In-place de Casteljau subdivision of Bernstein coefficients on I at the
+// point with barycentric weights (1 - mu.x - mu.y, mu.x, mu.y) of (a1, a2, a3).
+// Afterwards lattice slot (i,j) holds the coefficient with multi-index
+// (N-i-j, i, j) of the same polynomial on the sub-triangle (point, a2, a3).
+template <int N, typename T>
+__device__ inline void decasteljau(T* c, double2 mu) {
+  const T m2 = (T)mu.x, m3 = (T)mu.y;
+  const T m1 = (T)(1.0 - mu.x - mu.y);
+#pragma unroll
+  for (int n = N; n >= 1; --n)
+#pragma unroll
+    for (int j = 0; j <= n - 1; ++j)
+#pragma unroll
+      for (int i = 0; i <= n - 1 - j; ++i)
+        c[lat(N, i, j)] = m1 * c[lat(N, i, j)] + m2 * c[lat(N, i + 1, j)] + m3 * c[lat(N, i, j + 1)];
+}
+
+// Reorder one element's nodal values so that face f is the hypotenuse of the
+// reference triangle (section "Reordering nodes in the reference domain"):
+// rotated vertices (v3, v1, v2) for face 0, (v1, v2, v3) for face 1 and
+// (v2, v3, v1) for face 2, a register permutation.  trace[j] receives the
+// values on face f, counter-clockwise.
+template <int N, typename T>
+__device__ inline void rotate_to_face(const T* v, int f, T* t, T* trace) {
+#pragma unroll
+  for (int j = 0; j <= N; ++j)
+#pragma unroll
+    for (int i = 0; i <= N - j; ++i) {
+      const T a0 = v[lat(N, j, N - i - j)];
+      const T a1 = v[lat(N, i, j)];
+      const T a2 = v[lat(N, N - i - j, i)];
+      t[lat(N, i, j)] = (f == 0) ? a0 : ((f == 1) ? a1 : a2);
+    }
+#pragma unroll
+  for (int j = 0; j <= N; ++j) trace[j] = t[lat(N, N - j, j)];
+}
+
+// Pipelined products where registers allow it (moderate orders), the
+// one-row-at-a-time form otherwise.
+template <bool PF, int ROWS, int COLS, typename T>
+__device__ inline void matvec_sel(cptr<T> A0, const T* x, T* y) {
+  if constexpr (PF)
+    matvec_pf<ROWS, COLS, T>(A0, x, y);
+  else
+    matvec<ROWS, COLS, T>(A0, x, y);
+}
+
+template <int N, typename T, bool ALG1>
+__device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
+                                 const T* __restrict__ u, T* __restrict__ flux) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp;
+  constexpr bool kBoth = sizeof(T) == 8 ? N <= 4 : N <= 5;
+  const int64_t E = m.E_int + m.E_bdy;
+  const T* uf = u + (int64_t)field * m.K * Np;
+  T F[Nfp];
+  T tr1[Nfp], tr2[Nfp];
+  double2 vn = make_double2(0.0, 0.0);
+  if (e < m.E_int) {
+    // one round of loads for the edge table, a second for both elements
+    const int2 ef = m.ef[e];
+    const double2 g = m.gam[e], mu1 = m.mu1[e], mu2 = m.mu2[e];
+    if (m.conv) vn = m.vn[e];
+    const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
+    const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
+    double D1d = 0.0, D2d = 0.0;
+    if (ALG1) {
+      D1d = m.Delem[k1];
+      D2d = m.Delem[k2];
+    }
+    // rotate, convert to Bernstein coefficients, subdivide each side at its
+    // apex.  Up to moderate order both elements are loaded at once and
+    // converted with one pass over the conversion matrix; above it the sides
+    // go one after the other to stay within the register file.
+    T c[2][Np];
+    if (kBoth) {
+      T v[2][Np], t[2][Np];
+#pragma unroll
+      for (int n = 0; n < Np; ++n) v[0][n] = uf[(int64_t)k1 * Np + n];
+#pragma unroll
+      for (int n = 0; n < Np; ++n) v[1][n] = uf[(int64_t)k2 * Np + n];
+      rotate_to_face<N, T>(v[0], fa, t[0], tr1);
+      rotate_to_face<N, T>(v[1], fb, t[1], tr2);
+      matvec_n<Np, Np, 2, T>(op + L.n2b, t, c);
+    } else {
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        T v[Np], t[Np];
+        const int64_t kk = sd ? k2 : k1;
+#pragma unroll
+        for (int n = 0; n < Np; ++n) v[n] = uf[kk * Np + n];
+        rotate_to_face<N, T>(v, sd ? fb : fa, t, sd ? tr2 : tr1);
+        matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c[sd]);
+      }
+    }
+    decasteljau<N, T>(c[0], mu1);
+    decasteljau<N, T>(c[1], mu2);
+    const T* cc = &c[0][0];
+    const T gR = (T)g.x, gS = (T)g.y;
+    if (ALG1) {
+      const T D1 = (T)D1d, D2 = (T)D2d;
+      if (D1d == D2d) {
+        // equal coefficients: Algorithm 1 reduces exactly to D (U1 - U2) c
+        T gg[2 * Nfp];
+        matvec_sel<kBoth, 2 * Nfp, 2 * Np, T>(op + L.udr, cc, gg);
+#pragma unroll
+        for (int j = 0; j < Nfp; ++j) F[j] = D1 * (gR * gg[j] + gS * gg[Nfp + j]);
+      } else {
+        T gg[4 * Nfp];
+        matvec_sel<kBoth, 4 * Nfp, 2 * Np, T>(op + L.u1r, cc, gg);
+#pragma unroll
+        for (int j = 0; j < Nfp; ++j)
+          F[j] = D1 * (gR * gg[j] + gS * gg[Nfp + j]) - D2 * (gR * gg[2 * Nfp + j] + gS * gg[3 * Nfp + j]);
+      }
+    } else {
+      const T D = (T)m.Dfield[field];
+      T gg[2 * Nfp];
+      matvec_sel<kBoth, 2 * Nfp, 2 * Np, T>(op + L.kr, cc, gg);
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gg[j] + gS * gg[Nfp + j]);
+    }
+  } else {
+    const int64_t b = e - m.E_int;
+    const int kb = m.bk[b];
+    const double2 g = m.bgam[b], mu = m.bmu[b];
+    if (m.conv) vn = m.vn[e];
+    const int k = kb & 0x3fffffff, fa = (int)((unsigned)kb >> 30);
+    T v[Np];
+#pragma unroll
+    for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
+    const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
+    T t[Np], c[Np];
+    rotate_to_face<N, T>(v, fa, t, tr1);
+    matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c);
+    decasteljau<N, T>(c, mu);
+    const T gR = (T)g.x, gS = (T)g.y;
+    T gb[2 * Nfp];
+    matvec_sel<kBoth, 2 * Nfp, Np, T>(op + (ALG1 ? L.ubr : L.kbr), c, gb);
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gb[j] + gS * gb[Nfp + j]);
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
+  }
+  if (m.conv) {
+    // upwind flux f* = max(n.v,0) u- + min(n.v,0) u+, subtracted from the
+    // diffusive flux; n.v is linear along the edge (affine velocity)
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T tau = op[L.tau + j];
+      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
+      const T up = tr2[N - j];
+      const T fs = (vnj > (T)0) ? vnj * tr1[j] : vnj * up;
+      F[j] -= fs;
+    }
+  }
+  T* out = flux + ((int64_t)field * E + e) * Nfp;
+#pragma unroll
+  for (int j = 0; j < Nfp; ++j) out[j] = F[j];
+}
+
+}  // namespace ardg

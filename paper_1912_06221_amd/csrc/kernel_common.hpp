@@ -68,6 +68,53 @@ template <> __device__ inline cptr<float> opbase<float>(const DevMesh& m) {
   return (cptr<float>)uniform_ptr(m.ops32);
 }
 
+// Affine map of a triangle (v1, v2, v3) onto the reference triangle: x_r =
+// (v2 - v1) / 2, x_s = (v3 - v1) / 2, J = x_r y_s - x_s y_r, and the inverse
+// metric r_x = y_s / J, r_y = -x_s / J, s_x = -y_r / J, s_y = x_r / J
+// (section on the mapping of a triangle to the reference element).
+struct ElemGeom {
+  double xr, yr, xs, ys, iJ, rx, ry, sx, sy;
+};
+
+__device__ inline ElemGeom elem_geom(double2 p1, double2 p2, double2 p3) {
+  ElemGeom g;
+  g.xr = 0.5 * (p2.x - p1.x);
+  g.yr = 0.5 * (p2.y - p1.y);
+  g.xs = 0.5 * (p3.x - p1.x);
+  g.ys = 0.5 * (p3.y - p1.y);
+  g.iJ = 1.0 / (g.xr * g.ys - g.xs * g.yr);
+  g.rx = g.ys * g.iJ;
+  g.ry = -g.xs * g.iJ;
+  g.sx = -g.yr * g.iJ;
+  g.sy = g.xr * g.iJ;
+  return g;
+}
+
+// Outward normal of face f times its surface factor sJ_f = |edge| / 2:
+// (t_y, -t_x) / 2 for the counter-clockwise edge vector t (no square root).
+__device__ inline double2 face_sjn(const ElemGeom& g, int f) {
+  if (f == 0) return make_double2(g.yr, -g.xr);                   // t = v2 - v1 = 2 x_r
+  if (f == 1) return make_double2(g.ys - g.yr, g.xr - g.xs);      // t = v3 - v2
+  return make_double2(-g.ys, g.xs);                               // t = v1 - v3 = -2 x_s
+}
+
+// Affine velocity v = (c0 + c2 x + c3 y, c1 + c4 x + c5 y) on one element as
+// a function of the reference coordinates: v = v1 + (r + 1) v_r + (s + 1) v_s.
+struct ElemVel {
+  double x1, y1, xr, yr, xs, ys;
+};
+
+__device__ inline ElemVel elem_vel(const double* c, double2 p1, const ElemGeom& g) {
+  ElemVel v;
+  v.x1 = c[0] + c[2] * p1.x + c[3] * p1.y;
+  v.y1 = c[1] + c[4] * p1.x + c[5] * p1.y;
+  v.xr = c[2] * g.xr + c[3] * g.yr;
+  v.yr = c[4] * g.xr + c[5] * g.yr;
+  v.xs = c[2] * g.xs + c[3] * g.ys;
+  v.ys = c[4] * g.xs + c[5] * g.ys;
+  return v;
+}
+
 // For N <= 4 the update operands are prefetched into registers before the
 // compute, asking for two waves per SIMD; higher orders keep the registers
 // for the element compute and load the operands in the update.
@@ -76,59 +123,79 @@ template <int N> struct ElemTune {
   static constexpr int waves = N <= 4 ? 2 : 1;
 };
 
-// One tile = TILE consecutive elements handled by TILE threads.  Their nodal
+// One tile = TILE consecutive elements handled by NT threads.  Their nodal
 // values form one contiguous chunk of the [F][K][Np] array: tile_begin stages
 // it through LDS (sh, TILE*Np entries) with coalesced loads and fetches the
 // operands of the Runge-Kutta update with the same coalesced pattern; the
 // element compute replaces sh's values by du/dt; tile_end runs the update over
-// the chunk's degrees of freedom with coalesced global traffic.
-template <int Np>
+// the chunk's degrees of freedom with coalesced global traffic.  Each thread
+// owns Q = ceil(TILE*Np/NT) of the chunk's entries, i = thread + q*NT.
+template <int Q>
 struct TileIO {
-  double Up[Np], Ap[Np];
+  double Up[Q], Ap[Q];
   int nel, ndof;
   int64_t base;
   bool rk, need_acc;
 };
 
-template <int N, typename T, int TILE>
+template <int N, int TILE, int NT>
+struct TileShape {
+  static constexpr int Np = (N + 1) * (N + 2) / 2;
+  static constexpr int Q = (TILE * Np + NT - 1) / NT;
+};
+
+template <int N, typename T, int TILE, int NT = TILE>
 __device__ inline void tile_begin(const DevMesh& m, int64_t k0, int field, const T* __restrict__ vin,
-                                  const Epilogue& epi, T* sh, TileIO<(N + 1) * (N + 2) / 2>& io,
+                                  const Epilogue& epi, T* sh, TileIO<TileShape<N, TILE, NT>::Q>& io,
                                   bool prefetch) {
-  constexpr int Np = (N + 1) * (N + 2) / 2;
+  constexpr int Np = TileShape<N, TILE, NT>::Np, Q = TileShape<N, TILE, NT>::Q;
   const int t = threadIdx.x;
   io.nel = (int)((m.K - k0) < TILE ? (m.K - k0) : TILE);
   io.ndof = io.nel * Np;
   io.base = ((int64_t)field * m.K + k0) * Np;
-#pragma unroll
-  for (int q = 0; q < Np; ++q) {
-    const int i = t + q * TILE;
-    if (i < io.ndof) sh[i] = vin[io.base + i];
-  }
   io.rk = epi.kind != EPI_RHS;
   io.need_acc = io.rk && epi.stage != 0;
+  // Loads are issued unconditionally from clamped (in-tile) indices and masked
+  // afterwards: a load under a branch is followed by a wait at the branch's
+  // end, which would serialise the round trips.
+  T x[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * NT;
+    x[q] = vin[io.base + (i < io.ndof ? i : 0)];
+  }
   if (prefetch && io.rk) {
     const double* U = epi.u + io.base;
-    const double* A = epi.acc + io.base;
+    const double* A = io.need_acc ? epi.acc + io.base : epi.u + io.base;
 #pragma unroll
-    for (int q = 0; q < Np; ++q) {
-      const int i = t + q * TILE;
-      io.Up[q] = (i < io.ndof) ? U[i] : 0.0;
-      io.Ap[q] = (io.need_acc && i < io.ndof) ? A[i] : 0.0;
+    for (int q = 0; q < Q; ++q) {
+      const int i = t + q * NT;
+      const int ic = i < io.ndof ? i : 0;
+      io.Up[q] = U[ic];
+      io.Ap[q] = A[ic];
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (!io.need_acc) io.Ap[q] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * NT;
+    if (i < io.ndof) sh[i] = x[q];
   }
 }
 
-template <int N, typename T, int TILE>
-__device__ inline void tile_end(const Epilogue& epi, const T* sh, TileIO<(N + 1) * (N + 2) / 2>& io,
+template <int N, typename T, int TILE, int NT = TILE>
+__device__ inline void tile_end(const Epilogue& epi, const T* sh, TileIO<TileShape<N, TILE, NT>::Q>& io,
                                 bool prefetched) {
-  constexpr int Np = (N + 1) * (N + 2) / 2;
+  constexpr int Q = TileShape<N, TILE, NT>::Q;
   const int t = threadIdx.x;
   const int ndof = io.ndof;
   if (!io.rk) {
     T* o = (T*)epi.rhs_out + io.base;
 #pragma unroll
-    for (int q = 0; q < Np; ++q) {
-      const int i = t + q * TILE;
+    for (int q = 0; q < Q; ++q) {
+      const int i = t + q * NT;
       if (i < ndof) o[i] = sh[i];
     }
     return;
@@ -138,20 +205,25 @@ __device__ inline void tile_end(const Epilogue& epi, const T* sh, TileIO<(N + 1)
   T* vn = epi.vnext ? (T*)epi.vnext + io.base : nullptr;
   const double dt = epi.dt;
   if (!prefetched) {
+    const double* Asrc = io.need_acc ? A : U;
 #pragma unroll
-    for (int q = 0; q < Np; ++q) {
-      const int i = t + q * TILE;
-      io.Up[q] = (i < ndof) ? U[i] : 0.0;
-      io.Ap[q] = (io.need_acc && i < ndof) ? A[i] : 0.0;
+    for (int q = 0; q < Q; ++q) {
+      const int i = t + q * NT;
+      const int ic = i < ndof ? i : 0;
+      io.Up[q] = U[ic];
+      io.Ap[q] = Asrc[ic];
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (!io.need_acc) io.Ap[q] = 0.0;
   }
   if (epi.kind == EPI_RK4) {
     const int s = epi.stage;
     if (s < 3) {
       const double c = (s < 2) ? 0.5 * dt : dt;
 #pragma unroll
-      for (int q = 0; q < Np; ++q) {
-        const int i = t + q * TILE;
+      for (int q = 0; q < Q; ++q) {
+        const int i = t + q * NT;
         if (i < ndof) {
           const double r = (double)sh[i];
           A[i] = (s == 0) ? r : io.Ap[q] + 2.0 * r;
@@ -160,8 +232,8 @@ __device__ inline void tile_end(const Epilogue& epi, const T* sh, TileIO<(N + 1)
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < Np; ++q) {
-        const int i = t + q * TILE;
+      for (int q = 0; q < Q; ++q) {
+        const int i = t + q * NT;
         if (i < ndof) {
           const double un = io.Up[q] + dt / 6.0 * (io.Ap[q] + (double)sh[i]);
           U[i] = un;
@@ -171,8 +243,8 @@ __device__ inline void tile_end(const Epilogue& epi, const T* sh, TileIO<(N + 1)
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < Np; ++q) {
-      const int i = t + q * TILE;
+    for (int q = 0; q < Q; ++q) {
+      const int i = t + q * NT;
       if (i < ndof) {
         const double r = dt * (double)sh[i];
         const double res = (epi.stage == 0) ? r : epi.a * io.Ap[q] + r;

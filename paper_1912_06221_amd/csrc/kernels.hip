@@ -33,138 +33,9 @@
 
 #include "device.hpp"
 #include "kernel_common.hpp"
+#include "edge_common.hpp"
 
 namespace ardg {
-template <int ROWS, int COLS, typename T>
-__device__ inline void matvec(cptr<T> A0, const T* x, T* y);
-
-// Load one element, rotate so that face f is the hypotenuse, convert to
-// Bernstein coefficients and subdivide at the apex (mu = weights of w2, w3).
-// trace[j] receives the element's values on face f, counter-clockwise.
-template <int N, typename T>
-__device__ inline void subtriangle_coeffs(const T* __restrict__ ue, int f, double2 mu,
-                                          cptr<T> n2b, T* c, T* trace) {
-  constexpr int Np = (N + 1) * (N + 2) / 2;
-  T v[Np];
-#pragma unroll
-  for (int n = 0; n < Np; ++n) v[n] = ue[n];
-  T t[Np];
-#pragma unroll
-  for (int j = 0; j <= N; ++j)
-#pragma unroll
-    for (int i = 0; i <= N - j; ++i) {
-      const T a0 = v[lat(N, j, N - i - j)];   // face (v1,v2): w = (v3, v1, v2)
-      const T a1 = v[lat(N, i, j)];           // face (v2,v3): identity
-      const T a2 = v[lat(N, N - i - j, i)];   // face (v3,v1): w = (v2, v3, v1)
-      t[lat(N, i, j)] = (f == 0) ? a0 : ((f == 1) ? a1 : a2);
-    }
-#pragma unroll
-  for (int j = 0; j <= N; ++j) trace[j] = t[lat(N, N - j, j)];
-  matvec<Np, Np, T>(n2b, t, c);
-  const T m2 = (T)mu.x, m3 = (T)mu.y;
-  const T m1 = (T)(1.0 - mu.x - mu.y);
-#pragma unroll
-  for (int n = N; n >= 1; --n)
-#pragma unroll
-    for (int j = 0; j <= n - 1; ++j)
-#pragma unroll
-      for (int i = 0; i <= n - 1 - j; ++i)
-        c[lat(N, i, j)] = m1 * c[lat(N, i, j)] + m2 * c[lat(N, i + 1, j)] + m3 * c[lat(N, i, j + 1)];
-}
-
-// y = A x for a constant row-major ROWS x COLS operator A.  Each row's entries
-// are wave-uniform scalar loads feeding scalar-operand FMAs; the row fence and
-// the fresh pointer keep one row in flight at a time (without them the whole
-// operator is hoisted into SGPRs and spilled).
-template <int ROWS, int COLS, typename T>
-__device__ inline void matvec(cptr<T> A0, const T* x, T* y) {
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r) {
-    row_fence();
-    const cptr<T> A = fresh(A0);
-    T s = A[r * COLS] * x[0];
-#pragma unroll
-    for (int q = 1; q < COLS; ++q) s = fma(A[r * COLS + q], x[q], s);
-    y[r] = s;
-  }
-}
-
-template <int N, typename T, bool ALG1>
-__device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
-                                 const T* __restrict__ u, T* __restrict__ flux) {
-  constexpr OpLayout L(N);
-  constexpr int Np = L.Np, Nfp = L.Nfp;
-  const int64_t E = m.E_int + m.E_bdy;
-  const T* uf = u + (int64_t)field * m.K * Np;
-  T F[Nfp];
-  T tr1[Nfp], tr2[Nfp];
-  double2 vn = make_double2(0.0, 0.0);
-  if (e < m.E_int) {
-    const int2 ef = m.ef[e];
-    const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
-    const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
-    const double2 g = m.gam[e];
-    T c[2 * Np];
-    subtriangle_coeffs<N, T>(uf + (int64_t)k1 * Np, fa, m.mu1[e], op + L.n2b, c, tr1);
-    subtriangle_coeffs<N, T>(uf + (int64_t)k2 * Np, fb, m.mu2[e], op + L.n2b, c + Np, tr2);
-    const T gR = (T)g.x, gS = (T)g.y;
-    if (ALG1) {
-      const double D1d = m.Delem[k1], D2d = m.Delem[k2];
-      const T D1 = (T)D1d, D2 = (T)D2d;
-      if (D1d == D2d) {
-        // equal coefficients: Algorithm 1 reduces exactly to D (U1 - U2) c
-        T g[2 * Nfp];
-        matvec<2 * Nfp, 2 * Np, T>(op + L.udr, c, g);
-#pragma unroll
-        for (int j = 0; j < Nfp; ++j) F[j] = D1 * (gR * g[j] + gS * g[Nfp + j]);
-      } else {
-        T g[4 * Nfp];
-        matvec<4 * Nfp, 2 * Np, T>(op + L.u1r, c, g);
-#pragma unroll
-        for (int j = 0; j < Nfp; ++j)
-          F[j] = D1 * (gR * g[j] + gS * g[Nfp + j]) - D2 * (gR * g[2 * Nfp + j] + gS * g[3 * Nfp + j]);
-      }
-    } else {
-      const T D = (T)m.Dfield[field];
-      T g[2 * Nfp];
-      matvec<2 * Nfp, 2 * Np, T>(op + L.kr, c, g);
-#pragma unroll
-      for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * g[j] + gS * g[Nfp + j]);
-    }
-    if (m.conv) vn = m.vn[e];
-  } else {
-    const int64_t b = e - m.E_int;
-    const int kb = m.bk[b];
-    const int k = kb & 0x3fffffff, fa = (int)((unsigned)kb >> 30);
-    const double2 g = m.bgam[b];
-    T c[Np];
-    subtriangle_coeffs<N, T>(uf + (int64_t)k * Np, fa, m.bmu[b], op + L.n2b, c, tr1);
-    const T gR = (T)g.x, gS = (T)g.y;
-    const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
-    T gb[2 * Nfp];
-    matvec<2 * Nfp, Np, T>(op + (ALG1 ? L.ubr : L.kbr), c, gb);
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gb[j] + gS * gb[Nfp + j]);
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
-    if (m.conv) vn = m.vn[e];
-  }
-  if (m.conv) {
-    // upwind flux f* = max(n.v,0) u- + min(n.v,0) u+, subtracted from the
-    // diffusive flux; n.v is linear along the edge (affine velocity)
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) {
-      const T tau = op[L.tau + j];
-      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
-      const T up = tr2[N - j];
-      const T fs = (vnj > (T)0) ? vnj * tr1[j] : vnj * up;
-      F[j] -= fs;
-    }
-  }
-  T* out = flux + ((int64_t)field * E + e) * Nfp;
-#pragma unroll
-  for (int j = 0; j < Nfp; ++j) out[j] = F[j];
-}
 
 template <int N, typename T, bool ALG1>
 __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __restrict__ u,
@@ -206,18 +77,22 @@ __device__ inline void load_elem_in(const DevMesh& m, int64_t k, int field,
   }
 }
 
-// du/dt of one element from its nodal values u (registers).
+// du/dt of one element from its nodal values u (registers):
+//   q = (r_x Dr u + s_x Ds u, r_y Dr u + s_y Ds u)
+//   w_r = D (r_x q_x + r_y q_y) - v_r u,  w_s = D (s_x q_x + s_y q_y) - v_s u
+//   rhs = [Dr Ds] [w_r; w_s] + LIFT [(1/J) (G_f - D (sJ n)_f.q + (sJ n)_f.v u)]_f
+// (strong form; convection folded into the volume pass through the
+// contravariant velocity v_r = r_x v_x + r_y v_y, v_s = s_x v_x + s_y v_y; the
+// face fluxes G_f arrive multiplied by sJ_f).
 template <int N, typename T, bool CONV>
 __device__ inline void element_rhs(const DevMesh& m, cptr<T> op, const T* u,
                                    const ElemIn<N + 1, T>& in, T* rhs) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
-  // affine factors of this element (eqs. mapping_tri_diff, triangle_jacobian_a/b)
-  const double2 p1 = in.p1, p2 = in.p2, p3 = in.p3;
-  const double xr = 0.5 * (p2.x - p1.x), yr = 0.5 * (p2.y - p1.y);
-  const double xs = 0.5 * (p3.x - p1.x), ys = 0.5 * (p3.y - p1.y);
-  const double J = xr * ys - xs * yr;
-  const T rx = (T)(ys / J), ry = (T)(-xs / J), sx = (T)(-yr / J), sy = (T)(xr / J);
+  const ElemGeom gm = elem_geom(in.p1, in.p2, in.p3);
+  const T rx = (T)gm.rx, ry = (T)gm.ry, sx = (T)gm.sx, sy = (T)gm.sy;
+  ElemVel ev = {};
+  if (CONV) ev = elem_vel(m.vel, in.p1, gm);
 
   T qx[Np], qy[Np];
   {
@@ -230,48 +105,42 @@ __device__ inline void element_rhs(const DevMesh& m, cptr<T> op, const T* u,
     }
   }
   const T D = (T)in.D;
-  {
-    T w[2 * Np];
-#pragma unroll
-    for (int i = 0; i < Np; ++i) {
-      w[i] = rx * qx[i] + ry * qy[i];
-      w[Np + i] = sx * qx[i] + sy * qy[i];
-    }
-    T div[Np];
-    matvec<Np, 2 * Np, T>(op + L.drsh, w, div);        // [Dr Ds] [wr; ws]
-#pragma unroll
-    for (int i = 0; i < Np; ++i) rhs[i] = D * div[i];
-  }
-
   T vx[Np], vy[Np];
   if (CONV) {
 #pragma unroll
     for (int n = 0; n < Np; ++n) {
-      const double r = (double)op[L.nr + n], s = (double)op[L.ns + n];
-      const double x = 0.5 * (-(r + s) * p1.x + (r + 1.0) * p2.x + (s + 1.0) * p3.x);
-      const double y = 0.5 * (-(r + s) * p1.y + (r + 1.0) * p2.y + (s + 1.0) * p3.y);
-      vx[n] = (T)(m.vel[0] + m.vel[2] * x + m.vel[3] * y);
-      vy[n] = (T)(m.vel[1] + m.vel[4] * x + m.vel[5] * y);
+      const T r1 = op[L.nr + n] + T(1), s1 = op[L.ns + n] + T(1);
+      vx[n] = (T)ev.x1 + r1 * (T)ev.xr + s1 * (T)ev.xs;
+      vy[n] = (T)ev.y1 + r1 * (T)ev.yr + s1 * (T)ev.ys;
     }
   }
+  {
+    T w[2 * Np];
+#pragma unroll
+    for (int i = 0; i < Np; ++i) {
+      w[i] = D * (rx * qx[i] + ry * qy[i]);
+      w[Np + i] = D * (sx * qx[i] + sy * qy[i]);
+      if (CONV) {
+        w[i] -= (rx * vx[i] + ry * vy[i]) * u[i];
+        w[Np + i] -= (sx * vx[i] + sy * vy[i]) * u[i];
+      }
+    }
+    matvec<Np, 2 * Np, T>(op + L.drsh, w, rhs);        // [Dr Ds] [w_r; w_s]
+  }
 
-  // surface terms: (J_f / J) LIFT_f (F_f - D n.q + [n.v u-]), one LIFT pass
+  // surface terms, one LIFT pass
   T jump[3 * Nfp];
+  const T iJ = (T)gm.iJ;
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    const double2 a = (f == 0) ? p1 : (f == 1 ? p2 : p3);
-    const double2 b = (f == 0) ? p2 : (f == 1 ? p3 : p1);
-    const double tx = b.x - a.x, ty = b.y - a.y;
-    const double len = sqrt(tx * tx + ty * ty);
-    const T nx = (T)(ty / len), ny = (T)(-tx / len);
-    const T scale = (T)(0.5 * len / J);
+    const double2 sn = face_sjn(gm, f);
+    const T nx = (T)sn.x, ny = (T)sn.y;
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
-      const T G = in.fv[f][j];
       const int nd = fnode(N, f, j);
-      T jv = G - D * (nx * qx[nd] + ny * qy[nd]);
+      T jv = in.fv[f][j] - D * (nx * qx[nd] + ny * qy[nd]);
       if (CONV) jv += (nx * vx[nd] + ny * vy[nd]) * u[nd];
-      jump[f * Nfp + j] = scale * jv;
+      jump[f * Nfp + j] = iJ * jv;
     }
   }
   {
@@ -279,22 +148,6 @@ __device__ inline void element_rhs(const DevMesh& m, cptr<T> op, const T* u,
     matvec<Np, 3 * Nfp, T>(op + L.lift, jump, lifted);
 #pragma unroll
     for (int i = 0; i < Np; ++i) rhs[i] += lifted[i];
-  }
-
-  if (CONV) {
-    // -(d/dx (vx u) + d/dy (vy u)), nodal collocation of the flux vector
-    T fx[Np], fy[Np];
-#pragma unroll
-    for (int n = 0; n < Np; ++n) {
-      fx[n] = vx[n] * u[n];
-      fy[n] = vy[n] * u[n];
-    }
-    T dfx[2 * Np], dfy[2 * Np];
-    matvec<2 * Np, Np, T>(op + L.dr, fx, dfx);
-    matvec<2 * Np, Np, T>(op + L.dr, fy, dfy);
-#pragma unroll
-    for (int i = 0; i < Np; ++i)
-      rhs[i] -= rx * dfx[i] + sx * dfx[Np + i] + ry * dfy[i] + sy * dfy[Np + i];
   }
 }
 
@@ -306,7 +159,7 @@ __device__ inline void element_tile(const DevMesh& m, cptr<T> op, int64_t k0, in
   constexpr int Np = (N + 1) * (N + 2) / 2;
   constexpr bool kPre = ElemTune<N>::prefetch;
   const int t = threadIdx.x;
-  TileIO<Np> io;
+  TileIO<TileShape<N, TILE, TILE>::Q> io;
   tile_begin<N, T, TILE>(m, k0, field, vin, epi, sh, io, kPre);
   ElemIn<N + 1, T> in;
   if (t < io.nel) load_elem_in<N, T>(m, k0 + t, field, flux, in);
@@ -457,6 +310,7 @@ hipError_t elem_dispatch(const DevMesh& m, int nf, const void* vin, const void* 
 
 hipError_t launch_edge_flux(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
                             hipStream_t st) {
+  if (m.edge_mfma) return launch_edge_mfma(m, fp64, nfields, u, flux, st);
   return fp64 ? edge_dispatch<double>(m, nfields, u, flux, st)
               : edge_dispatch<float>(m, nfields, u, flux, st);
 }

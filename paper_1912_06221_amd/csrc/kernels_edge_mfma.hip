@@ -1,0 +1,291 @@
+// Edge kernel on the matrix cores (gfx950 MFMA, 16x16 tiles).
+//
+// One wave takes 64 consecutive interior edges, as four sub-tiles of 16 edges
+// (the 16 columns of the MFMA tiles).  Per side of the edges:
+//   1. gather + rotate: the B fragments are read straight from the stage
+//      vector, the face's node reordering (section "Reordering nodes in the
+//      reference domain") applied as an index remap;
+//   2. nodal -> Bernstein on I: (Np x Np) x (Np x 16) products with the
+//      constant conversion matrix held as A fragments;
+//   3. projection onto the sub-triangle (eq. totalProjection): de Casteljau
+//      subdivision at the edge's own apex weights, one lane per edge, on the
+//      coefficients staged in LDS;
+//   4. the constant reconstruction-gradient operator (least squares on the
+//      enclosed parallelogram, d/dR and d/dS on the diagonal nodes) applied
+//      to this side's half of the coefficient vector, accumulated over the
+//      two sides on the matrix cores.
+// The operator rows are laid out so that the values one flux node needs
+// (d/dR and d/dS, and for Algorithm 1 the D1 and D2 blocks) arrive in the
+// same lane; the flux of the 64 edges is formed there, staged in LDS and
+// written as one contiguous block.  Boundary faces (mirror ghost) run the
+// vector-unit body in the same launch, one lane per face.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "edge_common.hpp"
+#include "kernel_common.hpp"
+#include "mfma.hpp"
+
+namespace ardg {
+
+constexpr int kEdgeTile = 64;   // interior edges per block (one wave)
+
+// Operator forms of step 4.
+//   PAIR_K : constant D, rows (d/dR, d/dS) of the reconstruction gradient
+//   PAIR_UD: Algorithm 1 with D1 == D2 on every edge of the wave: U1 - U2
+//   QUAD   : Algorithm 1, rows (U1R, U1S, U2R, U2S)
+enum EdgeForm { PAIR_K = 0, PAIR_UD = 1, QUAD = 2 };
+
+template <int N, typename T, int FORM, bool CONV>
+__device__ inline void edge_tile_mfma(const DevMesh& m, const T* __restrict__ opg, int field,
+                                      const T* __restrict__ uf, T* __restrict__ out, int nval,
+                                      int k1, int fa, int k2, int fb, double2 mu1, double2 mu2,
+                                      double2 gam, double D1, double D2, T* cb, T* fl,
+                                      const int* rot) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp, K2 = 2 * Np;
+  constexpr int MT = (Np + 15) / 16;                       // row tiles of the conversion
+  constexpr int KC = (Np + 3) / 4;                         // k steps over one side's nodes
+  constexpr int RPT = FORM == QUAD ? 4 : 8;                // flux nodes per row tile
+  constexpr int MG = (Nfp + RPT - 1) / RPT;                // row tiles of step 4
+  constexpr int base = FORM == PAIR_K ? L.kr : (FORM == PAIR_UD ? L.udr : L.u1r);
+  using M = Mma<T>;
+  typedef typename M::acc acc_t;
+  const int l = threadIdx.x, col = l & 15, grp = l >> 4;
+  const bool valid = l < nval;
+
+  // conversion matrix as A fragments: row 16 mt + col, column 4 c + grp
+  T aN[MT][KC];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const int i = 16 * mt + col, k = 4 * c + grp;
+      aN[mt][c] = (i < Np && k < Np) ? opg[L.n2b + i * Np + k] : T(0);
+    }
+  // step-4 operator row held by this lane in tile mt: MFMA row `col`
+  const int gi = M::grp_of(col), ri = M::reg_of(col);
+
+  acc_t g[4][MG];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int mt = 0; mt < MG; ++mt) g[t][mt] = M::zero();
+
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int kl = s ? k2 : k1, fl_ = s ? fb : fa;
+    // 1 + 2: gather, rotate, convert to Bernstein coefficients
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int el = 16 * t + col;
+      const int kk = __shfl(kl, el), ff = __shfl(fl_, el);
+      const bool ok = el < nval;
+      const T* ue = uf + (int64_t)kk * Np;
+      T bu[KC];
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const int n = 4 * c + grp;
+        T v = T(0);
+        if (ok && n < Np) v = ue[ff == 1 ? n : rot[(ff >> 1) * Np + n]];
+        bu[c] = v;
+      }
+      acc_t b[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        b[mt] = M::zero();
+#pragma unroll
+        for (int c = 0; c < KC; ++c) b[mt] = M::mma(aN[mt][c], bu[c], b[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * mt + M::row(grp, r);
+          if (row < Np) cb[row * kEdgeTile + el] = b[mt][r];
+        }
+    }
+    __syncthreads();
+    // 3: subdivision at this edge's apex, one lane per edge
+    if (valid) {
+      T c[Np];
+#pragma unroll
+      for (int n = 0; n < Np; ++n) c[n] = cb[n * kEdgeTile + l];
+      decasteljau<N, T>(c, s ? mu2 : mu1);
+#pragma unroll
+      for (int n = 0; n < Np; ++n) cb[n * kEdgeTile + l] = c[n];
+    }
+    __syncthreads();
+    // 4: this side's columns of the step-4 operator
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const int k = 4 * c + grp;
+      T a[MG];
+#pragma unroll
+      for (int mt = 0; mt < MG; ++mt) {
+        int jj, comp;
+        if (FORM == QUAD) {
+          jj = 4 * mt + gi;
+          comp = ri;
+        } else {
+          jj = 8 * mt + 2 * gi + (ri >> 1);
+          comp = ri & 1;
+        }
+        a[mt] = (jj < Nfp && k < Np) ? opg[base + (comp * Nfp + jj) * K2 + s * Np + k] : T(0);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const T bb = (k < Np) ? cb[k * kEdgeTile + 16 * t + col] : T(0);
+#pragma unroll
+        for (int mt = 0; mt < MG; ++mt) g[t][mt] = M::mma(a[mt], bb, g[t][mt]);
+      }
+    }
+    __syncthreads();   // cb is refilled by the other side
+  }
+
+  // flux at the diagonal nodes; lane group grp holds nodes of edge 16 t + col
+  const T Dc = (T)m.Dfield[field];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int el = 16 * t + col;
+    const bool ok = el < nval;
+    const T gR = (T)__shfl(gam.x, el), gS = (T)__shfl(gam.y, el);
+    const T d1 = (T)__shfl(D1, el), d2 = (T)__shfl(D2, el);
+#pragma unroll
+    for (int mt = 0; mt < MG; ++mt) {
+      if (FORM == QUAD) {
+        const int jj = 4 * mt + grp;
+        if (ok && jj < Nfp) {
+          T F = d1 * (gR * g[t][mt][0] + gS * g[t][mt][1]) - d2 * (gR * g[t][mt][2] + gS * g[t][mt][3]);
+          if (CONV) F -= fl[el * Nfp + jj];
+          fl[el * Nfp + jj] = F;
+        }
+      } else {
+        const T D = FORM == PAIR_K ? Dc : d1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int jj = 8 * mt + 2 * grp + h;
+          if (ok && jj < Nfp) {
+            T F = D * (gR * g[t][mt][2 * h] + gS * g[t][mt][2 * h + 1]);
+            if (CONV) F -= fl[el * Nfp + jj];
+            fl[el * Nfp + jj] = F;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Nfp; ++q) {
+    const int i = l + q * kEdgeTile;
+    if (i < nval * Nfp) out[i] = fl[i];
+  }
+}
+
+template <int N, typename T, bool ALG1, bool CONV>
+__global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m, const T* __restrict__ u,
+                                                              T* __restrict__ flux, int nb_int) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp;
+  __shared__ T cb[Np * kEdgeTile];
+  __shared__ T fl[kEdgeTile * Nfp];
+  __shared__ int rot[2 * Np];
+  const int l = threadIdx.x;
+  const int field = blockIdx.y;
+  const int64_t E = m.E_int + m.E_bdy;
+  const int b = blockIdx.x;
+  if (b >= nb_int) {
+    // boundary faces: mirror-ghost operator on the vector unit, one lane per face
+    const int64_t e = m.E_int + (int64_t)(b - nb_int) * kEdgeTile + l;
+    if (e < E) edge_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
+    return;
+  }
+  const int64_t e0 = xcd_block(b, nb_int) * kEdgeTile;
+  const int nval = (int)((m.E_int - e0) < kEdgeTile ? (m.E_int - e0) : kEdgeTile);
+  // rotated lattice node -> element node for faces 0 and 2 (face 1: identity)
+  for (int n = l; n < Np; n += kEdgeTile) {
+    int j = 0;
+    while (lat(N, 0, j + 1) <= n) ++j;
+    const int i = n - lat(N, 0, j);
+    rot[n] = lat(N, j, N - i - j);
+    rot[Np + n] = lat(N, N - i - j, i);
+  }
+  const bool valid = l < nval;
+  const int64_t e = e0 + (valid ? l : 0);
+  const int2 ef = m.ef[e];
+  const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
+  const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
+  const double2 mu1 = m.mu1[e], mu2 = m.mu2[e], gam = m.gam[e];
+  const double D1 = ALG1 ? m.Delem[k1] : 0.0, D2 = ALG1 ? m.Delem[k2] : 0.0;
+  const T* uf = u + (int64_t)field * m.K * Np;
+  const T* opg = (const T*)(const void*)opbase<T>(m);
+  if (CONV && valid) {
+    // upwind flux f* = max(n.v,0) u- + min(n.v,0) u+ at the face nodes,
+    // subtracted from the diffusive flux; n.v is linear along the edge
+    const double2 vn = m.vn[e];
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T tau = opg[L.tau + j];
+      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
+      const T um = uf[(int64_t)k1 * Np + fnode(N, fa, j)];
+      const T up = uf[(int64_t)k2 * Np + fnode(N, fb, N - j)];
+      fl[l * Nfp + j] = (vnj > (T)0) ? vnj * um : vnj * up;
+    }
+  }
+  __syncthreads();
+  T* out = flux + ((int64_t)field * E + e0) * Nfp;
+  if (!ALG1) {
+    edge_tile_mfma<N, T, PAIR_K, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+                                       D1, D2, cb, fl, rot);
+  } else if (__ballot(valid && D1 != D2) == 0) {
+    edge_tile_mfma<N, T, PAIR_UD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+                                        D1, D2, cb, fl, rot);
+  } else {
+    edge_tile_mfma<N, T, QUAD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+                                     D1, D2, cb, fl, rot);
+  }
+}
+
+template <int N, typename T>
+hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
+  const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
+  const int64_t nbb = (m.E_bdy + kEdgeTile - 1) / kEdgeTile;
+  if (nbi + nbb == 0) return hipSuccess;
+  dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
+  const T* uu = (const T*)u;
+  T* ff = (T*)flux;
+  const int ni = (int)nbi;
+  if (m.alg1) {
+    if (m.conv)
+      hipLaunchKernelGGL((edge_mfma_kernel<N, T, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+    else
+      hipLaunchKernelGGL((edge_mfma_kernel<N, T, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+  } else {
+    if (m.conv)
+      hipLaunchKernelGGL((edge_mfma_kernel<N, T, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+    else
+      hipLaunchKernelGGL((edge_mfma_kernel<N, T, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t edge_mfma_dispatch(const DevMesh& m, int nf, const void* u, void* flux, hipStream_t st) {
+  switch (m.N) {
+    case 1: return edge_mfma_t<1, T>(m, nf, u, flux, st);
+    case 2: return edge_mfma_t<2, T>(m, nf, u, flux, st);
+    case 3: return edge_mfma_t<3, T>(m, nf, u, flux, st);
+    case 4: return edge_mfma_t<4, T>(m, nf, u, flux, st);
+    case 5: return edge_mfma_t<5, T>(m, nf, u, flux, st);
+    case 6: return edge_mfma_t<6, T>(m, nf, u, flux, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_edge_mfma(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
+                            hipStream_t st) {
+  return fp64 ? edge_mfma_dispatch<double>(m, nfields, u, flux, st)
+              : edge_mfma_dispatch<float>(m, nfields, u, flux, st);
+}
+
+}  // namespace ardg

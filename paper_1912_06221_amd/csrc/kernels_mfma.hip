@@ -4,63 +4,40 @@
 // Dr, Ds (Np x Np) and LIFT (Np x 3 Nfp) -- act on every element's vector, so
 // for 16 elements at a time they are dense products (Np x Np) x (Np x 16) on
 // the matrix cores.  The operators stay resident in registers as MFMA A
-// fragments for the whole kernel (no per-entry operand loads); the element
-// data enters as B fragments and comes out in the accumulator layout, and the
-// conversions between the two layouts go through LDS.
+// fragments (no per-entry operand loads); the element data enters as B
+// fragments and comes out in the accumulator layout, and the conversions
+// between the two layouts go through LDS.
 //
-// Fragment layouts of the 16x16xK instructions used here (K per instruction
-// = 4, one value per lane): lane l supplies A[row = l % 16][k = l / 16] and
-// B[k = l / 16][col = l % 16].  The 16x16 result sits in four registers per
-// lane with column l % 16; the row of register r differs by instruction:
-// 4 (l / 16) + r for the FP32 one and 4 r + l / 16 for the FP64 one.
-//
-// Per 16-element sub-tile (columns = elements, rows = nodes):
-//   (ur; us) = (Dr; Ds) u                    -> q = geometric combination
-//   div      = Dr (r_x q_x + r_y q_y) + Ds (s_x q_x + s_y q_y)
-//   rhs      = D div + LIFT [ (J_f/J) (F_f - D n_f.q_f (+ n_f.v u)) ]_f
-//   (convection: rhs -= r_x Dr(v_x u) + s_x Ds(v_x u) + r_y Dr(v_y u) + s_y Ds(v_y u))
+// A block takes 64 elements; each of its four waves one 16-element sub-tile
+// (columns = elements, rows = nodes):
+//   (ur; us) = (Dr; Ds) u,  q = (r_x ur + s_x us, r_y ur + s_y us)
+//   w_r = D (r_x q_x + r_y q_y) - v_r u,  w_s = D (s_x q_x + s_y q_y) - v_s u
+//   rhs = Dr w_r + Ds w_s + LIFT [ (1/J) (G_f - D (sJ n)_f.q_f + (sJ n)_f.v u) ]_f
+// with the contravariant velocity v_r = r_x v_x + r_y v_y, v_s = s_x v_x +
+// s_y v_y (convection only): because the metric terms are constant on an
+// affine element, the strong-form diffusion divergence and the convective
+// volume term -(d/dx (v_x u) + d/dy (v_y u)) share one [Dr Ds] product.  G_f
+// is the edge kernel's flux, already multiplied by the face's sJ.
+// Every global load of a tile (stage input, update operands, vertices, face
+// map and the gathered fluxes) is issued before the compute, so a wave waits
+// for memory twice (the face map, then the fluxes) instead of once per step.
 // The tile's stage input, the Runge-Kutta update and the output use the same
 // LDS-staged, coalesced passes as the thread-per-element kernel.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
 #include "kernel_common.hpp"
+#include "mfma.hpp"
 
 namespace ardg {
 
-typedef double mf_d4 __attribute__((ext_vector_type(4)));
-typedef float mf_f4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mma;
-template <> struct Mma<double> {
-  typedef mf_d4 acc;
-  __device__ static acc zero() {
-    acc z = {0.0, 0.0, 0.0, 0.0};
-    return z;
-  }
-  __device__ static acc mma(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static constexpr int row(int grp, int r) { return 4 * r + grp; }
-};
-template <> struct Mma<float> {
-  typedef mf_f4 acc;
-  __device__ static acc zero() {
-    acc z = {0.f, 0.f, 0.f, 0.f};
-    return z;
-  }
-  __device__ static acc mma(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static constexpr int row(int grp, int r) { return 4 * grp + r; }
-};
-
-constexpr int kMfmaTile = 64;   // elements per block (one wave)
+constexpr int kMfmaTile = 64;     // elements per block
+constexpr int kMfmaThreads = 256; // four waves, one 16-element sub-tile each
 
 template <int N, typename T, bool CONV>
-__global__ __launch_bounds__(kMfmaTile) void element_mfma_kernel(DevMesh m, const T* __restrict__ vin,
-                                                                 const T* __restrict__ flux,
-                                                                 Epilogue epi) {
+__global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, const T* __restrict__ vin,
+                                                                    const T* __restrict__ flux,
+                                                                    Epilogue epi) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
   constexpr int MT = (Np + 15) / 16;     // row tiles of nodes
@@ -72,14 +49,47 @@ __global__ __launch_bounds__(kMfmaTile) void element_mfma_kernel(DevMesh m, cons
   using M = Mma<T>;
   typedef typename M::acc acc_t;
   __shared__ T sh[kMfmaTile * Np];
-  __shared__ T sq[4][RW * 16];           // q_x, q_y, w_r, w_s of one sub-tile, [node][column]
-  const int l = threadIdx.x, col = l & 15, grp = l >> 4;
+  __shared__ T sqa[4][4][RW * 16];       // per wave: q_x, q_y, w_r, w_s of its sub-tile, [node][column]
+  const int l = threadIdx.x & 63, col = l & 15, grp = l >> 4;
+  const int st = threadIdx.x >> 6;       // this wave's sub-tile
+  T (*sq)[RW * 16] = sqa[st];
   const int64_t k0 = xcd_block(blockIdx.x, gridDim.x) * kMfmaTile;
   const int field = blockIdx.y;
   const int64_t E = m.E_int + m.E_bdy;
   const T* opg = (const T*)(sizeof(T) == 8 ? (const void*)m.ops64 : (const void*)m.ops32);
 
-  // operator fragments, resident for the whole kernel
+  // ---- loads: element data, face map, stage input, update operands ----
+  const int el = st * 16 + col;
+  const bool valid = k0 + el < m.K;
+  const int64_t k = valid ? k0 + el : k0;
+  const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
+  const double Dd = m.alg1 ? m.Delem[k] : m.Dfield[field];
+  int code[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) code[f] = m.elem_face[f * m.K + k];
+
+  TileIO<TileShape<N, kMfmaTile, kMfmaThreads>::Q> io;
+  tile_begin<N, T, kMfmaTile, kMfmaThreads>(m, k0, field, vin, epi, sh, io, kPre);
+
+  // face fluxes in the B layout of the lift: value q = 4c + grp is node q % Nfp
+  // of face q / Nfp, read from its edge (reversed and negated on side 2)
+  // (unconditional loads from clamped indices, masked afterwards)
+  T G[KL];
+#pragma unroll
+  for (int c = 0; c < KL; ++c) {
+    const int q = 4 * c + grp;
+    const int qc = q < NJ ? q : 0;
+    const int f = qc / Nfp, jj = qc - f * Nfp;
+    const int cd = (f == 0) ? code[0] : (f == 1 ? code[1] : code[2]);
+    const bool side2 = cd & 1;
+    const T x = flux[((int64_t)field * E + (cd >> 1)) * Nfp + (side2 ? Nfp - 1 - jj : jj)];
+    // the mask multiplies instead of selecting, so the load is not sunk
+    // into a branch of its own
+    const T sgn = (valid && q < NJ) ? (side2 ? T(-1) : T(1)) : T(0);
+    G[c] = sgn * x;
+  }
+
+  // operator fragments: row 16 mt + col, column 4 c + grp
   T aDr[MT][KC], aDs[MT][KC], aL[MT][KL];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
@@ -97,159 +107,133 @@ __global__ __launch_bounds__(kMfmaTile) void element_mfma_kernel(DevMesh m, cons
       aL[mt][c] = (row < Np && kk < NJ) ? opg[L.lift + row * NJ + kk] : T(0);
     }
   }
-
-  TileIO<Np> io;
-  tile_begin<N, T, kMfmaTile>(m, k0, field, vin, epi, sh, io, kPre);
-  __syncthreads();
-
-  for (int st = 0; st < kMfmaTile / 16; ++st) {
-    const int el = st * 16 + col;
-    const bool valid = el < io.nel;
-    const int64_t k = k0 + (valid ? el : 0);
-    const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
-    const double xr = 0.5 * (p2.x - p1.x), yr = 0.5 * (p2.y - p1.y);
-    const double xs = 0.5 * (p3.x - p1.x), ys = 0.5 * (p3.y - p1.y);
-    const double J = xr * ys - xs * yr;
-    const T rx = (T)(ys / J), ry = (T)(-xs / J), sx = (T)(-yr / J), sy = (T)(xr / J);
-    const T D = (T)(m.alg1 ? m.Delem[k] : m.Dfield[field]);
-
-    // u as B fragments: node 4c + grp of element `col`
-    T bu[KC];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      const int n = 4 * c + grp;
-      bu[c] = (valid && n < Np) ? sh[el * Np + n] : T(0);
-    }
-    acc_t ur[MT], us[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      ur[mt] = M::zero();
-      us[mt] = M::zero();
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        ur[mt] = M::mma(aDr[mt][c], bu[c], ur[mt]);
-        us[mt] = M::mma(aDs[mt][c], bu[c], us[mt]);
-      }
-    }
-    // accumulator layout: node 16 mt + M::row(grp, r) of element `col`
+  // reference coordinates (+1) of the nodes this lane touches (convection)
+  T r1a[MT][4], s1a[MT][4], r1f[KL], s1f[KL];
+  if (CONV) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int node = 16 * mt + M::row(grp, r);
-        const T qx = rx * ur[mt][r] + sx * us[mt][r];
-        const T qy = ry * ur[mt][r] + sy * us[mt][r];
-        sq[0][node * 16 + col] = qx;
-        sq[1][node * 16 + col] = qy;
-        sq[2][node * 16 + col] = rx * qx + ry * qy;
-        sq[3][node * 16 + col] = sx * qx + sy * qy;
+        const int nc = node < Np ? node : 0;
+        r1a[mt][r] = opg[L.nr + nc] + T(1);
+        s1a[mt][r] = opg[L.ns + nc] + T(1);
       }
-    __syncthreads();
-
-    acc_t rhs[MT];
-    {
-      T bw[KC], bs[KC];
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        const int n = 4 * c + grp;
-        bw[c] = sq[2][n * 16 + col];
-        bs[c] = sq[3][n * 16 + col];
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        acc_t dv = M::zero();
-#pragma unroll
-        for (int c = 0; c < KC; ++c) {
-          dv = M::mma(aDr[mt][c], bw[c], dv);
-          dv = M::mma(aDs[mt][c], bs[c], dv);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) rhs[mt][r] = D * dv[r];
-      }
-    }
-
-    // face values as B fragments over q = 4c + grp (face q / Nfp, node q % Nfp)
-    T bj[KL];
 #pragma unroll
     for (int c = 0; c < KL; ++c) {
       const int q = 4 * c + grp;
-      T v = T(0);
-      if (valid && q < NJ) {
-        const int f = q / Nfp, jj = q - f * Nfp;
-        const int nd = (f == 0) ? lat(N, jj, 0) : (f == 1 ? lat(N, N - jj, jj) : lat(N, 0, N - jj));
-        const double2 a = (f == 0) ? p1 : (f == 1 ? p2 : p3);
-        const double2 b = (f == 0) ? p2 : (f == 1 ? p3 : p1);
-        const double tx = b.x - a.x, ty = b.y - a.y;
-        const double len = sqrt(tx * tx + ty * ty);
-        const T nx = (T)(ty / len), ny = (T)(-tx / len);
-        const int code = m.elem_face[f * m.K + k];
-        const T* fe = flux + ((int64_t)field * E + (code >> 1)) * Nfp;
-        const T G = (code & 1) ? -fe[Nfp - 1 - jj] : fe[jj];
-        T jv = G - D * (nx * sq[0][nd * 16 + col] + ny * sq[1][nd * 16 + col]);
-        if (CONV) {
-          const double rr = (double)opg[L.nr + nd], ss = (double)opg[L.ns + nd];
-          const double x = 0.5 * (-(rr + ss) * p1.x + (rr + 1.0) * p2.x + (ss + 1.0) * p3.x);
-          const double y = 0.5 * (-(rr + ss) * p1.y + (rr + 1.0) * p2.y + (ss + 1.0) * p3.y);
-          const T vx = (T)(m.vel[0] + m.vel[2] * x + m.vel[3] * y);
-          const T vy = (T)(m.vel[1] + m.vel[4] * x + m.vel[5] * y);
-          jv += (nx * vx + ny * vy) * sh[el * Np + nd];
-        }
-        v = (T)(0.5 * len / J) * jv;
+      const int qc = q < NJ ? q : 0;
+      const int f = qc / Nfp;
+      const int nd = fnode(N, f, qc - f * Nfp);
+      r1f[c] = opg[L.nr + nd] + T(1);
+      s1f[c] = opg[L.ns + nd] + T(1);
+    }
+  }
+  __syncthreads();
+
+  // ---- compute ----
+  const ElemGeom gm = elem_geom(p1, p2, p3);
+  const T rx = (T)gm.rx, ry = (T)gm.ry, sx = (T)gm.sx, sy = (T)gm.sy;
+  const T D = (T)Dd;
+  ElemVel ev = {};
+  if (CONV) ev = elem_vel(m.vel, p1, gm);
+
+  // u as B fragments: node 4c + grp of element `col`
+  T bu[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const int n = 4 * c + grp;
+    bu[c] = (valid && n < Np) ? sh[el * Np + n] : T(0);
+  }
+  acc_t ur[MT], us[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    ur[mt] = M::zero();
+    us[mt] = M::zero();
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      ur[mt] = M::mma(aDr[mt][c], bu[c], ur[mt]);
+      us[mt] = M::mma(aDs[mt][c], bu[c], us[mt]);
+    }
+  }
+  // accumulator layout: node 16 mt + M::row(grp, r) of element `col`
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int node = 16 * mt + M::row(grp, r);
+      const T qx = rx * ur[mt][r] + sx * us[mt][r];
+      const T qy = ry * ur[mt][r] + sy * us[mt][r];
+      T wr = D * (rx * qx + ry * qy);
+      T ws = D * (sx * qx + sy * qy);
+      if (CONV) {
+        const T vx = (T)ev.x1 + r1a[mt][r] * (T)ev.xr + s1a[mt][r] * (T)ev.xs;
+        const T vy = (T)ev.y1 + r1a[mt][r] * (T)ev.yr + s1a[mt][r] * (T)ev.ys;
+        const T un = (valid && node < Np) ? sh[el * Np + (node < Np ? node : 0)] : T(0);
+        wr -= (rx * vx + ry * vy) * un;
+        ws -= (sx * vx + sy * vy) * un;
       }
-      bj[c] = v;
+      sq[0][node * 16 + col] = qx;
+      sq[1][node * 16 + col] = qy;
+      sq[2][node * 16 + col] = wr;
+      sq[3][node * 16 + col] = ws;
+    }
+  __syncthreads();
+
+  acc_t rhs[MT];
+  {
+    T bw[KC], bs[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const int n = 4 * c + grp;
+      bw[c] = sq[2][n * 16 + col];
+      bs[c] = sq[3][n * 16 + col];
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      acc_t lf = M::zero();
-#pragma unroll
-      for (int c = 0; c < KL; ++c) lf = M::mma(aL[mt][c], bj[c], lf);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) rhs[mt][r] += lf[r];
-    }
-
-    if (CONV) {
-      // nodal collocation of v u; -(d/dx (v_x u) + d/dy (v_y u))
-      T bfx[KC], bfy[KC];
+      rhs[mt] = M::zero();
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
-        const int n = 4 * c + grp;
-        T fx = T(0), fy = T(0);
-        if (valid && n < Np) {
-          const double rr = (double)opg[L.nr + n], ss = (double)opg[L.ns + n];
-          const double x = 0.5 * (-(rr + ss) * p1.x + (rr + 1.0) * p2.x + (ss + 1.0) * p3.x);
-          const double y = 0.5 * (-(rr + ss) * p1.y + (rr + 1.0) * p2.y + (ss + 1.0) * p3.y);
-          const T uu = sh[el * Np + n];
-          fx = (T)(m.vel[0] + m.vel[2] * x + m.vel[3] * y) * uu;
-          fy = (T)(m.vel[1] + m.vel[4] * x + m.vel[5] * y) * uu;
-        }
-        bfx[c] = fx;
-        bfy[c] = fy;
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        acc_t xr_ = M::zero(), xs_ = M::zero(), yr_ = M::zero(), ys_ = M::zero();
-#pragma unroll
-        for (int c = 0; c < KC; ++c) {
-          xr_ = M::mma(aDr[mt][c], bfx[c], xr_);
-          xs_ = M::mma(aDs[mt][c], bfx[c], xs_);
-          yr_ = M::mma(aDr[mt][c], bfy[c], yr_);
-          ys_ = M::mma(aDs[mt][c], bfy[c], ys_);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) rhs[mt][r] -= rx * xr_[r] + sx * xs_[r] + ry * yr_[r] + sy * ys_[r];
+        rhs[mt] = M::mma(aDr[mt][c], bw[c], rhs[mt]);
+        rhs[mt] = M::mma(aDs[mt][c], bs[c], rhs[mt]);
       }
     }
-    __syncthreads();   // every read of sq and of this sub-tile's u is done
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int node = 16 * mt + M::row(grp, r);
-        if (valid && node < Np) sh[el * Np + node] = rhs[mt][r];
-      }
-    __syncthreads();
   }
-  tile_end<N, T, kMfmaTile>(epi, sh, io, kPre);
+
+  // face values (1/J) (G - D (sJ n).q (+ (sJ n).v u)) as B fragments
+  T bj[KL];
+  const T iJ = (T)gm.iJ;
+#pragma unroll
+  for (int c = 0; c < KL; ++c) {
+    const int q = 4 * c + grp;
+    const int qc = q < NJ ? q : 0;
+    const int f = qc / Nfp;
+    const int nd = fnode(N, f, qc - f * Nfp);
+    const double2 sn = face_sjn(gm, f);
+    const T nx = (T)sn.x, ny = (T)sn.y;
+    T jv = G[c] - D * (nx * sq[0][nd * 16 + col] + ny * sq[1][nd * 16 + col]);
+    if (CONV) {
+      const T vx = (T)ev.x1 + r1f[c] * (T)ev.xr + s1f[c] * (T)ev.xs;
+      const T vy = (T)ev.y1 + r1f[c] * (T)ev.yr + s1f[c] * (T)ev.ys;
+      jv += (nx * vx + ny * vy) * sh[el * Np + nd];
+    }
+    bj[c] = (valid && q < NJ) ? iJ * jv : T(0);
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int c = 0; c < KL; ++c) rhs[mt] = M::mma(aL[mt][c], bj[c], rhs[mt]);
+
+  __syncthreads();   // every read of sq and of this sub-tile's u is done
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int node = 16 * mt + M::row(grp, r);
+      if (valid && node < Np) sh[el * Np + node] = rhs[mt][r];
+    }
+  __syncthreads();
+  tile_end<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre);
 }
 
 template <int N, typename T>
@@ -257,10 +241,10 @@ hipError_t elem_mfma_t(const DevMesh& m, int nfields, const void* vin, const voi
                        const Epilogue& epi, hipStream_t st) {
   dim3 grid((unsigned)((m.K + kMfmaTile - 1) / kMfmaTile), (unsigned)nfields);
   if (m.conv)
-    hipLaunchKernelGGL((element_mfma_kernel<N, T, true>), grid, dim3(kMfmaTile), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, T, true>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi);
   else
-    hipLaunchKernelGGL((element_mfma_kernel<N, T, false>), grid, dim3(kMfmaTile), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, T, false>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi);
   return hipGetLastError();
 }

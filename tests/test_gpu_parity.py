@@ -26,6 +26,10 @@ TOL32 = 2e-4
 
 
 def _flux_oracle(pr, u, nfields):
+    """Oracle edge fluxes times each edge's surface factor sJ = |edge| / 2,
+    the scaling the library's edge_flux_eval returns."""
+    sj = np.array([pr.geom.sJ[k1, f1] for (k1, f1, _, _) in pr.int_edges] +
+                  [pr.geom.sJ[k, fb] for (k, fb) in pr.bdy_edges])[:, None]
     out = []
     for f in range(nfields):
         Fi, Fb = pr.diffusive_flux(u[f], f)
@@ -34,7 +38,7 @@ def _flux_oracle(pr, u, nfields):
             ie = pr.int_edges
             Fi = Fi - np.array([fs[k1, f1] for (k1, f1, _, _) in ie]).reshape(Fi.shape)
             Fb = Fb - np.array([fs[k, fb] for (k, fb) in pr.bdy_edges]).reshape(Fb.shape)
-        out.append(np.vstack([Fi, Fb]))
+        out.append(np.vstack([Fi, Fb]) * sj)
     return np.stack(out)
 
 
@@ -199,3 +203,67 @@ def test_check_detects_nonfinite():
     with pytest.raises(ardg.ArdgError) as ei:
         lm.check(u)
     assert ei.value.status == -9
+
+
+VARIANT_CASES = [
+    # m, N, D kind, velocity
+    (10, 1, "blocks", None),
+    (10, 2, "blocks", None),
+    (11, 3, "blocks", None),
+    (12, 4, "blocks", None),
+    (9, 5, "blocks", None),
+    (9, 6, "blocks", None),
+    (12, 4, "const", None),
+    (10, 3, "const", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)),
+    (10, 4, "blocks", (0.3, -0.2, 0.0, -1.0, 1.0, 0.0)),
+]
+
+
+def _blocks_D(mesh):
+    # two values of D, split at the middle element index: edge tiles away from
+    # the split see one value (equal-D form of Algorithm 1), tiles near it two
+    k = np.arange(mesh.K)
+    return np.where(k < mesh.K // 2, 0.7, 3.1)
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES,
+                         ids=lambda c: f"m{c[0]}-N{c[1]}-{c[2]}-{'conv' if c[3] else 'diff'}")
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
+    """The kernel variants -- default (thread-per-edge edge kernel, matrix-core
+    element kernel), all thread-per-item, all matrix-core -- compute the same
+    flux and RHS (to rounding), each matching the oracle."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    m, N, dk, vel = case
+    print(f"variants m{m} N{N} {dk} {prec}", flush=True)
+    mesh = W.split_square_mesh(m, 0.2, seed=100 + N)
+    D_mode = "element" if dk == "blocks" else "const"
+    D = _blocks_D(mesh) if dk == "blocks" else [0.9]
+    pr = oracle_problem(mesh, N, D_mode, D, vel, 1)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    p = ardg.FP64 if prec == "fp64" else ardg.FP32
+    tol = TOL64 if prec == "fp64" else TOL32
+    outs = {}
+    variants = {"default": (None, None), "valu": ("valu", "valu"), "mfma": ("mfma", "mfma")}
+    for variant, (edge_k, elem_k) in variants.items():
+        for var, val in (("ARDG_EDGE_KERNEL", edge_k), ("ARDG_ELEMENT_KERNEL", elem_k)):
+            if val is None:
+                monkeypatch.delenv(var, raising=False)
+            else:
+                monkeypatch.setenv(var, val)
+        ops, lm = library_mesh(mesh, N, D_mode, D, vel, 1)
+        u = W.random_nodal((1, mesh.K, ops.Np), seed=7 * N + m)
+        ud = to_dev(u, dt)
+        flux = torch.empty((1, lm.E, ops.Nfp), dtype=dt, device=ud.device)
+        lm.edge_flux_eval(ud, flux, precision=p)
+        rhs = torch.empty_like(ud)
+        lm.rhs_eval(ud, rhs, precision=p)
+        outs[variant] = (to_np(flux), to_np(rhs))
+    Fo = _flux_oracle(pr, u, 1)
+    ro = pr.rhs(u)
+    for variant, (Fg, rg) in outs.items():
+        ef = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+        er = np.abs(rg - ro).max() / np.abs(ro).max()
+        print(f"  {variant}: flux {ef:.2e} rhs {er:.2e}", flush=True)
+        assert ef <= tol and er <= tol
