@@ -4,12 +4,15 @@ Workload (default): unit square 256 x 256 x 2 = 131072 triangles, interior
 vertices jittered by +-0.2 h (seeded), N = 4 (Np = 15), element-wise D with
 contrast 1e4 (1e-2 outside, 1e2 inside a circle of radius 0.25; Algorithm 1
 flux), initial data a seeded sum of 16 Fourier modes, classic RK4.  The FP64
-path is the headline value; the mixed mode (FP32 operators and arithmetic,
-FP64 RK state) is reported beside it with its L2 difference to the FP64 path.
+path is the headline value; the mixed modes (FP32 operators and arithmetic,
+and split-BF16 products on the matrix cores with FP32 accumulation, both with
+the FP64 RK state) are reported beside it with their L2 difference to the
+FP64 path.
 
 One bench step = one RK4 time step = 4 passes of the whole hot path (edge
 reconstruction kernel + element kernel with the fused RK update).  Inputs are
-resident in HBM before timing starts; the step loop is a replayed HIP graph.
+resident in HBM before timing starts; the K timed steps are one HIP graph,
+captured before the timed region and launched once inside it.
 
 `cpu_baseline` times the FP64 NumPy oracle (test infrastructure) on a bounded
 sample: one RHS stage on the first S elements of the same workload.
@@ -36,6 +39,41 @@ FP64_PEAK_TFLOPS = 78.6
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernel_common.hpp",
+                  "edge_common.hpp", "mfma.hpp", "device.hpp")
+
+
+def kernel_source_hash():
+    """SHA-256 over the device-code sources, to tie stored counter data to the
+    kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1912_06221_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel
+    calibration), or None when there is none or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    src, val = None, None
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip().strip("`")
+            if line.startswith("kernel-source-sha256:"):
+                src = line.split(":", 1)[1].strip()
+            elif line.startswith(f"traffic-bytes-per-launch {kernel}:"):
+                val = float(line.split(":", 1)[1])
+    if src is None or val is None or src != kernel_source_hash():
+        return None
+    return val
 
 
 def build_workload(name):
@@ -184,7 +222,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="contrast_256x256_N4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true", help="time the FP64 path only")
     ap.add_argument("--power-iters", type=int, default=30)
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched workload")
     ap.add_argument("--calib-copy", action="store_true",
@@ -243,30 +281,38 @@ def main():
         nrm = float(torch.linalg.vector_norm(w))
         rho = nrm / float(torch.linalg.vector_norm(v))
         v = w / nrm
-    dt = 1.0 / rho
+    # half the explicit limit of the estimate: power iteration approaches the
+    # spectral radius from below, and the L2 differences between precisions
+    # are only meaningful on a stable run
+    dt = 0.5 / rho
     log(f"bench: spectral radius ~{rho:.3e}, dt={dt:.3e}")
 
     results = {}
-    for prec_name, prec in (("fp64", ardg.FP64), ("fp32", ardg.FP32)):
-        if prec_name == "fp32" and args.skip_fp32:
+    for prec_name, prec in (("fp64", ardg.FP64), ("fp32", ardg.FP32), ("bf16x3", ardg.BF16X3)):
+        if prec_name != "fp64" and args.skip_fp32:
             continue
         u = torch.from_numpy(u0.copy()).to(dev)
         work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, prec, nf), dev)
         for _ in range(args.warmup):
             lm.rk_step(u, work, dt, 1, scheme=ardg.RK4, precision=prec, nfields=nf)
+        # the K timed steps are one graph (captured here, outside the timing)
+        lm.rk_prepare(u, work, dt, args.steps, scheme=ardg.RK4, precision=prec, nfields=nf)
         torch.cuda.synchronize()
         st = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        for _ in range(args.steps):
-            lm.rk_step(u, work, dt, 1, scheme=ardg.RK4, precision=prec, nfields=nf)
+        lm.rk_step(u, work, dt, args.steps, scheme=ardg.RK4, precision=prec, nfields=nf)
         e1.record(st)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
-        # per-kernel durations (HIP events around each launch, same stream)
-        t_edge, t_elem = lm.stage_timing(u, work, dt, 40, scheme=ardg.RK4, precision=prec, nfields=nf)
         lm.check(u, nfields=nf)
-        results[prec_name] = dict(ms=ms, t_edge=t_edge, t_elem=t_elem, u=u.detach().cpu().numpy())
+        un = u.detach().cpu().numpy()
+        # per-kernel durations: HIP events on the launch stream around replays
+        # of a 40-stage graph and of its element kernels alone (alters u, so
+        # it comes after the state is read)
+        t_edge, t_elem = lm.stage_timing(u, work, dt, 40, scheme=ardg.RK4, precision=prec, nfields=nf)
+        results[prec_name] = dict(ms=ms, t_edge=t_edge, t_elem=t_elem, u=un,
+                                  norm_ratio=float(np.linalg.norm(un) / np.linalg.norm(u0)))
         log(f"bench: {prec_name}: {ms:.3f} ms/step, edge {t_edge*1e3:.1f} us, elem {t_elem*1e3:.1f} us")
 
     r64 = results["fp64"]
@@ -277,9 +323,10 @@ def main():
     bw_elem = b_elem / (r64["t_elem"] * 1e-3) / 1e9
     dom = "element" if r64["t_elem"] >= r64["t_edge"] else "edge"
     bw = bw_elem if dom == "element" else bw_edge
+    traffic = stored_traffic(args.workload, f"{dom}-fp64")
     fl = edge_flops(K, Np, Nfp, N, lm.E_int, lm.E_bdy, alg1, nf)
     line = {
-        "metric": "DOF*RK-stage/s per MI355X (FP64 path; mixed FP32 path beside it with L2 difference)",
+        "metric": "DOF*RK-stage/s per MI355X (FP64 path; mixed FP32 and BF16x3 paths beside it with L2 difference)",
         "value": value,
         "unit": "DOF*stage/s",
         "n_gpus": 1,
@@ -295,20 +342,23 @@ def main():
         "config": {"workload": args.workload, "K": K, "N": N, "Np": Np, "DOF": dof,
                    "E_int": lm.E_int, "E_bdy": lm.E_bdy, "D": spec["D"], "scheme": "RK4",
                    "dt": dt, "fields": nf},
+        "state_norm_ratio": r64["norm_ratio"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": bw, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": bw / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": bw / HBM_PEAK_GBS, "traffic": traffic,
                      "edge_kernel_us": r64["t_edge"] * 1e3, "element_kernel_us": r64["t_elem"] * 1e3,
                      "edge_GBps": bw_edge, "element_GBps": bw_elem,
                      "edge_algorithmic_bytes": b_edge, "element_algorithmic_bytes": b_elem,
                      "edge_TFLOPs": fl / (r64["t_edge"] * 1e-3) / 1e12,
                      "edge_fp64_frac": fl / (r64["t_edge"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
     }
-    if "fp32" in results:
-        r32 = results["fp32"]
+    for mode in ("fp32", "bf16x3"):
+        if mode not in results:
+            continue
+        r32 = results[mode]
         d = r32["u"] - r64["u"]
         l2 = float(np.sqrt(np.sum(d * d) / np.sum(r64["u"] ** 2)))
         b_edge32, b_elem32 = algorithmic_bytes(K, Np, Nfp, lm.E_int, lm.E_bdy, 4, alg1, nf)
-        line["mixed_fp32"] = {
+        line["mixed_" + mode] = {
             "value": dof * 4 / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"],
             "speedup_vs_fp64": r64["ms"] / r32["ms"],
             "rel_l2_diff_vs_fp64_after_steps": l2,

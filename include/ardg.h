@@ -190,13 +190,22 @@ ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int3
                          double* u_dev, void* work_dev, double t0, double dt, int32_t nsteps,
                          void* hip_stream);
 
-/* Kernel timing hook (profiling): run `reps` Runge-Kutta stages of the same
- * configuration as ardg_rk_step with plain launches (no graph), recording HIP
- * events on hip_stream around each kernel, and return the average duration
- * in milliseconds of the edge kernel (out_ms[0]) and of the element kernel
- * with its fused update (out_ms[1]).  Advances u_dev like ardg_rk_step
- * (reps must be a multiple of the scheme's stage count).  Synchronises the
- * stream.  Errors as ardg_rk_step. */
+/* Capture and instantiate the graph that ardg_rk_step replays for exactly
+ * these arguments (nsteps >= 1) without running it, so that a caller can
+ * keep the capture cost out of a latency-critical or timed region.  Nothing
+ * is enqueued.  Errors as ardg_rk_step. */
+ardg_status ardg_rk_prepare(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
+                            double* u_dev, void* work_dev, double dt, int32_t nsteps);
+
+/* Kernel timing hook (profiling): `reps` Runge-Kutta stages in the
+ * configuration of ardg_rk_step are captured into graph A, and the same
+ * stages' element kernels alone into graph B; each is replayed once untimed
+ * and once between HIP events on hip_stream.  Returns the average duration in
+ * milliseconds of the edge kernel, (A - B) / reps (out_ms[0]), and of the
+ * element kernel with its fused update, B / reps (out_ms[1]).  Changes u_dev
+ * and the workspace (graph B repeats stages), so the state is not a solution
+ * afterwards; reps must be a multiple of the scheme's stage count.
+ * Synchronises the stream.  Errors as ardg_rk_step. */
 ardg_status ardg_stage_timing(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
                               double* u_dev, void* work_dev, double dt, int32_t reps,
                               void* hip_stream, float* out_ms);

@@ -60,6 +60,7 @@ SIGNATURES = {
     "ardg_rk_workspace_bytes": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_int64)]),
     "ardg_rk_step": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
                                c_double, c_int32, c_void_p]),
+    "ardg_rk_prepare": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double, c_int32]),
     "ardg_stage_timing": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
                                     c_int32, c_void_p, POINTER(ctypes.c_float)]),
     "ardg_check": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
@@ -211,9 +212,17 @@ class Mesh:
         _check(lib().ardg_rk_step(self.handle, scheme, precision, nfields, _ptr(u), _ptr(work), t0,
                                   dt, nsteps, _stream(stream)))
 
+    def rk_prepare(self, u, work, dt: float, nsteps: int, scheme: int = RK4, precision: int = FP64,
+                   nfields: int = 1):
+        """Capture the graph rk_step would replay for these arguments, without
+        running it."""
+        _check(lib().ardg_rk_prepare(self.handle, scheme, precision, nfields, _ptr(u), _ptr(work),
+                                     dt, nsteps))
+
     def stage_timing(self, u, work, dt: float, reps: int, scheme: int = RK4, precision: int = FP64,
                      nfields: int = 1, stream=None):
-        """Average (edge kernel ms, element kernel ms) over `reps` stages."""
+        """Average kernel duration (edge ms, element ms) from replays of a graph
+        of `reps` RK stages and of one of their element kernels alone; alters u."""
         out = (ctypes.c_float * 2)()
         _check(lib().ardg_stage_timing(self.handle, scheme, precision, nfields, _ptr(u), _ptr(work),
                                        dt, reps, _stream(stream), out))

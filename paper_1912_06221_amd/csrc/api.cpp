@@ -243,13 +243,17 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
     m->dm.N = m->N;
     {
       // kernel implementations.  Element kernel: matrix cores (default) or one
-      // thread per element (ARDG_ELEMENT_KERNEL=valu).  Edge kernel: one
-      // thread per edge (default) or interior edges on the matrix cores
-      // (ARDG_EDGE_KERNEL=mfma).
+      // thread per element (ARDG_ELEMENT_KERNEL=valu).  Edge kernel: chosen
+      // per launch from the grid size (default), two waves per tile split by
+      // side (ARDG_EDGE_KERNEL=split), one thread per edge (=lane) or interior
+      // edges on the matrix cores (=mfma).
       const char* ek = std::getenv("ARDG_ELEMENT_KERNEL");
       m->dm.elem_mfma = (ek && std::string(ek) == "valu") ? 0 : 1;
       const char* ed = std::getenv("ARDG_EDGE_KERNEL");
-      m->dm.edge_mfma = (ed && std::string(ed) == "mfma") ? 1 : 0;
+      const std::string eds = ed ? ed : "";
+      m->dm.edge_kernel = eds == "mfma" ? EDGE_MFMA
+                          : eds == "lane" ? EDGE_LANE
+                          : eds == "split" ? EDGE_SPLIT : EDGE_AUTO;
     }
     m->dm.K = m->hm.K;
     m->dm.E_int = m->hm.E_int;
@@ -471,8 +475,8 @@ ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* p
 static ardg_status check_compute(ardg_mesh mesh, int32_t precision, int32_t nfields) {
   if (!mesh) return fail(ARDG_E_INVALID_ARG, "null mesh");
   if (mesh->device < 0) return fail(ARDG_E_INVALID_ARG, "mesh was created host-only (device -1)");
-  if (precision != ARDG_FP64 && precision != ARDG_FP32)
-    return fail(ARDG_E_UNSUPPORTED, "precision not built (FP64 and FP32 are)");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32 && precision != ARDG_BF16X3)
+    return fail(ARDG_E_UNSUPPORTED, "unknown precision");
   if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "nfields out of range");
   if (mesh->dm.alg1 && nfields != 1) return fail(ARDG_E_INVALID_ARG, "element-wise D is for one field");
   if (!mesh->dm.alg1 && nfields > mesh->nfields_D && mesh->nfields_D != 1)
@@ -497,7 +501,7 @@ ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfiel
   if (s != ARDG_OK) return s;
   if (!u_dev || !flux_dev) return fail(ARDG_E_INVALID_ARG, "edge_flux_eval: null buffer");
   DeviceGuard g(mesh->device);
-  HIP_TRY(launch_edge_flux(mesh->dm, precision == ARDG_FP64, nfields, u_dev, flux_dev,
+  HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux_dev,
                            (hipStream_t)hip_stream), "edge flux launch");
   return ARDG_OK;
 }
@@ -515,11 +519,11 @@ ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, co
   if (s != ARDG_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool f64 = precision == ARDG_FP64;
-  HIP_TRY(launch_edge_flux(mesh->dm, f64, nfields, u_dev, mesh->flux_scratch, st), "edge flux launch");
+  HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, mesh->flux_scratch, st), "edge flux launch");
   Epilogue epi;
   epi.kind = EPI_RHS;
   epi.rhs_out = rhs_dev;
-  HIP_TRY(launch_element(mesh->dm, f64, nfields, u_dev, mesh->flux_scratch, epi, st), "element launch");
+  HIP_TRY(launch_element(mesh->dm, precision, nfields, u_dev, mesh->flux_scratch, epi, st), "element launch");
   return ARDG_OK;
 }
 
@@ -549,7 +553,8 @@ ardg_status ardg_rk_workspace_bytes(ardg_mesh mesh, int32_t scheme, int32_t prec
                                     int64_t* bytes) {
   if (!mesh || !bytes) return fail(ARDG_E_INVALID_ARG, "rk_workspace_bytes: null argument");
   if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
-  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32 && precision != ARDG_BF16X3)
+    return fail(ARDG_E_UNSUPPORTED, "unknown precision");
   size_t t = 0;
   work_layout(mesh, precision, nfields, &t, nullptr, nullptr);
   *bytes = (int64_t)t;
@@ -586,7 +591,7 @@ static hipError_t enqueue_steps(ardg_mesh mesh, int scheme, int precision, int n
         vin = (scheme == ARDG_LSERK54 || s == 0) ? (const void*)u : w.v;
       else
         vin = w.v;
-      e = launch_edge_flux(mesh->dm, f64, nfields, vin, w.flux, st);
+      e = launch_edge_flux(mesh->dm, precision, nfields, vin, w.flux, st);
       if (e != hipSuccess) return e;
       epi.stage = s;
       if (scheme == ARDG_RK4) {
@@ -598,27 +603,19 @@ static hipError_t enqueue_steps(ardg_mesh mesh, int scheme, int precision, int n
         epi.b = kLsB[s];
         epi.vnext = f64 ? nullptr : w.v;
       }
-      e = launch_element(mesh->dm, f64, nfields, vin, w.flux, epi, st);
+      e = launch_element(mesh->dm, precision, nfields, vin, w.flux, epi, st);
       if (e != hipSuccess) return e;
     }
   }
   return hipSuccess;
 }
 
-ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields, double* u_dev,
-                         void* work_dev, double t0, double dt, int32_t nsteps, void* hip_stream) {
-  (void)t0;
-  ardg_status s = check_compute(mesh, precision, nfields);
-  if (s != ARDG_OK) return s;
-  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
-  if (!u_dev || !work_dev) return fail(ARDG_E_INVALID_ARG, "rk_step: null buffer");
-  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "rk_step: work_dev not 256-byte aligned");
-  if (nsteps < 0 || !std::isfinite(dt)) return fail(ARDG_E_INVALID_ARG, "rk_step: bad nsteps or dt");
-  if (nsteps == 0) return ARDG_OK;
-  DeviceGuard g(mesh->device);
+// The instantiated graph of `nsteps` steps for these arguments, captured on
+// first use and cached on the mesh (a bounded cache).
+static ardg_status step_graph(ardg_mesh mesh, int scheme, int precision, int nfields, double* u_dev,
+                              void* work_dev, double dt, int nsteps, hipGraphExec_t* out) {
   Work w;
   work_layout(mesh, precision, nfields, nullptr, &w, work_dev);
-  hipStream_t st = (hipStream_t)hip_stream;
   GraphKey key{scheme, precision, nfields, nsteps, u_dev, work_dev, dt, mesh->version};
   auto it = mesh->graphs.find(key);
   if (it == mesh->graphs.end()) {
@@ -639,8 +636,78 @@ ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int3
     if (mesh->graphs.size() >= 8) mesh->drop_graphs();
     it = mesh->graphs.emplace(key, exec).first;
   }
-  HIP_TRY(hipGraphLaunch(it->second, st), "hipGraphLaunch");
+  *out = it->second;
   return ARDG_OK;
+}
+
+ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields, double* u_dev,
+                         void* work_dev, double t0, double dt, int32_t nsteps, void* hip_stream) {
+  (void)t0;
+  ardg_status s = check_compute(mesh, precision, nfields);
+  if (s != ARDG_OK) return s;
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  if (!u_dev || !work_dev) return fail(ARDG_E_INVALID_ARG, "rk_step: null buffer");
+  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "rk_step: work_dev not 256-byte aligned");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(ARDG_E_INVALID_ARG, "rk_step: bad nsteps or dt");
+  if (nsteps == 0) return ARDG_OK;
+  DeviceGuard g(mesh->device);
+  hipGraphExec_t exec = nullptr;
+  s = step_graph(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nsteps, &exec);
+  if (s != ARDG_OK) return s;
+  HIP_TRY(hipGraphLaunch(exec, (hipStream_t)hip_stream), "hipGraphLaunch");
+  return ARDG_OK;
+}
+
+ardg_status ardg_rk_prepare(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields, double* u_dev,
+                            void* work_dev, double dt, int32_t nsteps) {
+  ardg_status s = check_compute(mesh, precision, nfields);
+  if (s != ARDG_OK) return s;
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  if (!u_dev || !work_dev) return fail(ARDG_E_INVALID_ARG, "rk_prepare: null buffer");
+  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "rk_prepare: work_dev not 256-byte aligned");
+  if (nsteps < 1 || !std::isfinite(dt)) return fail(ARDG_E_INVALID_ARG, "rk_prepare: bad nsteps or dt");
+  DeviceGuard g(mesh->device);
+  hipGraphExec_t exec = nullptr;
+  return step_graph(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nsteps, &exec);
+}
+
+// One graph of `reps` stages of the step sequence (edge kernel + element
+// kernel each), or of the element kernels alone (with_edge false).
+static hipError_t capture_stages(ardg_mesh mesh, int scheme, int precision, int nfields, double* u_dev,
+                                 const Work& w, double dt, int reps, bool with_edge, hipGraphExec_t* out) {
+  const bool f64 = precision == ARDG_FP64;
+  const int nst = scheme == ARDG_RK4 ? 4 : 5;
+  hipStream_t cs = mesh->cap_stream;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t ec = hipSuccess;
+  if (!f64) ec = launch_to_f32(u_dev, (float*)w.v, (int64_t)nfields * mesh->hm.K * mesh->ro.Np, cs);
+  Epilogue epi;
+  epi.u = u_dev;
+  epi.acc = w.acc;
+  epi.dt = dt;
+  for (int r = 0; r < reps && ec == hipSuccess; ++r) {
+    const int sidx = r % nst;
+    const void* vin = f64 ? ((scheme == ARDG_LSERK54 || sidx == 0) ? (const void*)u_dev : w.v) : w.v;
+    epi.stage = sidx;
+    if (scheme == ARDG_RK4) {
+      epi.kind = EPI_RK4;
+      epi.vnext = (sidx < 3) ? w.v : (f64 ? nullptr : w.v);
+    } else {
+      epi.kind = EPI_LSERK;
+      epi.a = kLsA[sidx];
+      epi.b = kLsB[sidx];
+      epi.vnext = f64 ? nullptr : w.v;
+    }
+    if (with_edge) ec = launch_edge_flux(mesh->dm, precision, nfields, vin, w.flux, cs);
+    if (ec == hipSuccess) ec = launch_element(mesh->dm, precision, nfields, vin, w.flux, epi, cs);
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  if (ec != hipSuccess) e = ec;
+  if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  return e;
 }
 
 ardg_status ardg_stage_timing(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
@@ -657,47 +724,36 @@ ardg_status ardg_stage_timing(ardg_mesh mesh, int32_t scheme, int32_t precision,
   Work w;
   work_layout(mesh, precision, nfields, nullptr, &w, work_dev);
   hipStream_t st = (hipStream_t)hip_stream;
-  const bool f64 = precision == ARDG_FP64;
-  std::vector<hipEvent_t> ev(3 * reps);
-  for (auto& e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
-  hipError_t e = hipSuccess;
-  if (!f64) e = launch_to_f32(u_dev, (float*)w.v, (int64_t)nfields * mesh->hm.K * mesh->ro.Np, st);
-  Epilogue epi;
-  epi.u = u_dev;
-  epi.acc = w.acc;
-  epi.dt = dt;
-  for (int r = 0; r < reps && e == hipSuccess; ++r) {
-    const int sidx = r % nst;
-    const void* vin = f64 ? ((scheme == ARDG_LSERK54 || sidx == 0) ? (const void*)u_dev : w.v) : w.v;
-    epi.stage = sidx;
-    if (scheme == ARDG_RK4) {
-      epi.kind = EPI_RK4;
-      epi.vnext = (sidx < 3) ? w.v : (f64 ? nullptr : w.v);
-    } else {
-      epi.kind = EPI_LSERK;
-      epi.a = kLsA[sidx];
-      epi.b = kLsB[sidx];
-      epi.vnext = f64 ? nullptr : w.v;
-    }
-    (void)hipEventRecord(ev[3 * r], st);
-    e = launch_edge_flux(mesh->dm, f64, nfields, vin, w.flux, st);
-    (void)hipEventRecord(ev[3 * r + 1], st);
-    if (e == hipSuccess) e = launch_element(mesh->dm, f64, nfields, vin, w.flux, epi, st);
-    (void)hipEventRecord(ev[3 * r + 2], st);
-  }
+  if (!mesh->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&mesh->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+  // graph A: the stage sequence; graph B: its element kernels alone.  Events
+  // on the launch stream bracket each replay: element = B / reps, edge =
+  // (A - B) / reps (kernels in a graph follow each other without host gaps)
+  hipGraphExec_t ga = nullptr, gb = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = capture_stages(mesh, scheme, precision, nfields, u_dev, w, dt, reps, true, &ga);
+  if (e == hipSuccess) e = capture_stages(mesh, scheme, precision, nfields, u_dev, w, dt, reps, false, &gb);
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  // one replay of each first (warm-up), then the timed replays
+  if (e == hipSuccess) e = hipGraphLaunch(ga, st);
+  if (e == hipSuccess) e = hipGraphLaunch(gb, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+  if (e == hipSuccess) e = hipGraphLaunch(ga, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], st);
+  if (e == hipSuccess) e = hipGraphLaunch(gb, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  double te = 0.0, tl = 0.0;
-  for (int r = 0; r < reps && e == hipSuccess; ++r) {
-    float a = 0.f, b = 0.f;
-    e = hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]);
-    if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * r + 1], ev[3 * r + 2]);
-    te += a;
-    tl += b;
-  }
-  for (auto& x : ev) (void)hipEventDestroy(x);
+  float ta = 0.f, tb = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ta, ev[0], ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&tb, ev[2], ev[3]);
+  if (ga) (void)hipGraphExecDestroy(ga);
+  if (gb) (void)hipGraphExecDestroy(gb);
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
   if (e != hipSuccess) return hip_fail(e, "stage_timing");
-  out_ms[0] = (float)(te / reps);
-  out_ms[1] = (float)(tl / reps);
+  out_ms[0] = (ta - tb) / reps;
+  out_ms[1] = tb / reps;
   return ARDG_OK;
 }
 
@@ -1050,7 +1106,8 @@ void ardg_batch_destroy(ardg_batch batch) { delete batch; }
 ardg_status ardg_batch_workspace_bytes(ardg_batch batch, int32_t scheme, int32_t precision, int64_t* bytes) {
   if (!batch || !bytes) return fail(ARDG_E_INVALID_ARG, "batch_workspace_bytes: null argument");
   if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
-  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32)
+    return fail(ARDG_E_UNSUPPORTED, "batched stepping is built for FP64 and FP32");
   size_t t = 0;
   batch_layout(batch, precision, nullptr, &t);
   *bytes = (int64_t)t;
@@ -1060,7 +1117,8 @@ ardg_status ardg_batch_workspace_bytes(ardg_batch batch, int32_t scheme, int32_t
 ardg_status ardg_batch_tiles(ardg_batch batch, int32_t precision, int32_t N, int32_t* edge_tile,
                              int32_t* elem_tile, int32_t* grid) {
   if (!batch) return fail(ARDG_E_INVALID_ARG, "batch_tiles: null batch");
-  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32)
+    return fail(ARDG_E_UNSUPPORTED, "batched stepping is built for FP64 and FP32");
   DeviceGuard g(batch->device);
   ardg_status s = tune(batch, precision);
   if (s != ARDG_OK) return s;
@@ -1079,7 +1137,8 @@ ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
                             void* work_dev, const double* dt, int32_t nsteps, void* hip_stream) {
   if (!batch || !u_devs || !work_dev || !dt) return fail(ARDG_E_INVALID_ARG, "batch_step: null argument");
   if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
-  if (precision != ARDG_FP64 && precision != ARDG_FP32) return fail(ARDG_E_UNSUPPORTED, "precision not built");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32)
+    return fail(ARDG_E_UNSUPPORTED, "batched stepping is built for FP64 and FP32");
   if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "batch_step: work_dev not 256-byte aligned");
   if (nsteps < 0) return fail(ARDG_E_INVALID_ARG, "batch_step: nsteps < 0");
   const size_t n = batch->meshes.size();

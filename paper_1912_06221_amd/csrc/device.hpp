@@ -9,6 +9,11 @@ namespace ardg {
 
 constexpr int kMaxFields = 16;
 
+// Arithmetic of the operator products (values as in the C ABI).  FP64:
+// double data; FP32: float data; BF16X3: float data, products on the BF16
+// matrix cores with split operands (hi + lo) and FP32 accumulation.
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
+
 // Offsets of the packed constant operators (same layout in FP64 and FP32).
 struct OpLayout {
   int Np, Nfp;
@@ -38,6 +43,12 @@ struct OpLayout {
         total(ns + Np) {}
 };
 
+// Edge kernel implementations.
+// EDGE_AUTO picks EDGE_SPLIT where one thread per edge leaves the chip
+// latency-bound (few waves per SIMD, or high order with few waves resident)
+// and EDGE_LANE otherwise.
+enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3 };
+
 struct DevMesh {
   int N = 0;
   int64_t K = 0, E_int = 0, E_bdy = 0;
@@ -57,7 +68,7 @@ struct DevMesh {
   const float* ops32 = nullptr;
   int alg1 = 0;                   // element-wise D (Algorithm 1)
   int elem_mfma = 1;              // element kernel on the matrix cores
-  int edge_mfma = 0;              // interior edges on the matrix cores
+  int edge_kernel = EDGE_AUTO;    // EdgeKernel
   int conv = 0;                   // convective term on
   double Dfield[kMaxFields] = {};
   double vel[6] = {};             // v = (p0 + p2 x + p3 y, p1 + p4 x + p5 y)
@@ -88,10 +99,10 @@ struct BatchProb {
 };
 
 // Edge fluxes of all interior and boundary edges for nfields fields.
-hipError_t launch_edge_flux(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
+hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st);
 // Element volume + LIFT of the fluxes + epilogue.
-hipError_t launch_element(const DevMesh& m, bool fp64, int nfields, const void* vin,
+hipError_t launch_element(const DevMesh& m, int prec, int nfields, const void* vin,
                           const void* flux, const Epilogue& epi, hipStream_t st);
 // Batched (persistent) kernels over work items (problem, tile).  tile is the
 // number of edges / elements per item and the block size (64, 128 or 256);
@@ -109,10 +120,10 @@ hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int ni
 
 // Edge kernel with interior edges on the matrix cores (same contract as
 // launch_edge_flux).
-hipError_t launch_edge_mfma(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
+hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st);
 // Element kernel on the matrix cores (same contract as launch_element).
-hipError_t launch_element_mfma(const DevMesh& m, bool fp64, int nfields, const void* vin,
+hipError_t launch_element_mfma(const DevMesh& m, int prec, int nfields, const void* vin,
                                const void* flux, const Epilogue& epi, hipStream_t st);
 
 // Copy an FP64 state into an FP32 copy (stage input of the FP32 mode).

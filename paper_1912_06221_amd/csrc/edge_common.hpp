@@ -59,6 +59,45 @@ __device__ inline void matvec_n(cptr<T> A0, XA x, YA y) {
   }
 }
 
+// y = A x for the ROWS x COLS block of a row-major operator with leading
+// dimension LD (a column slice of a wider matrix), chunk-pipelined like
+// matvec_n.
+template <int ROWS, int COLS, int LD, typename T>
+__device__ inline void matvec_ld(cptr<T> A0, const T* x, T* y) {
+  constexpr int CH = sizeof(T) == 8 ? 12 : 16;
+  constexpr int NCH = (COLS + CH - 1) / CH;
+  constexpr int NSTEP = ROWS * NCH;
+  T buf[2][CH];
+  {
+    const cptr<T> A = fresh(A0);
+#pragma unroll
+    for (int q = 0; q < CH && q < COLS; ++q) buf[0][q] = A[q];
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int st = 0; st < NSTEP; ++st) {
+    const int r = st / NCH, ch = st % NCH;
+    const int q0 = ch * CH;
+    const int qn = (COLS - q0) < CH ? (COLS - q0) : CH;
+    row_fence();
+    if (st + 1 < NSTEP) {
+      const int r1 = (st + 1) / NCH, c1 = (st + 1) % NCH;
+      const int p0 = c1 * CH;
+      const int pn = (COLS - p0) < CH ? (COLS - p0) : CH;
+      const cptr<T> A = fresh(A0);
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (q < pn) buf[(st + 1) & 1][q] = A[r1 * LD + p0 + q];
+    }
+    T sum = (ch == 0) ? buf[st & 1][0] * x[q0] : fma(buf[st & 1][0], x[q0], acc);
+#pragma unroll
+    for (int q = 1; q < CH; ++q)
+      if (q < qn) sum = fma(buf[st & 1][q], x[q0 + q], sum);
+    acc = sum;
+    if (ch == NCH - 1) y[r] = sum;
+  }
+}
+
 // single-vector views for matvec_n: v[0][q] == p[q]
 template <typename P>
 struct OneVec {
@@ -132,6 +171,60 @@ __device__ inline void matvec_sel(cptr<T> A0, const T* x, T* y) {
     matvec_pf<ROWS, COLS, T>(A0, x, y);
   else
     matvec<ROWS, COLS, T>(A0, x, y);
+}
+
+// Diffusive flux of boundary face e (index past the interior edges): the
+// element's sub-triangle on its mirror-ghost rhombus and the boundary
+// reconstruction operator.  F receives sJ * flux, trace the element's values
+// on the face, vn the stored n.v (convection).
+template <int N, typename T, bool ALG1>
+__device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, int field,
+                                     const T* __restrict__ uf, T* F, T* trace, double2& vn) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp;
+  const int64_t b = e - m.E_int;
+  const int kb = m.bk[b];
+  const double2 g = m.bgam[b], mu = m.bmu[b];
+  if (m.conv) vn = m.vn[e];
+  const int k = kb & 0x3fffffff, fa = (int)((unsigned)kb >> 30);
+  T v[Np];
+#pragma unroll
+  for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
+  const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
+  T t[Np], c[Np];
+  rotate_to_face<N, T>(v, fa, t, trace);
+  matvec<Np, Np, T>(op + L.n2b, t, c);
+  decasteljau<N, T>(c, mu);
+  const T gR = (T)g.x, gS = (T)g.y;
+  T gb[2 * Nfp];
+  matvec<2 * Nfp, Np, T>(op + (ALG1 ? L.ubr : L.kbr), c, gb);
+#pragma unroll
+  for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gb[j] + gS * gb[Nfp + j]);
+}
+
+// Boundary face e with its upwind convective flux (u+ = 0 outside), written
+// to the flux array.
+template <int N, typename T, bool ALG1>
+__device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
+                                     const T* __restrict__ u, T* __restrict__ flux) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp;
+  const int64_t E = m.E_int + m.E_bdy;
+  const T* uf = u + (int64_t)field * m.K * Np;
+  T F[Nfp], tr[Nfp];
+  double2 vn = make_double2(0.0, 0.0);
+  boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr, vn);
+  if (m.conv) {
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T tau = op[L.tau + j];
+      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
+      if (vnj > (T)0) F[j] -= vnj * tr[j];
+    }
+  }
+  T* out = flux + ((int64_t)field * E + e) * Nfp;
+#pragma unroll
+  for (int j = 0; j < Nfp; ++j) out[j] = F[j];
 }
 
 template <int N, typename T, bool ALG1>
@@ -209,24 +302,7 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gg[j] + gS * gg[Nfp + j]);
     }
   } else {
-    const int64_t b = e - m.E_int;
-    const int kb = m.bk[b];
-    const double2 g = m.bgam[b], mu = m.bmu[b];
-    if (m.conv) vn = m.vn[e];
-    const int k = kb & 0x3fffffff, fa = (int)((unsigned)kb >> 30);
-    T v[Np];
-#pragma unroll
-    for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
-    const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
-    T t[Np], c[Np];
-    rotate_to_face<N, T>(v, fa, t, tr1);
-    matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c);
-    decasteljau<N, T>(c, mu);
-    const T gR = (T)g.x, gS = (T)g.y;
-    T gb[2 * Nfp];
-    matvec_sel<kBoth, 2 * Nfp, Np, T>(op + (ALG1 ? L.ubr : L.kbr), c, gb);
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gb[j] + gS * gb[Nfp + j]);
+    boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr1, vn);
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
   }

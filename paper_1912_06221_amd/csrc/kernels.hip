@@ -45,6 +45,109 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
   edge_body<N, T, ALG1>(m, opbase<T>(m), e, blockIdx.y, u, flux);
 }
 
+// Interior edges split by side: a block of two waves takes 64 edges; wave s
+// (s = 0, 1) gathers, rotates, converts and subdivides element s+1 of every
+// edge and applies the columns of the reconstruction operator that act on
+// that side's sub-triangle coefficients.  The operator entries stay
+// wave-uniform (one column slice per wave), the serial chain of each wave is
+// half that of one lane per edge, and the two partial sums meet in LDS.
+// Blocks past the interior range take 128 boundary faces each (mirror-ghost
+// operator, one lane per face).
+constexpr int kSplitTile = 64;
+
+template <int N, typename T, bool ALG1>
+__global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
+                                                                    T* __restrict__ flux, int nb_int) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp, K2 = 2 * Np;
+  __shared__ T part[4 * Nfp][kSplitTile];
+  __shared__ T trace2[Nfp][kSplitTile];
+  const int field = blockIdx.y;
+  const int64_t E = m.E_int + m.E_bdy;
+  const cptr<T> op = opbase<T>(m);
+  const int b = blockIdx.x;
+  if (b >= nb_int) {
+    const int64_t e = m.E_int + (int64_t)(b - nb_int) * (2 * kSplitTile) + threadIdx.x;
+    if (e < E) boundary_body<N, T, ALG1>(m, op, e, field, u, flux);
+    return;
+  }
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's side
+  const int l = threadIdx.x & 63;
+  const int64_t e0 = xcd_block(b, nb_int) * kSplitTile;
+  const bool valid = e0 + l < m.E_int;
+  const int64_t e = valid ? e0 + l : e0;
+  const int2 ef = m.ef[e];
+  const double2 mu = s ? m.mu2[e] : m.mu1[e];
+  const double2 g = m.gam[e];
+  double2 vn = make_double2(0.0, 0.0);
+  if (m.conv) vn = m.vn[e];
+  const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
+  const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
+  const int k = s ? k2 : k1, f = s ? fb : fa;
+  const T* uf = u + (int64_t)field * m.K * Np;
+  T v[Np];
+#pragma unroll
+  for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
+  double D1d = 0.0, D2d = 0.0;
+  if (ALG1) {
+    D1d = m.Delem[k1];
+    D2d = m.Delem[k2];
+  }
+  T t[Np], tr[Nfp], c[Np];
+  rotate_to_face<N, T>(v, f, t, tr);
+  matvec_pf<Np, Np, T>(op + L.n2b, t, c);
+  decasteljau<N, T>(c, mu);
+  // Algorithm 1 reduces to D (U1 - U2) when every edge of the tile has
+  // D1 == D2; both waves see the same tile and take the same branch
+  const bool quad = ALG1 && __ballot(valid && D1d != D2d) != 0;
+  const int base = !ALG1 ? L.kr : (quad ? L.u1r : L.udr);
+  T gg[4 * Nfp];
+  if (quad)
+    matvec_ld<4 * Nfp, Np, K2, T>(op + base + s * Np, c, gg);
+  else
+    matvec_ld<2 * Nfp, Np, K2, T>(op + base + s * Np, c, gg);
+  if (s == 1) {
+    const int R = quad ? 4 * Nfp : 2 * Nfp;
+#pragma unroll
+    for (int r = 0; r < 4 * Nfp; ++r)
+      if (r < R) part[r][l] = gg[r];
+    if (m.conv) {
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j) trace2[j][l] = tr[j];
+    }
+  }
+  __syncthreads();
+  if (s == 1 || !valid) return;
+  const T gR = (T)g.x, gS = (T)g.y;
+  T F[Nfp];
+  if (quad) {
+    const T D1 = (T)D1d, D2 = (T)D2d;
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T a0 = gg[j] + part[j][l], a1 = gg[Nfp + j] + part[Nfp + j][l];
+      const T a2 = gg[2 * Nfp + j] + part[2 * Nfp + j][l], a3 = gg[3 * Nfp + j] + part[3 * Nfp + j][l];
+      F[j] = D1 * (gR * a0 + gS * a1) - D2 * (gR * a2 + gS * a3);
+    }
+  } else {
+    const T D = ALG1 ? (T)D1d : (T)m.Dfield[field];
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j)
+      F[j] = D * (gR * (gg[j] + part[j][l]) + gS * (gg[Nfp + j] + part[Nfp + j][l]));
+  }
+  if (m.conv) {
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T tau = op[L.tau + j];
+      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
+      const T fs = (vnj > (T)0) ? vnj * tr[j] : vnj * trace2[N - j][l];
+      F[j] -= fs;
+    }
+  }
+  T* out = flux + ((int64_t)field * E + e) * Nfp;
+#pragma unroll
+  for (int j = 0; j < Nfp; ++j) out[j] = F[j];
+}
+
 constexpr int kElemBlock = 256;
 
 // Per-element inputs besides the nodal values, loaded ahead of the compute.
@@ -265,6 +368,26 @@ template <int N, typename T>
 hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   const int64_t E = m.E_int + m.E_bdy;
   if (E == 0) return hipSuccess;
+  bool split = m.edge_kernel == EDGE_SPLIT;
+  if (m.edge_kernel == EDGE_AUTO) {
+    // one thread per edge: about 8 waves per SIMD (1024 SIMDs) hide the
+    // latency of its serial chain; below that, or at orders whose register
+    // use leaves few waves resident, the side-split tiles are faster
+    const int64_t lane_waves = (m.E_int * nfields + 63) / 64;
+    split = N >= 5 || lane_waves < 8 * 1024;
+  }
+  if (split) {
+    const int64_t nbi = (m.E_int + kSplitTile - 1) / kSplitTile;
+    const int64_t nbb = (m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile);
+    dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
+    if (m.alg1)
+      hipLaunchKernelGGL((edge_split_kernel<N, T, true>), grid, dim3(2 * kSplitTile), 0, st, m,
+                         (const T*)u, (T*)flux, (int)nbi);
+    else
+      hipLaunchKernelGGL((edge_split_kernel<N, T, false>), grid, dim3(2 * kSplitTile), 0, st, m,
+                         (const T*)u, (T*)flux, (int)nbi);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((E + 255) / 256), (unsigned)nfields);
   if (m.alg1)
     hipLaunchKernelGGL((edge_flux_kernel<N, T, true>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux);
@@ -308,18 +431,19 @@ hipError_t elem_dispatch(const DevMesh& m, int nf, const void* vin, const void* 
   ARDG_DISPATCH_N(elem_launch_t, m, nf, vin, flux, epi, st)
 }
 
-hipError_t launch_edge_flux(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
+hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st) {
-  if (m.edge_mfma) return launch_edge_mfma(m, fp64, nfields, u, flux, st);
-  return fp64 ? edge_dispatch<double>(m, nfields, u, flux, st)
-              : edge_dispatch<float>(m, nfields, u, flux, st);
+  // split-BF16 products exist only on the matrix cores
+  if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) return launch_edge_mfma(m, prec, nfields, u, flux, st);
+  return prec == PREC_FP64 ? edge_dispatch<double>(m, nfields, u, flux, st)
+                           : edge_dispatch<float>(m, nfields, u, flux, st);
 }
 
-hipError_t launch_element(const DevMesh& m, bool fp64, int nfields, const void* vin,
+hipError_t launch_element(const DevMesh& m, int prec, int nfields, const void* vin,
                           const void* flux, const Epilogue& epi, hipStream_t st) {
-  if (m.elem_mfma) return launch_element_mfma(m, fp64, nfields, vin, flux, epi, st);
-  return fp64 ? elem_dispatch<double>(m, nfields, vin, flux, epi, st)
-              : elem_dispatch<float>(m, nfields, vin, flux, epi, st);
+  if (m.elem_mfma || prec == PREC_BF16X3) return launch_element_mfma(m, prec, nfields, vin, flux, epi, st);
+  return prec == PREC_FP64 ? elem_dispatch<double>(m, nfields, vin, flux, epi, st)
+                           : elem_dispatch<float>(m, nfields, vin, flux, epi, st);
 }
 
 template <int N, typename T>

@@ -36,59 +36,73 @@ constexpr int kEdgeTile = 64;   // interior edges per block (one wave)
 //   QUAD   : Algorithm 1, rows (U1R, U1S, U2R, U2S)
 enum EdgeForm { PAIR_K = 0, PAIR_UD = 1, QUAD = 2 };
 
-template <int N, typename T, int FORM, bool CONV>
-__device__ inline void edge_tile_mfma(const DevMesh& m, const T* __restrict__ opg, int field,
-                                      const T* __restrict__ uf, T* __restrict__ out, int nval,
-                                      int k1, int fa, int k2, int fb, double2 mu1, double2 mu2,
-                                      double2 gam, double D1, double D2, T* cb, T* fl,
+template <int N, typename P, int FORM, bool CONV>
+__device__ inline void edge_tile_mfma(const DevMesh& m, const typename Mma<P>::T* __restrict__ opg,
+                                      int field, const typename Mma<P>::T* __restrict__ uf,
+                                      typename Mma<P>::T* __restrict__ out, int nval, int k1, int fa,
+                                      int k2, int fb, double2 mu1, double2 mu2, double2 gam, double D1,
+                                      double D2, typename Mma<P>::T* cb, typename Mma<P>::T* fl,
                                       const int* rot) {
+  using M = Mma<P>;
+  using T = typename M::T;
+  typedef typename M::acc acc_t;
+  typedef typename M::frag frag_t;
+  constexpr int KPL = M::KPL, KS = M::KSTEP;
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp, K2 = 2 * Np;
   constexpr int MT = (Np + 15) / 16;                       // row tiles of the conversion
-  constexpr int KC = (Np + 3) / 4;                         // k steps over one side's nodes
+  constexpr int KC = (Np + KS - 1) / KS;                   // k steps over one side's nodes
   constexpr int RPT = FORM == QUAD ? 4 : 8;                // flux nodes per row tile
   constexpr int MG = (Nfp + RPT - 1) / RPT;                // row tiles of step 4
   constexpr int base = FORM == PAIR_K ? L.kr : (FORM == PAIR_UD ? L.udr : L.u1r);
-  using M = Mma<T>;
-  typedef typename M::acc acc_t;
   const int l = threadIdx.x, col = l & 15, grp = l >> 4;
   const bool valid = l < nval;
 
-  // conversion matrix as A fragments: row 16 mt + col, column 4 c + grp
-  T aN[MT][KC];
+  // conversion matrix as A fragments: row 16 mt + col, columns kidx(c, grp, .)
+  frag_t aN[MT][KC];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      const int i = 16 * mt + col, k = 4 * c + grp;
-      aN[mt][c] = (i < Np && k < Np) ? opg[L.n2b + i * Np + k] : T(0);
+      T v[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int i = 16 * mt + col, k = kidx<M>(c, grp, t);
+        v[t] = (i < Np && k < Np) ? opg[L.n2b + i * Np + k] : T(0);
+      }
+      aN[mt][c] = M::make(v);
     }
   // step-4 operator row held by this lane in tile mt: MFMA row `col`
   const int gi = M::grp_of(col), ri = M::reg_of(col);
 
   acc_t g[4][MG];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
-    for (int mt = 0; mt < MG; ++mt) g[t][mt] = M::zero();
+    for (int mt = 0; mt < MG; ++mt) g[sb][mt] = M::zero();
 
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int kl = s ? k2 : k1, fl_ = s ? fb : fa;
     // 1 + 2: gather, rotate, convert to Bernstein coefficients
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int el = 16 * t + col;
+    for (int sb = 0; sb < 4; ++sb) {
+      const int el = 16 * sb + col;
       const int kk = __shfl(kl, el), ff = __shfl(fl_, el);
       const bool ok = el < nval;
       const T* ue = uf + (int64_t)kk * Np;
-      T bu[KC];
+      frag_t bu[KC];
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
-        const int n = 4 * c + grp;
-        T v = T(0);
-        if (ok && n < Np) v = ue[ff == 1 ? n : rot[(ff >> 1) * Np + n]];
-        bu[c] = v;
+        T v[KPL];
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const int n = kidx<M>(c, grp, t);
+          const int nc = n < Np ? n : 0;
+          const T x = ue[ff == 1 ? nc : rot[(ff >> 1) * Np + nc]];
+          v[t] = (ok && n < Np) ? x : T(0);
+        }
+        bu[c] = M::make(v);
       }
       acc_t b[MT];
 #pragma unroll
@@ -119,8 +133,7 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const T* __restrict__ op
     // 4: this side's columns of the step-4 operator
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      const int k = 4 * c + grp;
-      T a[MG];
+      frag_t a[MG];
 #pragma unroll
       for (int mt = 0; mt < MG; ++mt) {
         int jj, comp;
@@ -131,23 +144,35 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const T* __restrict__ op
           jj = 8 * mt + 2 * gi + (ri >> 1);
           comp = ri & 1;
         }
-        a[mt] = (jj < Nfp && k < Np) ? opg[base + (comp * Nfp + jj) * K2 + s * Np + k] : T(0);
+        T v[KPL];
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const int k = kidx<M>(c, grp, t);
+          v[t] = (jj < Nfp && k < Np) ? opg[base + (comp * Nfp + jj) * K2 + s * Np + k] : T(0);
+        }
+        a[mt] = M::make(v);
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const T bb = (k < Np) ? cb[k * kEdgeTile + 16 * t + col] : T(0);
+      for (int sb = 0; sb < 4; ++sb) {
+        T v[KPL];
 #pragma unroll
-        for (int mt = 0; mt < MG; ++mt) g[t][mt] = M::mma(a[mt], bb, g[t][mt]);
+        for (int t = 0; t < KPL; ++t) {
+          const int k = kidx<M>(c, grp, t);
+          v[t] = (k < Np) ? cb[k * kEdgeTile + 16 * sb + col] : T(0);
+        }
+        const frag_t bb = M::make(v);
+#pragma unroll
+        for (int mt = 0; mt < MG; ++mt) g[sb][mt] = M::mma(a[mt], bb, g[sb][mt]);
       }
     }
     __syncthreads();   // cb is refilled by the other side
   }
 
-  // flux at the diagonal nodes; lane group grp holds nodes of edge 16 t + col
+  // flux at the diagonal nodes; lane group grp holds nodes of edge 16 sb + col
   const T Dc = (T)m.Dfield[field];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int el = 16 * t + col;
+  for (int sb = 0; sb < 4; ++sb) {
+    const int el = 16 * sb + col;
     const bool ok = el < nval;
     const T gR = (T)__shfl(gam.x, el), gS = (T)__shfl(gam.y, el);
     const T d1 = (T)__shfl(D1, el), d2 = (T)__shfl(D2, el);
@@ -156,7 +181,7 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const T* __restrict__ op
       if (FORM == QUAD) {
         const int jj = 4 * mt + grp;
         if (ok && jj < Nfp) {
-          T F = d1 * (gR * g[t][mt][0] + gS * g[t][mt][1]) - d2 * (gR * g[t][mt][2] + gS * g[t][mt][3]);
+          T F = d1 * (gR * g[sb][mt][0] + gS * g[sb][mt][1]) - d2 * (gR * g[sb][mt][2] + gS * g[sb][mt][3]);
           if (CONV) F -= fl[el * Nfp + jj];
           fl[el * Nfp + jj] = F;
         }
@@ -166,7 +191,7 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const T* __restrict__ op
         for (int h = 0; h < 2; ++h) {
           const int jj = 8 * mt + 2 * grp + h;
           if (ok && jj < Nfp) {
-            T F = D * (gR * g[t][mt][2 * h] + gS * g[t][mt][2 * h + 1]);
+            T F = D * (gR * g[sb][mt][2 * h] + gS * g[sb][mt][2 * h + 1]);
             if (CONV) F -= fl[el * Nfp + jj];
             fl[el * Nfp + jj] = F;
           }
@@ -182,9 +207,12 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const T* __restrict__ op
   }
 }
 
-template <int N, typename T, bool ALG1, bool CONV>
-__global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m, const T* __restrict__ u,
-                                                              T* __restrict__ flux, int nb_int) {
+template <int N, typename P, bool ALG1, bool CONV>
+__global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
+                                                              const typename Mma<P>::T* __restrict__ u,
+                                                              typename Mma<P>::T* __restrict__ flux,
+                                                              int nb_int) {
+  using T = typename Mma<P>::T;
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
   __shared__ T cb[Np * kEdgeTile];
@@ -197,7 +225,7 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m, const T
   if (b >= nb_int) {
     // boundary faces: mirror-ghost operator on the vector unit, one lane per face
     const int64_t e = m.E_int + (int64_t)(b - nb_int) * kEdgeTile + l;
-    if (e < E) edge_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   const int64_t e0 = xcd_block(b, nb_int) * kEdgeTile;
@@ -235,19 +263,20 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m, const T
   __syncthreads();
   T* out = flux + ((int64_t)field * E + e0) * Nfp;
   if (!ALG1) {
-    edge_tile_mfma<N, T, PAIR_K, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+    edge_tile_mfma<N, P, PAIR_K, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
                                        D1, D2, cb, fl, rot);
   } else if (__ballot(valid && D1 != D2) == 0) {
-    edge_tile_mfma<N, T, PAIR_UD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+    edge_tile_mfma<N, P, PAIR_UD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
                                         D1, D2, cb, fl, rot);
   } else {
-    edge_tile_mfma<N, T, QUAD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+    edge_tile_mfma<N, P, QUAD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
                                      D1, D2, cb, fl, rot);
   }
 }
 
-template <int N, typename T>
+template <int N, typename P>
 hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
+  using T = typename Mma<P>::T;
   const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
   const int64_t nbb = (m.E_bdy + kEdgeTile - 1) / kEdgeTile;
   if (nbi + nbb == 0) return hipSuccess;
@@ -257,35 +286,39 @@ hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux,
   const int ni = (int)nbi;
   if (m.alg1) {
     if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, T, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
     else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, T, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
   } else {
     if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, T, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
     else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, T, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
   }
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename P>
 hipError_t edge_mfma_dispatch(const DevMesh& m, int nf, const void* u, void* flux, hipStream_t st) {
   switch (m.N) {
-    case 1: return edge_mfma_t<1, T>(m, nf, u, flux, st);
-    case 2: return edge_mfma_t<2, T>(m, nf, u, flux, st);
-    case 3: return edge_mfma_t<3, T>(m, nf, u, flux, st);
-    case 4: return edge_mfma_t<4, T>(m, nf, u, flux, st);
-    case 5: return edge_mfma_t<5, T>(m, nf, u, flux, st);
-    case 6: return edge_mfma_t<6, T>(m, nf, u, flux, st);
+    case 1: return edge_mfma_t<1, P>(m, nf, u, flux, st);
+    case 2: return edge_mfma_t<2, P>(m, nf, u, flux, st);
+    case 3: return edge_mfma_t<3, P>(m, nf, u, flux, st);
+    case 4: return edge_mfma_t<4, P>(m, nf, u, flux, st);
+    case 5: return edge_mfma_t<5, P>(m, nf, u, flux, st);
+    case 6: return edge_mfma_t<6, P>(m, nf, u, flux, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_edge_mfma(const DevMesh& m, bool fp64, int nfields, const void* u, void* flux,
+hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st) {
-  return fp64 ? edge_mfma_dispatch<double>(m, nfields, u, flux, st)
-              : edge_mfma_dispatch<float>(m, nfields, u, flux, st);
+  switch (prec) {
+    case PREC_FP64: return edge_mfma_dispatch<double>(m, nfields, u, flux, st);
+    case PREC_FP32: return edge_mfma_dispatch<float>(m, nfields, u, flux, st);
+    case PREC_BF16X3: return edge_mfma_dispatch<Bf16x3>(m, nfields, u, flux, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace ardg

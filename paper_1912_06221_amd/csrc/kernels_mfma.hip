@@ -34,25 +34,31 @@ namespace ardg {
 constexpr int kMfmaTile = 64;     // elements per block
 constexpr int kMfmaThreads = 256; // four waves, one 16-element sub-tile each
 
-template <int N, typename T, bool CONV>
-__global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, const T* __restrict__ vin,
-                                                                    const T* __restrict__ flux,
+template <int N, typename P, bool CONV>
+__global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
+                                                                    const typename Mma<P>::T* __restrict__ vin,
+                                                                    const typename Mma<P>::T* __restrict__ flux,
                                                                     Epilogue epi) {
+  using M = Mma<P>;
+  using T = typename M::T;
+  typedef typename M::acc acc_t;
+  typedef typename M::frag frag_t;
+  constexpr int KPL = M::KPL, KS = M::KSTEP;
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
   constexpr int MT = (Np + 15) / 16;     // row tiles of nodes
-  constexpr int KC = (Np + 3) / 4;       // K steps over nodes
+  constexpr int KC = (Np + KS - 1) / KS; // K steps over nodes
   constexpr int NJ = 3 * Nfp;            // face values lifted
-  constexpr int KL = (NJ + 3) / 4;       // K steps over face values
+  constexpr int KL = (NJ + KS - 1) / KS; // K steps over face values
   constexpr int RW = 16 * MT;            // padded node rows
+  constexpr int KW = KS * KC;            // padded node columns (B fragments)
+  constexpr int SQ = (RW > KW ? RW : KW) * 16;
   constexpr bool kPre = N <= 4;
-  using M = Mma<T>;
-  typedef typename M::acc acc_t;
   __shared__ T sh[kMfmaTile * Np];
-  __shared__ T sqa[4][4][RW * 16];       // per wave: q_x, q_y, w_r, w_s of its sub-tile, [node][column]
+  __shared__ T sqa[4][4][SQ];            // per wave: q_x, q_y, w_r, w_s of its sub-tile, [node][column]
   const int l = threadIdx.x & 63, col = l & 15, grp = l >> 4;
   const int st = threadIdx.x >> 6;       // this wave's sub-tile
-  T (*sq)[RW * 16] = sqa[st];
+  T (*sq)[SQ] = sqa[st];
   const int64_t k0 = xcd_block(blockIdx.x, gridDim.x) * kMfmaTile;
   const int field = blockIdx.y;
   const int64_t E = m.E_int + m.E_bdy;
@@ -71,44 +77,56 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, c
   TileIO<TileShape<N, kMfmaTile, kMfmaThreads>::Q> io;
   tile_begin<N, T, kMfmaTile, kMfmaThreads>(m, k0, field, vin, epi, sh, io, kPre);
 
-  // face fluxes in the B layout of the lift: value q = 4c + grp is node q % Nfp
-  // of face q / Nfp, read from its edge (reversed and negated on side 2)
-  // (unconditional loads from clamped indices, masked afterwards)
-  T G[KL];
+  // face fluxes in the B layout of the lift: value q = kidx(c, grp, t) is node
+  // q % Nfp of face q / Nfp, read from its edge (reversed and negated on side
+  // 2).  Loads are unconditional from clamped indices; the mask multiplies
+  // instead of selecting, so no load is sunk into a branch of its own.
+  T G[KL][KPL];
 #pragma unroll
-  for (int c = 0; c < KL; ++c) {
-    const int q = 4 * c + grp;
-    const int qc = q < NJ ? q : 0;
-    const int f = qc / Nfp, jj = qc - f * Nfp;
-    const int cd = (f == 0) ? code[0] : (f == 1 ? code[1] : code[2]);
-    const bool side2 = cd & 1;
-    const T x = flux[((int64_t)field * E + (cd >> 1)) * Nfp + (side2 ? Nfp - 1 - jj : jj)];
-    // the mask multiplies instead of selecting, so the load is not sunk
-    // into a branch of its own
-    const T sgn = (valid && q < NJ) ? (side2 ? T(-1) : T(1)) : T(0);
-    G[c] = sgn * x;
-  }
+  for (int c = 0; c < KL; ++c)
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      const int q = kidx<M>(c, grp, t);
+      const int qc = q < NJ ? q : 0;
+      const int f = qc / Nfp, jj = qc - f * Nfp;
+      const int cd = (f == 0) ? code[0] : (f == 1 ? code[1] : code[2]);
+      const bool side2 = cd & 1;
+      const T x = flux[((int64_t)field * E + (cd >> 1)) * Nfp + (side2 ? Nfp - 1 - jj : jj)];
+      const T sgn = (valid && q < NJ) ? (side2 ? T(-1) : T(1)) : T(0);
+      G[c][t] = sgn * x;
+    }
 
-  // operator fragments: row 16 mt + col, column 4 c + grp
-  T aDr[MT][KC], aDs[MT][KC], aL[MT][KL];
+  // operator fragments: row 16 mt + col, columns kidx(c, grp, .)
+  frag_t aDr[MT][KC], aDs[MT][KC], aL[MT][KL];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int row = 16 * mt + col;
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      const int kk = 4 * c + grp;
-      const bool ok = row < Np && kk < Np;
-      aDr[mt][c] = ok ? opg[L.dr + row * Np + kk] : T(0);
-      aDs[mt][c] = ok ? opg[L.ds + row * Np + kk] : T(0);
+      T vr[KPL], vs[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int kk = kidx<M>(c, grp, t);
+        const bool ok = row < Np && kk < Np;
+        vr[t] = ok ? opg[L.dr + row * Np + kk] : T(0);
+        vs[t] = ok ? opg[L.ds + row * Np + kk] : T(0);
+      }
+      aDr[mt][c] = M::make(vr);
+      aDs[mt][c] = M::make(vs);
     }
 #pragma unroll
     for (int c = 0; c < KL; ++c) {
-      const int kk = 4 * c + grp;
-      aL[mt][c] = (row < Np && kk < NJ) ? opg[L.lift + row * NJ + kk] : T(0);
+      T vl[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int kk = kidx<M>(c, grp, t);
+        vl[t] = (row < Np && kk < NJ) ? opg[L.lift + row * NJ + kk] : T(0);
+      }
+      aL[mt][c] = M::make(vl);
     }
   }
   // reference coordinates (+1) of the nodes this lane touches (convection)
-  T r1a[MT][4], s1a[MT][4], r1f[KL], s1f[KL];
+  T r1a[MT][4], s1a[MT][4], r1f[KL][KPL], s1f[KL][KPL];
   if (CONV) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -120,14 +138,16 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, c
         s1a[mt][r] = opg[L.ns + nc] + T(1);
       }
 #pragma unroll
-    for (int c = 0; c < KL; ++c) {
-      const int q = 4 * c + grp;
-      const int qc = q < NJ ? q : 0;
-      const int f = qc / Nfp;
-      const int nd = fnode(N, f, qc - f * Nfp);
-      r1f[c] = opg[L.nr + nd] + T(1);
-      s1f[c] = opg[L.ns + nd] + T(1);
-    }
+    for (int c = 0; c < KL; ++c)
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int q = kidx<M>(c, grp, t);
+        const int qc = q < NJ ? q : 0;
+        const int f = qc / Nfp;
+        const int nd = fnode(N, f, qc - f * Nfp);
+        r1f[c][t] = opg[L.nr + nd] + T(1);
+        s1f[c][t] = opg[L.ns + nd] + T(1);
+      }
   }
   __syncthreads();
 
@@ -138,12 +158,17 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, c
   ElemVel ev = {};
   if (CONV) ev = elem_vel(m.vel, p1, gm);
 
-  // u as B fragments: node 4c + grp of element `col`
-  T bu[KC];
+  // u as B fragments: nodes kidx(c, grp, .) of element `col`
+  frag_t bu[KC];
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
-    const int n = 4 * c + grp;
-    bu[c] = (valid && n < Np) ? sh[el * Np + n] : T(0);
+    T v[KPL];
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      const int n = kidx<M>(c, grp, t);
+      v[t] = (valid && n < Np) ? sh[el * Np + n] : T(0);
+    }
+    bu[c] = M::make(v);
   }
   acc_t ur[MT], us[MT];
 #pragma unroll
@@ -182,12 +207,18 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, c
 
   acc_t rhs[MT];
   {
-    T bw[KC], bs[KC];
+    frag_t bw[KC], bs[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      const int n = 4 * c + grp;
-      bw[c] = sq[2][n * 16 + col];
-      bs[c] = sq[3][n * 16 + col];
+      T vw[KPL], vs[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int n = kidx<M>(c, grp, t);
+        vw[t] = n < RW ? sq[2][n * 16 + col] : T(0);
+        vs[t] = n < RW ? sq[3][n * 16 + col] : T(0);
+      }
+      bw[c] = M::make(vw);
+      bs[c] = M::make(vs);
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -201,23 +232,28 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, c
   }
 
   // face values (1/J) (G - D (sJ n).q (+ (sJ n).v u)) as B fragments
-  T bj[KL];
+  frag_t bj[KL];
   const T iJ = (T)gm.iJ;
 #pragma unroll
   for (int c = 0; c < KL; ++c) {
-    const int q = 4 * c + grp;
-    const int qc = q < NJ ? q : 0;
-    const int f = qc / Nfp;
-    const int nd = fnode(N, f, qc - f * Nfp);
-    const double2 sn = face_sjn(gm, f);
-    const T nx = (T)sn.x, ny = (T)sn.y;
-    T jv = G[c] - D * (nx * sq[0][nd * 16 + col] + ny * sq[1][nd * 16 + col]);
-    if (CONV) {
-      const T vx = (T)ev.x1 + r1f[c] * (T)ev.xr + s1f[c] * (T)ev.xs;
-      const T vy = (T)ev.y1 + r1f[c] * (T)ev.yr + s1f[c] * (T)ev.ys;
-      jv += (nx * vx + ny * vy) * sh[el * Np + nd];
+    T vj[KPL];
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      const int q = kidx<M>(c, grp, t);
+      const int qc = q < NJ ? q : 0;
+      const int f = qc / Nfp;
+      const int nd = fnode(N, f, qc - f * Nfp);
+      const double2 sn = face_sjn(gm, f);
+      const T nx = (T)sn.x, ny = (T)sn.y;
+      T jv = G[c][t] - D * (nx * sq[0][nd * 16 + col] + ny * sq[1][nd * 16 + col]);
+      if (CONV) {
+        const T vx = (T)ev.x1 + r1f[c][t] * (T)ev.xr + s1f[c][t] * (T)ev.xs;
+        const T vy = (T)ev.y1 + r1f[c][t] * (T)ev.yr + s1f[c][t] * (T)ev.ys;
+        jv += (nx * vx + ny * vy) * sh[el * Np + nd];
+      }
+      vj[t] = (valid && q < NJ) ? iJ * jv : T(0);
     }
-    bj[c] = (valid && q < NJ) ? iJ * jv : T(0);
+    bj[c] = M::make(vj);
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -236,37 +272,42 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m, c
   tile_end<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre);
 }
 
-template <int N, typename T>
+template <int N, typename P>
 hipError_t elem_mfma_t(const DevMesh& m, int nfields, const void* vin, const void* flux,
                        const Epilogue& epi, hipStream_t st) {
+  using T = typename Mma<P>::T;
   dim3 grid((unsigned)((m.K + kMfmaTile - 1) / kMfmaTile), (unsigned)nfields);
   if (m.conv)
-    hipLaunchKernelGGL((element_mfma_kernel<N, T, true>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, true>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi);
   else
-    hipLaunchKernelGGL((element_mfma_kernel<N, T, false>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, false>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename P>
 hipError_t elem_mfma_dispatch(const DevMesh& m, int nf, const void* vin, const void* flux,
                               const Epilogue& epi, hipStream_t st) {
   switch (m.N) {
-    case 1: return elem_mfma_t<1, T>(m, nf, vin, flux, epi, st);
-    case 2: return elem_mfma_t<2, T>(m, nf, vin, flux, epi, st);
-    case 3: return elem_mfma_t<3, T>(m, nf, vin, flux, epi, st);
-    case 4: return elem_mfma_t<4, T>(m, nf, vin, flux, epi, st);
-    case 5: return elem_mfma_t<5, T>(m, nf, vin, flux, epi, st);
-    case 6: return elem_mfma_t<6, T>(m, nf, vin, flux, epi, st);
+    case 1: return elem_mfma_t<1, P>(m, nf, vin, flux, epi, st);
+    case 2: return elem_mfma_t<2, P>(m, nf, vin, flux, epi, st);
+    case 3: return elem_mfma_t<3, P>(m, nf, vin, flux, epi, st);
+    case 4: return elem_mfma_t<4, P>(m, nf, vin, flux, epi, st);
+    case 5: return elem_mfma_t<5, P>(m, nf, vin, flux, epi, st);
+    case 6: return elem_mfma_t<6, P>(m, nf, vin, flux, epi, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_element_mfma(const DevMesh& m, bool fp64, int nfields, const void* vin,
+hipError_t launch_element_mfma(const DevMesh& m, int prec, int nfields, const void* vin,
                                const void* flux, const Epilogue& epi, hipStream_t st) {
-  return fp64 ? elem_mfma_dispatch<double>(m, nfields, vin, flux, epi, st)
-              : elem_mfma_dispatch<float>(m, nfields, vin, flux, epi, st);
+  switch (prec) {
+    case PREC_FP64: return elem_mfma_dispatch<double>(m, nfields, vin, flux, epi, st);
+    case PREC_FP32: return elem_mfma_dispatch<float>(m, nfields, vin, flux, epi, st);
+    case PREC_BF16X3: return elem_mfma_dispatch<Bf16x3>(m, nfields, vin, flux, epi, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace ardg

@@ -10,6 +10,13 @@ Tolerances:
 * FP32 (operators and arithmetic in FP32, built from FP64): the same
   measures with 2e-4 (FP32 rounding ~6e-8 amplified by the operator norm, up
   to ~1e3 at N=6).  The FP64 RK update keeps state errors at that level.
+* BF16X3 (FP32 data, products on the BF16 matrix cores as hi*hi + hi*lo +
+  lo*hi with hi = bf16(x), lo = bf16(x - hi), FP32 accumulation): each
+  product keeps ~16 significant bits of its operands, a relative error of
+  about 2^-16 = 1.5e-5 per term instead of FP32's 2^-24; the same
+  amplification allowance as for FP32 (2e-4 / 2^-24 ~ 3.4e3) gives 5e-2 on
+  the max-norm measures.  The state after RK steps (FP64 update, rhs errors
+  scaled by dt) is held to the FP32 bound.
 """
 import math
 
@@ -23,6 +30,9 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 2e-4
+TOLBF = 5e-2
+
+PRECS = {"fp64": (0, 1e-12), "fp32": (1, 2e-4), "bf16x3": (2, 5e-2)}
 
 
 def _flux_oracle(pr, u, nfields):
@@ -63,7 +73,7 @@ def _ids(c):
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_edge_flux_and_rhs_parity_random(case, prec):
     import torch
     from paper_1912_06221_amd import ardg
@@ -76,14 +86,15 @@ def test_edge_flux_and_rhs_parity_random(case, prec):
     pr = oracle_problem(mesh, N, D_mode, D, vel, nf)
     u = W.random_nodal((nf, mesh.K, ops.Np), seed=m + N)
     dt = torch.float64 if prec == "fp64" else torch.float32
-    p = ardg.FP64 if prec == "fp64" else ardg.FP32
-    tol = TOL64 if prec == "fp64" else TOL32
+    p, tol = PRECS[prec]
     ud = to_dev(u, dt)
     flux = torch.empty((nf, lm.E, ops.Nfp), dtype=dt, device=ud.device)
     lm.edge_flux_eval(ud, flux, precision=p, nfields=nf)
     Fo = _flux_oracle(pr, u, nf)
     Fg = to_np(flux)
-    assert np.abs(Fg - Fo).max() <= tol * np.abs(Fo).max()
+    ef = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+    print(f"  flux rel err {ef:.2e}", flush=True)
+    assert ef <= tol
     rhs = torch.empty_like(ud)
     lm.rhs_eval(ud, rhs, precision=p, nfields=nf)
     ro = pr.rhs(u)
@@ -135,7 +146,7 @@ def test_empty_and_tiny_meshes():
 
 
 @pytest.mark.parametrize("scheme", ["rk4", "lserk"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_time_stepping_heat_8x8(scheme, prec):
     """The plain heat problem: 8x8x2 unjittered, N=2, D=1,
     u0 = sin(pi x) sin(pi y), 100 steps; state parity with the oracle and the
@@ -156,9 +167,11 @@ def test_time_stepping_heat_8x8(scheme, prec):
     for _ in range(nsteps):
         uo = step(pr.rhs, uo, dt)
     sch = ardg.RK4 if scheme == "rk4" else ardg.LSERK54
-    p = ardg.FP64 if prec == "fp64" else ardg.FP32
+    p = PRECS[prec][0]
     ud = to_dev(u0[None])
     work = ardg.alloc_workspace(lm.workspace_bytes(sch, p, 1), ud.device)
+    # capture the graph ahead (ardg_rk_prepare), then replay it
+    lm.rk_prepare(ud, work, dt, nsteps, scheme=sch, precision=p)
     lm.rk_step(ud, work, dt, nsteps, scheme=sch, precision=p)
     ug = to_np(ud)[0]
     rel = mass_norm(pr, ug - uo) / mass_norm(pr, uo)
@@ -230,9 +243,10 @@ def _blocks_D(mesh):
                          ids=lambda c: f"m{c[0]}-N{c[1]}-{c[2]}-{'conv' if c[3] else 'diff'}")
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
-    """The kernel variants -- default (thread-per-edge edge kernel, matrix-core
-    element kernel), all thread-per-item, all matrix-core -- compute the same
-    flux and RHS (to rounding), each matching the oracle."""
+    """The kernel variants -- default (edge kernel chosen by grid size,
+    matrix-core element kernel), edge tiles split by side, one thread per
+    edge / per element, all matrix-core -- compute the same flux and RHS (to
+    rounding), each matching the oracle."""
     import torch
     from paper_1912_06221_amd import ardg
     m, N, dk, vel = case
@@ -245,7 +259,8 @@ def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
     p = ardg.FP64 if prec == "fp64" else ardg.FP32
     tol = TOL64 if prec == "fp64" else TOL32
     outs = {}
-    variants = {"default": (None, None), "valu": ("valu", "valu"), "mfma": ("mfma", "mfma")}
+    variants = {"default": (None, None), "split": ("split", None), "lane": ("lane", "valu"),
+                "mfma": ("mfma", "mfma")}
     for variant, (edge_k, elem_k) in variants.items():
         for var, val in (("ARDG_EDGE_KERNEL", edge_k), ("ARDG_ELEMENT_KERNEL", elem_k)):
             if val is None:
@@ -267,3 +282,19 @@ def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
         er = np.abs(rg - ro).max() / np.abs(ro).max()
         print(f"  {variant}: flux {ef:.2e} rhs {er:.2e}", flush=True)
         assert ef <= tol and er <= tol
+
+
+def test_stage_timing_hook():
+    """The timing hook returns positive per-kernel durations and leaves the
+    state finite."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    print("stage timing", flush=True)
+    mesh = W.split_square_mesh(16, 0.2, seed=3)
+    ops, lm = library_mesh(mesh, 3, "const", 1.0, None, 1)
+    u = to_dev(W.random_nodal((1, mesh.K, ops.Np), seed=2))
+    for p in (ardg.FP64, ardg.FP32, ardg.BF16X3):
+        work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, p, 1), u.device)
+        te, tl = lm.stage_timing(u, work, 1e-6, 8, scheme=ardg.RK4, precision=p)
+        assert te > 0 and tl > 0
+    lm.check(u)
