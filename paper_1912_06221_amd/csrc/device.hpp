@@ -15,9 +15,13 @@ constexpr int kMaxFields = 16;
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 
 // Offsets of the packed constant operators (same layout in FP64 and FP32).
+// b2n: Bernstein coefficients -> nodal values; drb, dsb: Dr and Ds acting on
+// Bernstein coefficients (Dr b2n, Ds b2n); bf2n: 1D Bernstein coefficients of
+// a face -> values at its LGL nodes.
 struct OpLayout {
   int Np, Nfp;
-  int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, drsh, lift, tau, nr, ns, total;
+  int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, drsh, lift, tau, nr, ns;
+  int b2n, drb, dsb, bf2n, total;
   __host__ __device__ constexpr OpLayout(int N)
       : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
         n2b(0),
@@ -40,7 +44,11 @@ struct OpLayout {
         tau(lift + Np * 3 * Nfp),
         nr(tau + Nfp),
         ns(nr + Np),
-        total(ns + Np) {}
+        b2n(ns + Np),
+        drb(b2n + Np * Np),
+        dsb(drb + Np * Np),
+        bf2n(dsb + Np * Np),
+        total(bf2n + Nfp * Nfp) {}
 };
 
 // Edge kernel implementations.
@@ -69,6 +77,7 @@ struct DevMesh {
   int alg1 = 0;                   // element-wise D (Algorithm 1)
   int elem_mfma = 1;              // element kernel on the matrix cores
   int edge_kernel = EDGE_AUTO;    // EdgeKernel
+  int bern = 0;                   // stage vectors as Bernstein coefficients where the kernels allow
   int conv = 0;                   // convective term on
   double Dfield[kMaxFields] = {};
   double vel[6] = {};             // v = (p0 + p2 x + p3 y, p1 + p4 x + p5 y)
@@ -99,10 +108,13 @@ struct BatchProb {
 };
 
 // Edge fluxes of all interior and boundary edges for nfields fields.
-hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
+// bern: the stage input holds Bernstein coefficients (else nodal values).
+hipError_t launch_edge_flux(const DevMesh& m, int prec, bool bern, int nfields, const void* u, void* flux,
                             hipStream_t st);
 // Element volume + LIFT of the fluxes + epilogue.
-hipError_t launch_element(const DevMesh& m, int prec, int nfields, const void* vin,
+// bern: the stage input holds Bernstein coefficients, and the next stage
+// input (epi.vnext) is written as Bernstein coefficients too.
+hipError_t launch_element(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
                           const void* flux, const Epilogue& epi, hipStream_t st);
 // Batched (persistent) kernels over work items (problem, tile).  tile is the
 // number of edges / elements per item and the block size (64, 128 or 256);
@@ -123,9 +135,13 @@ hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int ni
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st);
 // Element kernel on the matrix cores (same contract as launch_element).
-hipError_t launch_element_mfma(const DevMesh& m, int prec, int nfields, const void* vin,
+hipError_t launch_element_mfma(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
                                const void* flux, const Epilogue& epi, hipStream_t st);
 
+// Bernstein coefficients of nodal data (double or float in, double or float
+// out): the first stage input when stage vectors are kept in Bernstein form.
+hipError_t launch_to_bernstein(const DevMesh& m, bool fp64_in, bool fp64_out, int nfields, const void* u,
+                               void* out, hipStream_t st);
 // Copy an FP64 state into an FP32 copy (stage input of the FP32 mode).
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // Count non-finite values of an FP64 array into *count_dev (int).

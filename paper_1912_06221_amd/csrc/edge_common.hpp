@@ -13,89 +13,70 @@
 
 namespace ardg {
 
-// y_v = A x_v (v < NV) for a constant row-major ROWS x COLS operator A.  The
-// entries are wave-uniform scalar loads feeding scalar-operand FMAs, taken in
-// chunks of at most CH entries walked row by row: the loads of the next chunk
-// are issued before the FMAs of the current one, so their latency is covered
-// by arithmetic, while the fence between chunks keeps at most two chunks in
-// SGPRs (without it the whole operator is hoisted into SGPRs and spilled).
-// With NV = 2 every loaded entry feeds two vectors.
-template <int ROWS, int COLS, int NV, typename T, typename XA, typename YA>
-__device__ inline void matvec_n(cptr<T> A0, XA x, YA y) {
-  constexpr int CH = sizeof(T) == 8 ? 12 : 16;
-  constexpr int NCH = (COLS + CH - 1) / CH;
-  constexpr int NSTEP = ROWS * NCH;
-  T buf[2][CH];
+// y_v = A x_v (v < NV) for the ROWS x COLS block of a constant row-major
+// operator with leading dimension LD.  The entries are wave-uniform scalar
+// loads feeding scalar-operand FMAs, walked in steps of RB rows x CC columns
+// (RB*CC <= 12 entries): the RB rows' accumulators are
+// independent, so consecutive FMAs do not wait on each other, and the loads
+// of the next step are issued before the FMAs of the current one, so their
+// latency is covered by arithmetic.  The fence between steps keeps at most
+// two steps of entries in SGPRs (without it the whole operator is hoisted
+// into SGPRs and spilled).  With NV = 2 every loaded entry feeds two vectors.
+template <int ROWS, int COLS, int LD, int NV, typename T, typename XA, typename YA>
+__device__ inline void matvec_blk(cptr<T> A0, XA x, YA y) {
+  constexpr int E = 12;
+  constexpr int RB = ROWS < 4 ? ROWS : 4;
+  constexpr int CC = E / RB;
+  constexpr int NRB = (ROWS + RB - 1) / RB;
+  constexpr int NCC = (COLS + CC - 1) / CC;
+  constexpr int NSTEP = NRB * NCC;
+  T buf[2][RB][CC];
   {
     const cptr<T> A = fresh(A0);
 #pragma unroll
-    for (int q = 0; q < CH && q < COLS; ++q) buf[0][q] = A[q];
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < CC; ++q)
+        if (r < ROWS && q < COLS) buf[0][r][q] = A[r * LD + q];
   }
-  T acc[NV];
+  T acc[NV][RB];
 #pragma unroll
   for (int st = 0; st < NSTEP; ++st) {
-    const int r = st / NCH, ch = st % NCH;
-    const int q0 = ch * CH;
-    const int qn = (COLS - q0) < CH ? (COLS - q0) : CH;
+    const int r0 = (st / NCC) * RB, q0 = (st % NCC) * CC;
+    const bool first = (st % NCC) == 0, last = (st % NCC) == NCC - 1;
     row_fence();
     if (st + 1 < NSTEP) {
-      const int r1 = (st + 1) / NCH, c1 = (st + 1) % NCH;
-      const int p0 = c1 * CH;
-      const int pn = (COLS - p0) < CH ? (COLS - p0) : CH;
+      const int r1 = ((st + 1) / NCC) * RB, q1 = ((st + 1) % NCC) * CC;
       const cptr<T> A = fresh(A0);
 #pragma unroll
-      for (int q = 0; q < CH; ++q)
-        if (q < pn) buf[(st + 1) & 1][q] = A[r1 * COLS + p0 + q];
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < CC; ++q)
+          if (r1 + r < ROWS && q1 + q < COLS) buf[(st + 1) & 1][r][q] = A[(r1 + r) * LD + q1 + q];
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      T s = (ch == 0) ? buf[st & 1][0] * x[v][q0] : fma(buf[st & 1][0], x[v][q0], acc[v]);
+    for (int q = 0; q < CC; ++q)
 #pragma unroll
-      for (int q = 1; q < CH; ++q)
-        if (q < qn) s = fma(buf[st & 1][q], x[v][q0 + q], s);
-      acc[v] = s;
-      if (ch == NCH - 1) y[v][r] = s;
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (r0 + r < ROWS && q0 + q < COLS) {
+            const T a = buf[st & 1][r][q];
+            acc[v][r] = (first && q == 0) ? a * x[v][q0] : fma(a, x[v][q0 + q], acc[v][r]);
+          }
+    if (last) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (r0 + r < ROWS) y[v][r0 + r] = acc[v][r];
     }
   }
 }
 
-// y = A x for the ROWS x COLS block of a row-major operator with leading
-// dimension LD (a column slice of a wider matrix), chunk-pipelined like
-// matvec_n.
-template <int ROWS, int COLS, int LD, typename T>
-__device__ inline void matvec_ld(cptr<T> A0, const T* x, T* y) {
-  constexpr int CH = sizeof(T) == 8 ? 12 : 16;
-  constexpr int NCH = (COLS + CH - 1) / CH;
-  constexpr int NSTEP = ROWS * NCH;
-  T buf[2][CH];
-  {
-    const cptr<T> A = fresh(A0);
-#pragma unroll
-    for (int q = 0; q < CH && q < COLS; ++q) buf[0][q] = A[q];
-  }
-  T acc = T(0);
-#pragma unroll
-  for (int st = 0; st < NSTEP; ++st) {
-    const int r = st / NCH, ch = st % NCH;
-    const int q0 = ch * CH;
-    const int qn = (COLS - q0) < CH ? (COLS - q0) : CH;
-    row_fence();
-    if (st + 1 < NSTEP) {
-      const int r1 = (st + 1) / NCH, c1 = (st + 1) % NCH;
-      const int p0 = c1 * CH;
-      const int pn = (COLS - p0) < CH ? (COLS - p0) : CH;
-      const cptr<T> A = fresh(A0);
-#pragma unroll
-      for (int q = 0; q < CH; ++q)
-        if (q < pn) buf[(st + 1) & 1][q] = A[r1 * LD + p0 + q];
-    }
-    T sum = (ch == 0) ? buf[st & 1][0] * x[q0] : fma(buf[st & 1][0], x[q0], acc);
-#pragma unroll
-    for (int q = 1; q < CH; ++q)
-      if (q < qn) sum = fma(buf[st & 1][q], x[q0 + q], sum);
-    acc = sum;
-    if (ch == NCH - 1) y[r] = sum;
-  }
+template <int ROWS, int COLS, int NV, typename T, typename XA, typename YA>
+__device__ inline void matvec_n(cptr<T> A0, XA x, YA y) {
+  matvec_blk<ROWS, COLS, COLS, NV, T>(A0, x, y);
 }
 
 // single-vector views for matvec_n: v[0][q] == p[q]
@@ -108,6 +89,12 @@ struct OneVec {
 template <int ROWS, int COLS, typename T>
 __device__ inline void matvec_pf(cptr<T> A0, const T* x, T* y) {
   matvec_n<ROWS, COLS, 1, T>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
+}
+
+// column slice of a wider row-major operator (leading dimension LD)
+template <int ROWS, int COLS, int LD, typename T>
+__device__ inline void matvec_ld(cptr<T> A0, const T* x, T* y) {
+  matvec_blk<ROWS, COLS, LD, 1, T>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
 }
 
 // y = A x with one operator row in flight at a time (no prefetch): the row
@@ -163,6 +150,19 @@ __device__ inline void rotate_to_face(const T* v, int f, T* t, T* trace) {
   for (int j = 0; j <= N; ++j) trace[j] = t[lat(N, N - j, j)];
 }
 
+// The trace of a Bernstein-form polynomial on the hypotenuse of its
+// (rotated) reference triangle: the face's Nfp coefficients, counter-
+// clockwise, mapped to the values at the face's LGL nodes (in place).
+template <int N, typename T>
+__device__ inline void face_bernstein_to_nodal(cptr<T> op, T* tr) {
+  constexpr OpLayout L(N);
+  constexpr int Nfp = N + 1;
+  T y[Nfp];
+  matvec<Nfp, Nfp, T>(op + L.bf2n, tr, y);
+#pragma unroll
+  for (int j = 0; j < Nfp; ++j) tr[j] = y[j];
+}
+
 // Pipelined products where registers allow it (moderate orders), the
 // one-row-at-a-time form otherwise.
 template <bool PF, int ROWS, int COLS, typename T>
@@ -177,7 +177,7 @@ __device__ inline void matvec_sel(cptr<T> A0, const T* x, T* y) {
 // element's sub-triangle on its mirror-ghost rhombus and the boundary
 // reconstruction operator.  F receives sJ * flux, trace the element's values
 // on the face, vn the stored n.v (convection).
-template <int N, typename T, bool ALG1>
+template <int N, typename T, bool ALG1, bool BERN>
 __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ uf, T* F, T* trace, double2& vn) {
   constexpr OpLayout L(N);
@@ -193,7 +193,13 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
   const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
   T t[Np], c[Np];
   rotate_to_face<N, T>(v, fa, t, trace);
-  matvec<Np, Np, T>(op + L.n2b, t, c);
+  if (BERN) {
+#pragma unroll
+    for (int n = 0; n < Np; ++n) c[n] = t[n];
+    if (m.conv) face_bernstein_to_nodal<N, T>(op, trace);
+  } else {
+    matvec<Np, Np, T>(op + L.n2b, t, c);
+  }
   decasteljau<N, T>(c, mu);
   const T gR = (T)g.x, gS = (T)g.y;
   T gb[2 * Nfp];
@@ -204,7 +210,7 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
 
 // Boundary face e with its upwind convective flux (u+ = 0 outside), written
 // to the flux array.
-template <int N, typename T, bool ALG1>
+template <int N, typename T, bool ALG1, bool BERN>
 __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -213,7 +219,7 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   const T* uf = u + (int64_t)field * m.K * Np;
   T F[Nfp], tr[Nfp];
   double2 vn = make_double2(0.0, 0.0);
-  boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr, vn);
+  boundary_flux<N, T, ALG1, BERN>(m, op, e, field, uf, F, tr, vn);
   if (m.conv) {
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
@@ -227,7 +233,10 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   for (int j = 0; j < Nfp; ++j) out[j] = F[j];
 }
 
-template <int N, typename T, bool ALG1>
+// One lane per edge.  BERN: the stage input holds Bernstein coefficients
+// (the conversion to Bernstein form is skipped; rotation is the same index
+// permutation), else nodal values.
+template <int N, typename T, bool ALG1, bool BERN>
 __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                  const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -263,7 +272,15 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       for (int n = 0; n < Np; ++n) v[1][n] = uf[(int64_t)k2 * Np + n];
       rotate_to_face<N, T>(v[0], fa, t[0], tr1);
       rotate_to_face<N, T>(v[1], fb, t[1], tr2);
-      matvec_n<Np, Np, 2, T>(op + L.n2b, t, c);
+      if (BERN) {
+#pragma unroll
+        for (int n = 0; n < Np; ++n) {
+          c[0][n] = t[0][n];
+          c[1][n] = t[1][n];
+        }
+      } else {
+        matvec_n<Np, Np, 2, T>(op + L.n2b, t, c);
+      }
     } else {
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
@@ -272,8 +289,17 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
 #pragma unroll
         for (int n = 0; n < Np; ++n) v[n] = uf[kk * Np + n];
         rotate_to_face<N, T>(v, sd ? fb : fa, t, sd ? tr2 : tr1);
-        matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c[sd]);
+        if (BERN) {
+#pragma unroll
+          for (int n = 0; n < Np; ++n) c[sd][n] = t[n];
+        } else {
+          matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c[sd]);
+        }
       }
+    }
+    if (BERN && m.conv) {
+      face_bernstein_to_nodal<N, T>(op, tr1);
+      face_bernstein_to_nodal<N, T>(op, tr2);
     }
     decasteljau<N, T>(c[0], mu1);
     decasteljau<N, T>(c[1], mu2);
@@ -302,7 +328,7 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gg[j] + gS * gg[Nfp + j]);
     }
   } else {
-    boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr1, vn);
+    boundary_flux<N, T, ALG1, BERN>(m, op, e, field, uf, F, tr1, vn);
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
   }

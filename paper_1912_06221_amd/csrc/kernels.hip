@@ -37,12 +37,12 @@
 
 namespace ardg {
 
-template <int N, typename T, bool ALG1>
+template <int N, typename T, bool ALG1, bool BERN>
 __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __restrict__ u,
                                                         T* __restrict__ flux) {
   const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (e >= m.E_int + m.E_bdy) return;
-  edge_body<N, T, ALG1>(m, opbase<T>(m), e, blockIdx.y, u, flux);
+  edge_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, blockIdx.y, u, flux);
 }
 
 // Interior edges split by side: a block of two waves takes 64 edges; wave s
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
 // operator, one lane per face).
 constexpr int kSplitTile = 64;
 
-template <int N, typename T, bool ALG1>
+template <int N, typename T, bool ALG1, bool BERN>
 __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
                                                                     T* __restrict__ flux, int nb_int) {
   constexpr OpLayout L(N);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, c
   const int b = blockIdx.x;
   if (b >= nb_int) {
     const int64_t e = m.E_int + (int64_t)(b - nb_int) * (2 * kSplitTile) + threadIdx.x;
-    if (e < E) boundary_body<N, T, ALG1>(m, op, e, field, u, flux);
+    if (e < E) boundary_body<N, T, ALG1, BERN>(m, op, e, field, u, flux);
     return;
   }
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's side
@@ -95,7 +95,14 @@ __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, c
   }
   T t[Np], tr[Nfp], c[Np];
   rotate_to_face<N, T>(v, f, t, tr);
-  matvec_pf<Np, Np, T>(op + L.n2b, t, c);
+  if (BERN) {
+    // the stage input holds Bernstein coefficients: rotation only
+#pragma unroll
+    for (int n = 0; n < Np; ++n) c[n] = t[n];
+    if (m.conv) face_bernstein_to_nodal<N, T>(op, tr);
+  } else {
+    matvec_pf<Np, Np, T>(op + L.n2b, t, c);
+  }
   decasteljau<N, T>(c, mu);
   // Algorithm 1 reduces to D (U1 - U2) when every edge of the tile has
   // D1 == D2; both waves see the same tile and take the same branch
@@ -309,7 +316,7 @@ __global__ __launch_bounds__(TILE) void batch_edge_kernel(const BatchProb* __res
     const int64_t e = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * TILE + threadIdx.x;
     if (e < P->m.E_int + P->m.E_bdy) {
       const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
-      edge_body<N, T, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+      edge_body<N, T, false, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
     }
   }
 }
@@ -364,8 +371,8 @@ __global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* c
 // launchers
 // ---------------------------------------------------------------------------
 
-template <int N, typename T>
-hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
+template <int N, typename T, bool BERN>
+hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   const int64_t E = m.E_int + m.E_bdy;
   if (E == 0) return hipSuccess;
   bool split = m.edge_kernel == EDGE_SPLIT;
@@ -381,19 +388,25 @@ hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flu
     const int64_t nbb = (m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile);
     dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
     if (m.alg1)
-      hipLaunchKernelGGL((edge_split_kernel<N, T, true>), grid, dim3(2 * kSplitTile), 0, st, m,
+      hipLaunchKernelGGL((edge_split_kernel<N, T, true, BERN>), grid, dim3(2 * kSplitTile), 0, st, m,
                          (const T*)u, (T*)flux, (int)nbi);
     else
-      hipLaunchKernelGGL((edge_split_kernel<N, T, false>), grid, dim3(2 * kSplitTile), 0, st, m,
+      hipLaunchKernelGGL((edge_split_kernel<N, T, false, BERN>), grid, dim3(2 * kSplitTile), 0, st, m,
                          (const T*)u, (T*)flux, (int)nbi);
     return hipGetLastError();
   }
   dim3 grid((unsigned)((E + 255) / 256), (unsigned)nfields);
   if (m.alg1)
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, true>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux);
+    hipLaunchKernelGGL((edge_flux_kernel<N, T, true, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux);
   else
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, false>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux);
+    hipLaunchKernelGGL((edge_flux_kernel<N, T, false, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux);
   return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t edge_launch_t(const DevMesh& m, bool bern, int nfields, const void* u, void* flux, hipStream_t st) {
+  return bern ? edge_launch_b<N, T, true>(m, nfields, u, flux, st)
+              : edge_launch_b<N, T, false>(m, nfields, u, flux, st);
 }
 
 template <int N, typename T>
@@ -421,8 +434,8 @@ hipError_t elem_launch_t(const DevMesh& m, int nfields, const void* vin, const v
   }
 
 template <typename T>
-hipError_t edge_dispatch(const DevMesh& m, int nf, const void* u, void* flux, hipStream_t st) {
-  ARDG_DISPATCH_N(edge_launch_t, m, nf, u, flux, st)
+hipError_t edge_dispatch(const DevMesh& m, bool bern, int nf, const void* u, void* flux, hipStream_t st) {
+  ARDG_DISPATCH_N(edge_launch_t, m, bern, nf, u, flux, st)
 }
 
 template <typename T>
@@ -431,19 +444,71 @@ hipError_t elem_dispatch(const DevMesh& m, int nf, const void* vin, const void* 
   ARDG_DISPATCH_N(elem_launch_t, m, nf, vin, flux, epi, st)
 }
 
-hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
+hipError_t launch_edge_flux(const DevMesh& m, int prec, bool bern, int nfields, const void* u, void* flux,
                             hipStream_t st) {
-  // split-BF16 products exist only on the matrix cores
-  if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) return launch_edge_mfma(m, prec, nfields, u, flux, st);
-  return prec == PREC_FP64 ? edge_dispatch<double>(m, nfields, u, flux, st)
-                           : edge_dispatch<float>(m, nfields, u, flux, st);
+  // split-BF16 products exist only on the matrix cores (nodal stage input)
+  if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) {
+    if (bern) return hipErrorInvalidValue;
+    return launch_edge_mfma(m, prec, nfields, u, flux, st);
+  }
+  return prec == PREC_FP64 ? edge_dispatch<double>(m, bern, nfields, u, flux, st)
+                           : edge_dispatch<float>(m, bern, nfields, u, flux, st);
 }
 
-hipError_t launch_element(const DevMesh& m, int prec, int nfields, const void* vin,
+hipError_t launch_element(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
                           const void* flux, const Epilogue& epi, hipStream_t st) {
-  if (m.elem_mfma || prec == PREC_BF16X3) return launch_element_mfma(m, prec, nfields, vin, flux, epi, st);
+  if (m.elem_mfma || prec == PREC_BF16X3) return launch_element_mfma(m, prec, bern, nfields, vin, flux, epi, st);
+  if (bern) return hipErrorInvalidValue;   // the thread-per-element kernel takes nodal values
   return prec == PREC_FP64 ? elem_dispatch<double>(m, nfields, vin, flux, epi, st)
                            : elem_dispatch<float>(m, nfields, vin, flux, epi, st);
+}
+
+// nodal values -> Bernstein coefficients, one thread per element (FP64
+// arithmetic, rounded once at the store)
+template <int N, typename TI, typename TO>
+__global__ __launch_bounds__(256) void to_bernstein_kernel(DevMesh m, int64_t nel, const TI* __restrict__ u,
+                                                           TO* __restrict__ out) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nel) return;
+  double v[Np], b[Np];
+#pragma unroll
+  for (int n = 0; n < Np; ++n) v[n] = (double)u[k * Np + n];
+  matvec<Np, Np, double>(opbase<double>(m) + L.n2b, v, b);
+#pragma unroll
+  for (int n = 0; n < Np; ++n) out[k * Np + n] = (TO)b[n];
+}
+
+template <int N, typename TI, typename TO>
+hipError_t to_bern_t(const DevMesh& m, int nfields, const void* u, void* out, hipStream_t st) {
+  const int64_t nel = (int64_t)nfields * m.K;
+  if (nel == 0) return hipSuccess;
+  hipLaunchKernelGGL((to_bernstein_kernel<N, TI, TO>), dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, st, m,
+                     nel, (const TI*)u, (TO*)out);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t to_bern_dispatch(const DevMesh& m, int nf, const void* u, void* out, hipStream_t st) {
+  switch (m.N) {
+    case 1: return to_bern_t<1, TI, TO>(m, nf, u, out, st);
+    case 2: return to_bern_t<2, TI, TO>(m, nf, u, out, st);
+    case 3: return to_bern_t<3, TI, TO>(m, nf, u, out, st);
+    case 4: return to_bern_t<4, TI, TO>(m, nf, u, out, st);
+    case 5: return to_bern_t<5, TI, TO>(m, nf, u, out, st);
+    case 6: return to_bern_t<6, TI, TO>(m, nf, u, out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_to_bernstein(const DevMesh& m, bool fp64_in, bool fp64_out, int nfields, const void* u,
+                               void* out, hipStream_t st) {
+  if (fp64_in)
+    return fp64_out ? to_bern_dispatch<double, double>(m, nfields, u, out, st)
+                    : to_bern_dispatch<double, float>(m, nfields, u, out, st);
+  return fp64_out ? to_bern_dispatch<float, double>(m, nfields, u, out, st)
+                  : to_bern_dispatch<float, float>(m, nfields, u, out, st);
 }
 
 template <int N, typename T>

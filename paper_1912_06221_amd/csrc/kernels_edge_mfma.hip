@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
   if (b >= nb_int) {
     // boundary faces: mirror-ghost operator on the vector unit, one lane per face
     const int64_t e = m.E_int + (int64_t)(b - nb_int) * kEdgeTile + l;
-    if (e < E) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, ALG1, false>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   const int64_t e0 = xcd_block(b, nb_int) * kEdgeTile;

@@ -34,7 +34,12 @@ namespace ardg {
 constexpr int kMfmaTile = 64;     // elements per block
 constexpr int kMfmaThreads = 256; // four waves, one 16-element sub-tile each
 
-template <int N, typename P, bool CONV>
+// BERN: the stage input holds Bernstein coefficients (Dr b2n and Ds b2n give
+// its nodal derivatives, b2n its nodal values where convection needs them;
+// the divergence still applies Dr and Ds to nodal quantities),
+// and the next stage input is converted to Bernstein coefficients by one
+// more product per sub-tile before it is stored.
+template <int N, typename P, bool CONV, bool BERN>
 __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
                                                                     const typename Mma<P>::T* __restrict__ vin,
                                                                     const typename Mma<P>::T* __restrict__ flux,
@@ -55,7 +60,11 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
   constexpr int SQ = (RW > KW ? RW : KW) * 16;
   constexpr bool kPre = N <= 4;
   __shared__ T sh[kMfmaTile * Np];
-  __shared__ T sqa[4][4][SQ];            // per wave: q_x, q_y, w_r, w_s of its sub-tile, [node][column]
+  __shared__ T sqa[4][2][SQ];            // per wave: w_r, w_s, then q_x, q_y of its sub-tile, [node][column]
+  // Bernstein conversions (nodal -> Bernstein for the next stage input,
+  // Bernstein -> nodal for convection), staged with the first loads
+  __shared__ T n2b_s[BERN ? Np * Np : 1];
+  __shared__ T b2n_s[(BERN && CONV) ? Np * Np : 1];
   const int l = threadIdx.x & 63, col = l & 15, grp = l >> 4;
   const int st = threadIdx.x >> 6;       // this wave's sub-tile
   T (*sq)[SQ] = sqa[st];
@@ -74,6 +83,12 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
 #pragma unroll
   for (int f = 0; f < 3; ++f) code[f] = m.elem_face[f * m.K + k];
 
+  if (BERN) {
+    for (int i = threadIdx.x; i < Np * Np; i += kMfmaThreads) {
+      n2b_s[i] = opg[L.n2b + i];
+      if (CONV) b2n_s[(BERN && CONV) ? i : 0] = opg[L.b2n + i];
+    }
+  }
   TileIO<TileShape<N, kMfmaTile, kMfmaThreads>::Q> io;
   tile_begin<N, T, kMfmaTile, kMfmaThreads>(m, k0, field, vin, epi, sh, io, kPre);
 
@@ -96,8 +111,11 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
       G[c][t] = sgn * x;
     }
 
-  // operator fragments: row 16 mt + col, columns kidx(c, grp, .)
+  // operator fragments: row 16 mt + col, columns kidx(c, grp, .).  Dr and Ds
+  // act on nodal quantities (the divergence); with Bernstein input the first
+  // product takes Dr b2n and Ds b2n instead
   frag_t aDr[MT][KC], aDs[MT][KC], aL[MT][KL];
+  frag_t aDrb[BERN ? MT : 1][BERN ? KC : 1], aDsb[BERN ? MT : 1][BERN ? KC : 1];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int row = 16 * mt + col;
@@ -113,6 +131,17 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
       }
       aDr[mt][c] = M::make(vr);
       aDs[mt][c] = M::make(vs);
+      if (BERN) {
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const int kk = kidx<M>(c, grp, t);
+          const bool ok = row < Np && kk < Np;
+          vr[t] = ok ? opg[L.drb + row * Np + kk] : T(0);
+          vs[t] = ok ? opg[L.dsb + row * Np + kk] : T(0);
+        }
+        aDrb[BERN ? mt : 0][BERN ? c : 0] = M::make(vr);
+        aDsb[BERN ? mt : 0][BERN ? c : 0] = M::make(vs);
+      }
     }
 #pragma unroll
     for (int c = 0; c < KL; ++c) {
@@ -177,11 +206,45 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
     us[mt] = M::zero();
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      ur[mt] = M::mma(aDr[mt][c], bu[c], ur[mt]);
-      us[mt] = M::mma(aDs[mt][c], bu[c], us[mt]);
+      if (BERN) {
+        ur[mt] = M::mma(aDrb[BERN ? mt : 0][BERN ? c : 0], bu[c], ur[mt]);
+        us[mt] = M::mma(aDsb[BERN ? mt : 0][BERN ? c : 0], bu[c], us[mt]);
+      } else {
+        ur[mt] = M::mma(aDr[mt][c], bu[c], ur[mt]);
+        us[mt] = M::mma(aDs[mt][c], bu[c], us[mt]);
+      }
     }
   }
-  // accumulator layout: node 16 mt + M::row(grp, r) of element `col`
+  // nodal values (convection with Bernstein input): b2n u, kept in sh for the
+  // face terms (each wave rewrites only its own sub-tile's elements)
+  acc_t un_b[MT];
+  if (CONV && BERN) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      un_b[mt] = M::zero();
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        T vb[KPL];
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const int row = 16 * mt + col, kk = kidx<M>(c, grp, t);
+          vb[t] = (row < Np && kk < Np) ? b2n_s[(BERN && CONV) ? row * Np + kk : 0] : T(0);
+        }
+        un_b[mt] = M::mma(M::make(vb), bu[c], un_b[mt]);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int node = 16 * mt + M::row(grp, r);
+        if (valid && node < Np) sh[el * Np + node] = un_b[mt][r];
+      }
+  }
+  // accumulator layout: node 16 mt + M::row(grp, r) of element `col`.  w_r and
+  // w_s go through LDS to become B fragments; q stays in registers until the
+  // same LDS rows are free for the face terms
+  T qxa[MT][4], qya[MT][4];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -189,19 +252,20 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
       const int node = 16 * mt + M::row(grp, r);
       const T qx = rx * ur[mt][r] + sx * us[mt][r];
       const T qy = ry * ur[mt][r] + sy * us[mt][r];
+      qxa[mt][r] = qx;
+      qya[mt][r] = qy;
       T wr = D * (rx * qx + ry * qy);
       T ws = D * (sx * qx + sy * qy);
       if (CONV) {
         const T vx = (T)ev.x1 + r1a[mt][r] * (T)ev.xr + s1a[mt][r] * (T)ev.xs;
         const T vy = (T)ev.y1 + r1a[mt][r] * (T)ev.yr + s1a[mt][r] * (T)ev.ys;
-        const T un = (valid && node < Np) ? sh[el * Np + (node < Np ? node : 0)] : T(0);
+        const T un = BERN ? un_b[mt][r]
+                          : ((valid && node < Np) ? sh[el * Np + (node < Np ? node : 0)] : T(0));
         wr -= (rx * vx + ry * vy) * un;
         ws -= (sx * vx + sy * vy) * un;
       }
-      sq[0][node * 16 + col] = qx;
-      sq[1][node * 16 + col] = qy;
-      sq[2][node * 16 + col] = wr;
-      sq[3][node * 16 + col] = ws;
+      sq[0][node * 16 + col] = wr;
+      sq[1][node * 16 + col] = ws;
     }
   __syncthreads();
 
@@ -214,22 +278,35 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
 #pragma unroll
       for (int t = 0; t < KPL; ++t) {
         const int n = kidx<M>(c, grp, t);
-        vw[t] = n < RW ? sq[2][n * 16 + col] : T(0);
-        vs[t] = n < RW ? sq[3][n * 16 + col] : T(0);
+        vw[t] = n < RW ? sq[0][n * 16 + col] : T(0);
+        vs[t] = n < RW ? sq[1][n * 16 + col] : T(0);
       }
       bw[c] = M::make(vw);
       bs[c] = M::make(vs);
     }
+    // two independent accumulator chains (Dr and Ds), summed afterwards
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      rhs[mt] = M::zero();
+      acc_t rr = M::zero(), rs = M::zero();
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
-        rhs[mt] = M::mma(aDr[mt][c], bw[c], rhs[mt]);
-        rhs[mt] = M::mma(aDs[mt][c], bs[c], rhs[mt]);
+        rr = M::mma(aDr[mt][c], bw[c], rr);
+        rs = M::mma(aDs[mt][c], bs[c], rs);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rhs[mt][r] = rr[r] + rs[r];
     }
   }
+  __syncthreads();   // the B fragments are read: the rows take q now
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int node = 16 * mt + M::row(grp, r);
+      sq[0][node * 16 + col] = qxa[mt][r];
+      sq[1][node * 16 + col] = qya[mt][r];
+    }
+  __syncthreads();
 
   // face values (1/J) (G - D (sJ n).q (+ (sJ n).v u)) as B fragments
   frag_t bj[KL];
@@ -256,9 +333,13 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
     bj[c] = M::make(vj);
   }
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+  for (int mt = 0; mt < MT; ++mt) {
+    acc_t rl = M::zero();
 #pragma unroll
-    for (int c = 0; c < KL; ++c) rhs[mt] = M::mma(aL[mt][c], bj[c], rhs[mt]);
+    for (int c = 0; c < KL; ++c) rl = M::mma(aL[mt][c], bj[c], rl);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rhs[mt][r] += rl[r];
+  }
 
   __syncthreads();   // every read of sq and of this sub-tile's u is done
 #pragma unroll
@@ -269,43 +350,102 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
       if (valid && node < Np) sh[el * Np + node] = rhs[mt][r];
     }
   __syncthreads();
-  tile_end<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre);
+  const bool v_bern = BERN && epi.kind != EPI_RHS && epi.vnext != nullptr;
+  if (!v_bern) {
+    tile_end<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre);
+  } else {
+    // next stage input: nodal values in sh -> Bernstein coefficients; state
+    // and accumulator are stored after the last barrier
+    TileNew<TileShape<N, kMfmaTile, kMfmaThreads>::Q> nw;
+    tile_update<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre, nw);
+    __syncthreads();
+    frag_t bv[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      T v[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int n = kidx<M>(c, grp, t);
+        v[t] = (valid && n < Np) ? sh[el * Np + n] : T(0);
+      }
+      bv[c] = M::make(v);
+    }
+    acc_t cb[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      cb[mt] = M::zero();
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        T va[KPL];
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const int row = 16 * mt + col, kk = kidx<M>(c, grp, t);
+          va[t] = (row < Np && kk < Np) ? n2b_s[BERN ? row * Np + kk : 0] : T(0);
+        }
+        cb[mt] = M::mma(M::make(va), bv[c], cb[mt]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int node = 16 * mt + M::row(grp, r);
+        if (valid && node < Np) sh[el * Np + node] = cb[mt][r];
+      }
+    __syncthreads();
+    T* vo = (T*)epi.vnext + io.base;
+    constexpr int Q = TileShape<N, kMfmaTile, kMfmaThreads>::Q;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = threadIdx.x + q * kMfmaThreads;
+      if (i < io.ndof) vo[i] = sh[i];
+    }
+    tile_store<N, T, kMfmaTile, kMfmaThreads>(epi, io, nw);
+  }
 }
 
-template <int N, typename P>
+template <int N, typename P, bool BERN>
 hipError_t elem_mfma_t(const DevMesh& m, int nfields, const void* vin, const void* flux,
                        const Epilogue& epi, hipStream_t st) {
   using T = typename Mma<P>::T;
   dim3 grid((unsigned)((m.K + kMfmaTile - 1) / kMfmaTile), (unsigned)nfields);
   if (m.conv)
-    hipLaunchKernelGGL((element_mfma_kernel<N, P, true>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, true, BERN>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi);
   else
-    hipLaunchKernelGGL((element_mfma_kernel<N, P, false>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, false, BERN>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi);
   return hipGetLastError();
 }
 
-template <typename P>
+template <typename P, bool BERN>
 hipError_t elem_mfma_dispatch(const DevMesh& m, int nf, const void* vin, const void* flux,
                               const Epilogue& epi, hipStream_t st) {
   switch (m.N) {
-    case 1: return elem_mfma_t<1, P>(m, nf, vin, flux, epi, st);
-    case 2: return elem_mfma_t<2, P>(m, nf, vin, flux, epi, st);
-    case 3: return elem_mfma_t<3, P>(m, nf, vin, flux, epi, st);
-    case 4: return elem_mfma_t<4, P>(m, nf, vin, flux, epi, st);
-    case 5: return elem_mfma_t<5, P>(m, nf, vin, flux, epi, st);
-    case 6: return elem_mfma_t<6, P>(m, nf, vin, flux, epi, st);
+    case 1: return elem_mfma_t<1, P, BERN>(m, nf, vin, flux, epi, st);
+    case 2: return elem_mfma_t<2, P, BERN>(m, nf, vin, flux, epi, st);
+    case 3: return elem_mfma_t<3, P, BERN>(m, nf, vin, flux, epi, st);
+    case 4: return elem_mfma_t<4, P, BERN>(m, nf, vin, flux, epi, st);
+    case 5: return elem_mfma_t<5, P, BERN>(m, nf, vin, flux, epi, st);
+    case 6: return elem_mfma_t<6, P, BERN>(m, nf, vin, flux, epi, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_element_mfma(const DevMesh& m, int prec, int nfields, const void* vin,
+hipError_t launch_element_mfma(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
                                const void* flux, const Epilogue& epi, hipStream_t st) {
   switch (prec) {
-    case PREC_FP64: return elem_mfma_dispatch<double>(m, nfields, vin, flux, epi, st);
-    case PREC_FP32: return elem_mfma_dispatch<float>(m, nfields, vin, flux, epi, st);
-    case PREC_BF16X3: return elem_mfma_dispatch<Bf16x3>(m, nfields, vin, flux, epi, st);
+    case PREC_FP64:
+      return bern ? elem_mfma_dispatch<double, true>(m, nfields, vin, flux, epi, st)
+                  : elem_mfma_dispatch<double, false>(m, nfields, vin, flux, epi, st);
+    case PREC_FP32:
+      return bern ? elem_mfma_dispatch<float, true>(m, nfields, vin, flux, epi, st)
+                  : elem_mfma_dispatch<float, false>(m, nfields, vin, flux, epi, st);
+    case PREC_BF16X3:
+      // split-BF16 stages keep nodal stage vectors
+      if (bern) return hipErrorInvalidValue;
+      return elem_mfma_dispatch<Bf16x3, false>(m, nfields, vin, flux, epi, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -145,23 +145,26 @@ def test_empty_and_tiny_meshes():
             assert np.abs(to_np(rhs) - ro).max() <= TOL64 * np.abs(ro).max()
 
 
+@pytest.mark.parametrize("form", ["nodal", "bernstein"])
 @pytest.mark.parametrize("scheme", ["rk4", "lserk"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_time_stepping_heat_8x8(scheme, prec):
-    """The plain heat problem: 8x8x2 unjittered, N=2, D=1,
+def test_time_stepping_heat_8x8(scheme, prec, form, monkeypatch):
+    """The plain heat problem: 8x8x2 unjittered, N=3, D=1,
     u0 = sin(pi x) sin(pi y), 100 steps; state parity with the oracle and the
-    error against the exact solution."""
+    error against the exact solution.  form: the stage vectors hold nodal
+    values or Bernstein coefficients (BF16X3 always steps nodal vectors)."""
     import torch
     from oracle.rhs import lserk_step, mass_norm, rk4_step
     from paper_1912_06221_amd import ardg
-    print(f"heat 8x8 {scheme} {prec}", flush=True)
+    print(f"heat 8x8 {scheme} {prec} {form}", flush=True)
+    monkeypatch.setenv("ARDG_STAGE_FORM", form)
     mesh = W.split_square_mesh(8, 0.0)
-    N = 2
+    N = 3
     ops, lm = library_mesh(mesh, N, "const", 1.0, None, 1)
     pr = oracle_problem(mesh, N, "const", 1.0, None, 1)
     xy = pr.nodal_xy()
     u0 = W.manufactured(xy[..., 0], xy[..., 1])
-    dt, nsteps = 2e-4, 100
+    dt, nsteps = 5e-5, 100
     uo = u0.copy()
     step = rk4_step if scheme == "rk4" else lserk_step
     for _ in range(nsteps):
@@ -244,9 +247,11 @@ def _blocks_D(mesh):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
     """The kernel variants -- default (edge kernel chosen by grid size,
-    matrix-core element kernel), edge tiles split by side, one thread per
-    edge / per element, all matrix-core -- compute the same flux and RHS (to
-    rounding), each matching the oracle."""
+    matrix-core element kernel, nodal stage vectors), the same with
+    Bernstein-form stage vectors, edge tiles split by side, one thread per
+    edge with Bernstein input, one thread per edge / per element, all
+    matrix-core -- compute the same flux and RHS (to rounding), each matching
+    the oracle."""
     import torch
     from paper_1912_06221_amd import ardg
     m, N, dk, vel = case
@@ -259,10 +264,12 @@ def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
     p = ardg.FP64 if prec == "fp64" else ardg.FP32
     tol = TOL64 if prec == "fp64" else TOL32
     outs = {}
-    variants = {"default": (None, None), "split": ("split", None), "lane": ("lane", "valu"),
-                "mfma": ("mfma", "mfma")}
-    for variant, (edge_k, elem_k) in variants.items():
-        for var, val in (("ARDG_EDGE_KERNEL", edge_k), ("ARDG_ELEMENT_KERNEL", elem_k)):
+    variants = {"default": (None, None, None), "bernstein-stages": (None, None, "bernstein"),
+                "split": ("split", None, None), "lane-bernstein": ("lane", None, "bernstein"),
+                "lane": ("lane", "valu", None), "mfma": ("mfma", "mfma", None)}
+    for variant, (edge_k, elem_k, form) in variants.items():
+        for var, val in (("ARDG_EDGE_KERNEL", edge_k), ("ARDG_ELEMENT_KERNEL", elem_k),
+                         ("ARDG_STAGE_FORM", form)):
             if val is None:
                 monkeypatch.delenv(var, raising=False)
             else:

@@ -52,6 +52,23 @@ def test_reference_operators_match_oracle(L, N):
         assert list(rp[f]) == list(oa.rotation_perm(N, f))
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
+def test_face_rotation_commutes_with_bernstein_conversion(L, N):
+    """Relabelling the vertices permutes Bernstein coefficients by the same
+    lattice permutation that it applies to the (symmetric) nodes, so the
+    nodal->Bernstein matrix commutes with each face's reordering: an element
+    can store its Bernstein coefficients once and every edge rotates them by
+    index, as it rotates nodal values."""
+    o = ardg.Ops(N)
+    Np = o.Np
+    n2b = o.export(ardg.OPS_N2B).reshape(Np, Np)
+    rp = o.export(ardg.OPS_ROT_PERM).reshape(3, Np).astype(int)
+    for f in range(3):
+        P = np.zeros((Np, Np))
+        P[np.arange(Np), rp[f]] = 1.0
+        assert np.abs(n2b @ P - P @ n2b).max() < 1e-12 * np.abs(n2b).max()
+
+
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 6])
 def test_reconstruction_operators_match_oracle(L, N):
     o = ardg.Ops(N)
