@@ -235,7 +235,10 @@ ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
                             double* const* u_devs, void* work_dev, const double* dt,
                             int32_t nsteps, void* hip_stream);
 /* The tile shapes in use for order N and a precision (tuning them first if
- * needed): edges per edge tile, elements per element tile, persistent blocks. */
+ * needed): edges per edge tile (64, 128, 256 with one thread per edge, or 0:
+ * side-split tiles of 64 interior edges on two waves), elements per element
+ * tile (64, 128, 256 with one thread per element, or 0: 64-element tiles on
+ * the matrix cores), and persistent blocks per compute unit. */
 ardg_status ardg_batch_tiles(ardg_batch batch, int32_t precision, int32_t N, int32_t* edge_tile,
                              int32_t* elem_tile, int32_t* grid);
 void ardg_batch_destroy(ardg_batch batch);

@@ -925,11 +925,19 @@ ardg_status build_items(ardg_batch b, BatchGroup& g, int pi, int tile_e, int til
   if (it.tile_e == tile_e && it.tile_l == tile_l && it.d_eitems) return ARDG_OK;
   it.eitems.clear();
   it.litems.clear();
+  // tile code 0: side-split edge tiles of 64 interior edges plus boundary
+  // tiles of 128 faces (negative index), and 64-element MFMA tiles
   for (int p : g.probs) {
     ardg_mesh m = b->meshes[p];
     const int64_t E = m->hm.E_int + m->hm.E_bdy, K = m->hm.K;
-    for (int64_t t = 0; t * tile_e < E; ++t) it.eitems.push_back(make_int2(p, (int)t));
-    for (int64_t t = 0; t * tile_l < K; ++t) it.litems.push_back(make_int2(p, (int)t));
+    if (tile_e == 0) {
+      for (int64_t t = 0; t * 64 < m->hm.E_int; ++t) it.eitems.push_back(make_int2(p, (int)t));
+      for (int64_t t = 0; t * 128 < m->hm.E_bdy; ++t) it.eitems.push_back(make_int2(p, (int)(-1 - t)));
+    } else {
+      for (int64_t t = 0; t * tile_e < E; ++t) it.eitems.push_back(make_int2(p, (int)t));
+    }
+    const int tl = tile_l == 0 ? 64 : tile_l;
+    for (int64_t t = 0; t * tl < K; ++t) it.litems.push_back(make_int2(p, (int)t));
   }
   if (it.d_eitems) (void)hipFree(it.d_eitems);
   if (it.d_litems) (void)hipFree(it.d_litems);
@@ -1076,7 +1084,8 @@ ardg_status tune(ardg_batch b, int precision) {
   }
   if (e == hipSuccess) e = hipMemcpy(b->dprobs, hp.data(), hp.size() * sizeof(BatchProb), hipMemcpyHostToDevice);
   ardg_status st = (e == hipSuccess) ? ARDG_OK : hip_fail(e, "batch tuning setup");
-  const int cand_tile[3] = {64, 128, 256};
+  // 0: side-split edge tiles / matrix-core element tiles
+  const int cand_tile[4] = {64, 128, 256, 0};
   const int cand_grid[4] = {1, 2, 4, 8};
   for (BatchGroup* g : todo) {
     if (st != ARDG_OK) break;
@@ -1248,7 +1257,8 @@ ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
         if (e != hipSuccess) break;
         GroupItems& gi = gr.items[pi];
         const int Np = (gr.N + 1) * (gr.N + 2) / 2;
-        e = launch_batch_to_f32(batch->dprobs, gi.d_litems, (int)gi.litems.size(), gi.tile_l, Np,
+        // element items cover 64 elements each under tile code 0
+        e = launch_batch_to_f32(batch->dprobs, gi.d_litems, (int)gi.litems.size(), gi.tile_l == 0 ? 64 : gi.tile_l, Np,
                                 grid_for(batch, (int)gi.litems.size(), gr.tiles[pi].grid_mult), batch->cap_stream);
       }
     const int nst = scheme == ARDG_RK4 ? 4 : 5;

@@ -117,10 +117,12 @@ hipError_t launch_edge_flux(const DevMesh& m, int prec, bool bern, int nfields, 
 hipError_t launch_element(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
                           const void* flux, const Epilogue& epi, hipStream_t st);
 // Batched (persistent) kernels over work items (problem, tile).  tile is the
-// number of edges / elements per item and the block size (64, 128 or 256);
-// grid is the number of persistent blocks.  in_u: the stage input is the
-// FP64 state itself (FP64 stage 0 or LSERK); write_v: the element kernel
-// writes the next stage input.
+// number of edges / elements per item and the block size (64, 128 or 256),
+// or 0: side-split edge tiles (64 interior edges per item, items with a
+// negative tile index are boundary tiles of 128 faces) and 64-element tiles
+// on the matrix cores; grid is the number of persistent blocks.  in_u: the
+// stage input is the FP64 state itself (FP64 stage 0 or LSERK); write_v: the
+// element kernel writes the next stage input.
 hipError_t launch_batch_edge(int N, bool fp64, int tile, int grid, const BatchProb* probs,
                              const int2* items, int nitems, int in_u, hipStream_t st);
 hipError_t launch_batch_element(int N, bool fp64, int tile, int grid, const BatchProb* probs,
@@ -134,6 +136,9 @@ hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int ni
 // launch_edge_flux).
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st);
+// Batched element kernel on the matrix cores (64-element tiles).
+hipError_t launch_batch_element_mfma(int N, bool fp64, int grid, const BatchProb* probs, const int2* items,
+                                     int nitems, const Epilogue& epi, int in_u, int write_v, hipStream_t st);
 // Element kernel on the matrix cores (same contract as launch_element).
 hipError_t launch_element_mfma(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
                                const void* flux, const Epilogue& epi, hipStream_t st);

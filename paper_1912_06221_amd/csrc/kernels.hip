@@ -1,13 +1,16 @@
-// gfx950 kernels of the affine-reconstructed nodal DG right-hand side.
+// gfx950 vector-unit kernels of the affine-reconstructed nodal DG
+// right-hand side (the matrix-core ones are in kernels_mfma.hip and
+// kernels_edge_mfma.hip).
 //
-// edge_flux_kernel (one thread per edge): Algorithm aRDG for one edge and the
-// flux on the diagonal of its enclosed parallelogram.
-//   1. gather the Np nodal values of each side and apply the face's node
-//      reordering (section "Reordering nodes in the reference domain") as a
-//      register permutation;
+// Edge kernels -- Algorithm aRDG for each edge and the flux on the diagonal
+// of its enclosed parallelogram:
+//   1. gather each side's Np values and apply the face's node reordering
+//      (section "Reordering nodes in the reference domain") as a register
+//      permutation;
 //   2. project onto the sub-triangle (eq. NodalToModalProjection, eq.
 //      totalProjection): nodal -> Bernstein coefficients on I (constant
-//      matrix), then an in-place de Casteljau subdivision at the apex's
+//      matrix; skipped when the stage vector already holds Bernstein
+//      coefficients), then an in-place de Casteljau subdivision at the apex's
 //      barycentric weights.  After the subdivision, lattice slot (i,j) holds
 //      the Bernstein coefficient of the sub-triangle (apex, a2, a3) with
 //      multi-index (N-i-j, i, j): the restriction of the polynomial, exactly;
@@ -17,11 +20,15 @@
 //      contract with the two per-edge factors gamma_R, gamma_S; with
 //      element-wise D, Algorithm 1's four constant blocks weighted by D1, D2;
 //   4. optionally subtract the upwind convective flux;
-//   5. write Nfp values per edge (no atomics: each edge owns its slot).
+//   5. write Nfp values per edge, times the edge's sJ (no atomics: each edge
+//      owns its slot).
+// edge_flux_kernel runs one lane per edge; edge_split_kernel gives each side
+// of a 64-edge tile its own wave.
 // element_kernel (one thread per element, the block's elements staged through
-// LDS): strong-form volume term with the element's affine factors,
-// (J_f/J) LIFT_f of the face jumps, optional convective volume term, and a
-// fused Runge-Kutta update in FP64 over the block's degrees of freedom.
+// LDS): strong-form volume term with the element's affine factors, LIFT of
+// the face jumps, optional convective volume term, and a fused Runge-Kutta
+// update in FP64 over the block's degrees of freedom.
+// batch_* kernels: the same bodies over work items of many meshes.
 //
 // Constant operators are read through the constant address space with
 // compile-time offsets, so every matrix entry is a wave-uniform scalar load
@@ -55,25 +62,26 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
 // operator, one lane per face).
 constexpr int kSplitTile = 64;
 
+template <int N, typename T>
+struct SplitShared {
+  static constexpr int Nfp = N + 1;
+  T part[4 * Nfp][kSplitTile];
+  T trace2[Nfp][kSplitTile];
+};
+
+// One tile of 64 interior edges starting at edge e0 (all 128 threads of the
+// block: wave s takes side s + 1).
 template <int N, typename T, bool ALG1, bool BERN>
-__global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
-                                                                    T* __restrict__ flux, int nb_int) {
+__device__ inline void edge_split_tile(const DevMesh& m, int64_t e0, int field, const T* __restrict__ u,
+                                       T* __restrict__ flux, SplitShared<N, T>& S) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp, K2 = 2 * Np;
-  __shared__ T part[4 * Nfp][kSplitTile];
-  __shared__ T trace2[Nfp][kSplitTile];
-  const int field = blockIdx.y;
+  T (*part)[kSplitTile] = S.part;
+  T (*trace2)[kSplitTile] = S.trace2;
   const int64_t E = m.E_int + m.E_bdy;
   const cptr<T> op = opbase<T>(m);
-  const int b = blockIdx.x;
-  if (b >= nb_int) {
-    const int64_t e = m.E_int + (int64_t)(b - nb_int) * (2 * kSplitTile) + threadIdx.x;
-    if (e < E) boundary_body<N, T, ALG1, BERN>(m, op, e, field, u, flux);
-    return;
-  }
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's side
   const int l = threadIdx.x & 63;
-  const int64_t e0 = xcd_block(b, nb_int) * kSplitTile;
   const bool valid = e0 + l < m.E_int;
   const int64_t e = valid ? e0 + l : e0;
   const int2 ef = m.ef[e];
@@ -153,6 +161,51 @@ __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, c
   T* out = flux + ((int64_t)field * E + e) * Nfp;
 #pragma unroll
   for (int j = 0; j < Nfp; ++j) out[j] = F[j];
+}
+
+template <int N, typename T, bool ALG1, bool BERN>
+__global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
+                                                                    T* __restrict__ flux, int nb_int) {
+  __shared__ SplitShared<N, T> S;
+  const int b = blockIdx.x;
+  if (b >= nb_int) {
+    // boundary faces: mirror-ghost operator, one lane per face
+    const int64_t e = m.E_int + (int64_t)(b - nb_int) * (2 * kSplitTile) + threadIdx.x;
+    if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, blockIdx.y, u, flux);
+    return;
+  }
+  edge_split_tile<N, T, ALG1, BERN>(m, xcd_block(b, nb_int) * kSplitTile, blockIdx.y, u, flux, S);
+}
+
+// Batched form: persistent blocks over items of many meshes (constant D, no
+// convection, nodal stage vectors): item (problem, t) with t >= 0 is the
+// interior-edge tile t, with t < 0 the boundary tile -1 - t of 128 faces.
+template <int N, typename T>
+__global__ __launch_bounds__(2 * kSplitTile) void batch_edge_split_kernel(const BatchProb* __restrict__ probs,
+                                                                          const int2* __restrict__ items,
+                                                                          int nitems, int in_u) {
+  __shared__ SplitShared<N, T> S;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchProb* P = probs + __builtin_amdgcn_readfirstlane(w.x);
+    const int t = __builtin_amdgcn_readfirstlane(w.y);
+    const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
+    if (t >= 0) {
+      edge_split_tile<N, T, false, false>(P->m, (int64_t)t * kSplitTile, 0, vin, (T*)P->flux, S);
+    } else {
+      const int64_t e = P->m.E_int + (int64_t)(-1 - t) * (2 * kSplitTile) + threadIdx.x;
+      if (e < P->m.E_int + P->m.E_bdy) boundary_body<N, T, false, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, typename T>
+hipError_t batch_edge_split_t(int grid, const BatchProb* probs, const int2* items, int nitems, int in_u,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((batch_edge_split_kernel<N, T>), dim3(grid), dim3(2 * kSplitTile), 0, st, probs, items,
+                     nitems, in_u);
+  return hipGetLastError();
 }
 
 constexpr int kElemBlock = 256;
@@ -561,6 +614,24 @@ hipError_t batch_elem_dispatch(int N, int tile, int grid, const BatchProb* probs
 hipError_t launch_batch_edge(int N, bool fp64, int tile, int grid, const BatchProb* probs,
                              const int2* items, int nitems, int in_u, hipStream_t st) {
   if (nitems == 0) return hipSuccess;
+  if (tile == 0) {
+    // side-split tiles (items as built for tile code 0)
+    switch (N) {
+      case 1: return fp64 ? batch_edge_split_t<1, double>(grid, probs, items, nitems, in_u, st)
+                          : batch_edge_split_t<1, float>(grid, probs, items, nitems, in_u, st);
+      case 2: return fp64 ? batch_edge_split_t<2, double>(grid, probs, items, nitems, in_u, st)
+                          : batch_edge_split_t<2, float>(grid, probs, items, nitems, in_u, st);
+      case 3: return fp64 ? batch_edge_split_t<3, double>(grid, probs, items, nitems, in_u, st)
+                          : batch_edge_split_t<3, float>(grid, probs, items, nitems, in_u, st);
+      case 4: return fp64 ? batch_edge_split_t<4, double>(grid, probs, items, nitems, in_u, st)
+                          : batch_edge_split_t<4, float>(grid, probs, items, nitems, in_u, st);
+      case 5: return fp64 ? batch_edge_split_t<5, double>(grid, probs, items, nitems, in_u, st)
+                          : batch_edge_split_t<5, float>(grid, probs, items, nitems, in_u, st);
+      case 6: return fp64 ? batch_edge_split_t<6, double>(grid, probs, items, nitems, in_u, st)
+                          : batch_edge_split_t<6, float>(grid, probs, items, nitems, in_u, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   return fp64 ? batch_edge_dispatch<double>(N, tile, grid, probs, items, nitems, in_u, st)
               : batch_edge_dispatch<float>(N, tile, grid, probs, items, nitems, 0, st);
 }
@@ -568,6 +639,8 @@ hipError_t launch_batch_edge(int N, bool fp64, int tile, int grid, const BatchPr
 hipError_t launch_batch_element(int N, bool fp64, int tile, int grid, const BatchProb* probs,
                                 const int2* items, int nitems, const Epilogue& epi, int in_u,
                                 int write_v, hipStream_t st) {
+  // tile code 0: 64-element tiles on the matrix cores
+  if (tile == 0) return launch_batch_element_mfma(N, fp64, grid, probs, items, nitems, epi, in_u, write_v, st);
   if (nitems == 0) return hipSuccess;
   return fp64 ? batch_elem_dispatch<double>(N, tile, grid, probs, items, nitems, epi, in_u, write_v, st)
               : batch_elem_dispatch<float>(N, tile, grid, probs, items, nitems, epi, 0, write_v, st);

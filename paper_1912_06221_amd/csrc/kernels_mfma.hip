@@ -39,11 +39,31 @@ constexpr int kMfmaThreads = 256; // four waves, one 16-element sub-tile each
 // the divergence still applies Dr and Ds to nodal quantities),
 // and the next stage input is converted to Bernstein coefficients by one
 // more product per sub-tile before it is stored.
+// LDS of one 64-element tile: the tile's stage input (then its du/dt), each
+// wave's transpose rows, and the Bernstein conversions (nodal -> Bernstein
+// for the next stage input, Bernstein -> nodal for convection) when used.
 template <int N, typename P, bool CONV, bool BERN>
-__global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
-                                                                    const typename Mma<P>::T* __restrict__ vin,
-                                                                    const typename Mma<P>::T* __restrict__ flux,
-                                                                    Epilogue epi) {
+struct ElemShared {
+  using M = Mma<P>;
+  using T = typename M::T;
+  static constexpr int Np = (N + 1) * (N + 2) / 2;
+  static constexpr int MT = (Np + 15) / 16;
+  static constexpr int KC = (Np + M::KSTEP - 1) / M::KSTEP;
+  static constexpr int RW = 16 * MT, KW = M::KSTEP * KC;
+  static constexpr int SQ = (RW > KW ? RW : KW) * 16;
+  T sh[kMfmaTile * Np];
+  T sqa[4][2][SQ];            // per wave: w_r, w_s, then q_x, q_y of its sub-tile, [node][column]
+  T n2b_s[BERN ? Np * Np : 1];
+  T b2n_s[(BERN && CONV) ? Np * Np : 1];
+};
+
+// One 64-element tile starting at element k0 of field `field`; all 256
+// threads of the block take part (wave w: sub-tile w).
+template <int N, typename P, bool CONV, bool BERN>
+__device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field,
+                                         const typename Mma<P>::T* __restrict__ vin,
+                                         const typename Mma<P>::T* __restrict__ flux, const Epilogue& epi,
+                                         ElemShared<N, P, CONV, BERN>& S) {
   using M = Mma<P>;
   using T = typename M::T;
   typedef typename M::acc acc_t;
@@ -56,20 +76,14 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
   constexpr int NJ = 3 * Nfp;            // face values lifted
   constexpr int KL = (NJ + KS - 1) / KS; // K steps over face values
   constexpr int RW = 16 * MT;            // padded node rows
-  constexpr int KW = KS * KC;            // padded node columns (B fragments)
-  constexpr int SQ = (RW > KW ? RW : KW) * 16;
+  constexpr int SQ = ElemShared<N, P, CONV, BERN>::SQ;
   constexpr bool kPre = N <= 4;
-  __shared__ T sh[kMfmaTile * Np];
-  __shared__ T sqa[4][2][SQ];            // per wave: w_r, w_s, then q_x, q_y of its sub-tile, [node][column]
-  // Bernstein conversions (nodal -> Bernstein for the next stage input,
-  // Bernstein -> nodal for convection), staged with the first loads
-  __shared__ T n2b_s[BERN ? Np * Np : 1];
-  __shared__ T b2n_s[(BERN && CONV) ? Np * Np : 1];
+  T* sh = S.sh;
+  T* n2b_s = S.n2b_s;
+  T* b2n_s = S.b2n_s;
   const int l = threadIdx.x & 63, col = l & 15, grp = l >> 4;
   const int st = threadIdx.x >> 6;       // this wave's sub-tile
-  T (*sq)[SQ] = sqa[st];
-  const int64_t k0 = xcd_block(blockIdx.x, gridDim.x) * kMfmaTile;
-  const int field = blockIdx.y;
+  T (*sq)[SQ] = S.sqa[st];
   const int64_t E = m.E_int + m.E_bdy;
   const T* opg = (const T*)(sizeof(T) == 8 ? (const void*)m.ops64 : (const void*)m.ops32);
 
@@ -403,6 +417,62 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
     }
     tile_store<N, T, kMfmaTile, kMfmaThreads>(epi, io, nw);
   }
+}
+
+template <int N, typename P, bool CONV, bool BERN>
+__global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
+                                                                    const typename Mma<P>::T* __restrict__ vin,
+                                                                    const typename Mma<P>::T* __restrict__ flux,
+                                                                    Epilogue epi) {
+  __shared__ ElemShared<N, P, CONV, BERN> S;
+  const int64_t k0 = xcd_block(blockIdx.x, gridDim.x) * kMfmaTile;
+  element_mfma_tile<N, P, CONV, BERN>(m, k0, blockIdx.y, vin, flux, epi, S);
+}
+
+// Batched form: persistent blocks over (problem, 64-element tile) items of
+// many meshes (constant D, no convection, nodal stage vectors); each item
+// reads its problem's descriptor (tables, buffers, dt).
+template <int N, typename T>
+__global__ __launch_bounds__(kMfmaThreads) void batch_element_mfma_kernel(const BatchProb* __restrict__ probs,
+                                                                          const int2* __restrict__ items,
+                                                                          int nitems, Epilogue epi0, int in_u,
+                                                                          int write_v) {
+  __shared__ ElemShared<N, T, false, false> S;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const BatchProb* Pb = probs + __builtin_amdgcn_readfirstlane(w.x);
+    Epilogue epi = epi0;
+    epi.u = Pb->u;
+    epi.acc = Pb->acc;
+    epi.vnext = write_v ? Pb->v : nullptr;
+    epi.dt = Pb->dt;
+    const T* vin = in_u ? (const T*)(const void*)Pb->u : (const T*)Pb->v;
+    const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * kMfmaTile;
+    element_mfma_tile<N, T, false, false>(Pb->m, k0, 0, vin, (const T*)Pb->flux, epi, S);
+    __syncthreads();
+  }
+}
+
+template <int N, typename T>
+hipError_t batch_elem_mfma_t(int grid, const BatchProb* probs, const int2* items, int nitems,
+                             const Epilogue& epi, int in_u, int write_v, hipStream_t st) {
+  hipLaunchKernelGGL((batch_element_mfma_kernel<N, T>), dim3(grid), dim3(kMfmaThreads), 0, st, probs, items,
+                     nitems, epi, in_u, write_v);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_element_mfma(int N, bool fp64, int grid, const BatchProb* probs, const int2* items,
+                                     int nitems, const Epilogue& epi, int in_u, int write_v, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+#define ARDG_BEM(NN)                                                                                    \
+  case NN:                                                                                              \
+    return fp64 ? batch_elem_mfma_t<NN, double>(grid, probs, items, nitems, epi, in_u, write_v, st)     \
+                : batch_elem_mfma_t<NN, float>(grid, probs, items, nitems, epi, in_u, write_v, st);
+  switch (N) {
+    ARDG_BEM(1) ARDG_BEM(2) ARDG_BEM(3) ARDG_BEM(4) ARDG_BEM(5) ARDG_BEM(6)
+    default: return hipErrorInvalidValue;
+  }
+#undef ARDG_BEM
 }
 
 template <int N, typename P, bool BERN>

@@ -65,7 +65,7 @@ def test_batch_matches_per_mesh(scheme, prec, tmp_path):
     assert ("fp64" if prec == "fp64" else "fp32") in text
     for N in (1, 2, 3, 4):
         et, lt, gm = b.tiles(p, N)
-        assert et in (64, 128, 256) and lt in (64, 128, 256) and gm in (1, 2, 4, 8)
+        assert et in (0, 64, 128, 256) and lt in (0, 64, 128, 256) and gm in (1, 2, 4, 8)
 
 
 def test_batch_matches_oracle():
