@@ -22,10 +22,10 @@ namespace ardg {
 // latency is covered by arithmetic.  The fence between steps keeps at most
 // two steps of entries in SGPRs (without it the whole operator is hoisted
 // into SGPRs and spilled).  With NV = 2 every loaded entry feeds two vectors.
-template <int ROWS, int COLS, int LD, int NV, typename T, typename XA, typename YA>
+template <int ROWS, int COLS, int LD, int NV, typename T, typename XA, typename YA, int RBX = 4>
 __device__ inline void matvec_blk(cptr<T> A0, XA x, YA y) {
   constexpr int E = 12;
-  constexpr int RB = ROWS < 4 ? ROWS : 4;
+  constexpr int RB = ROWS < RBX ? ROWS : RBX;
   constexpr int CC = E / RB;
   constexpr int NRB = (ROWS + RB - 1) / RB;
   constexpr int NCC = (COLS + CC - 1) / CC;
@@ -86,15 +86,62 @@ struct OneVec {
   __device__ P operator[](int) const { return p; }
 };
 
-template <int ROWS, int COLS, typename T>
+template <int ROWS, int COLS, typename T, int RBX = 4>
 __device__ inline void matvec_pf(cptr<T> A0, const T* x, T* y) {
-  matvec_n<ROWS, COLS, 1, T>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
+  matvec_blk<ROWS, COLS, COLS, 1, T, OneVec<const T*>, OneVec<T*>, RBX>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
 }
 
 // column slice of a wider row-major operator (leading dimension LD)
 template <int ROWS, int COLS, int LD, typename T>
 __device__ inline void matvec_ld(cptr<T> A0, const T* x, T* y) {
   matvec_blk<ROWS, COLS, LD, 1, T>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
+}
+
+// Row groups of a constant operator block (row-major, leading dimension LD,
+// the first COLS columns used): group g < NG is the G rows g + q GS (q < G).
+// Each group's G dot products with x are formed in the prefetched
+// scalar-operand steps of matvec_blk (E entries per step) and handed to
+// emit(g, acc) as soon as the group is complete, so only G accumulators are
+// live at a time.
+template <int G, int NG, int GS, int COLS, int LD, typename T, typename Emit, int E = 12>
+__device__ inline void matvec_groups(cptr<T> A0, const T* x, Emit emit) {
+  constexpr int CC = E / G;
+  constexpr int NCC = (COLS + CC - 1) / CC;
+  constexpr int NSTEP = NG * NCC;
+  T buf[2][G][CC];
+  {
+    const cptr<T> A = fresh(A0);
+#pragma unroll
+    for (int r = 0; r < G; ++r)
+#pragma unroll
+      for (int q = 0; q < CC; ++q)
+        if (q < COLS) buf[0][r][q] = A[r * GS * LD + q];
+  }
+  T acc[G];
+#pragma unroll
+  for (int st = 0; st < NSTEP; ++st) {
+    const int g = st / NCC, q0 = (st % NCC) * CC;
+    const bool first = (st % NCC) == 0, last = (st % NCC) == NCC - 1;
+    row_fence();
+    if (st + 1 < NSTEP) {
+      const int g1 = (st + 1) / NCC, q1 = ((st + 1) % NCC) * CC;
+      const cptr<T> A = fresh(A0);
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+#pragma unroll
+        for (int q = 0; q < CC; ++q)
+          if (q1 + q < COLS) buf[(st + 1) & 1][r][q] = A[(g1 + r * GS) * LD + q1 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < CC; ++q)
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+        if (q0 + q < COLS) {
+          const T a = buf[st & 1][r][q];
+          acc[r] = (first && q == 0) ? a * x[q0] : fma(a, x[q0 + q], acc[r]);
+        }
+    if (last) emit(g, acc);
+  }
 }
 
 // y = A x with one operator row in flight at a time (no prefetch): the row

@@ -58,26 +58,27 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
 // that side's sub-triangle coefficients.  The operator entries stay
 // wave-uniform (one column slice per wave), the serial chain of each wave is
 // half that of one lane per edge, and the two partial sums meet in LDS.
-// Blocks past the interior range take 128 boundary faces each (mirror-ghost
-// operator, one lane per face).
+// The first blocks take 128 boundary faces each (mirror-ghost operator, one
+// lane per face).
 constexpr int kSplitTile = 64;
 
 template <int N, typename T>
 struct SplitShared {
-  static constexpr int Nfp = N + 1;
-  T part[4 * Nfp][kSplitTile];
-  T trace2[Nfp][kSplitTile];
+  T part[N + 1][kSplitTile];
 };
 
 // One tile of 64 interior edges starting at edge e0 (all 128 threads of the
-// block: wave s takes side s + 1).
+// block: wave s takes side s + 1).  The flux is linear in each side's
+// coefficients, so each wave forms its side's share of it -- the
+// reconstruction operator's columns of that side, contracted with the edge's
+// gamma and D one flux node at a time, and the upwind term where this side is
+// upstream -- and the two shares meet in LDS.
 template <int N, typename T, bool ALG1, bool BERN>
 __device__ inline void edge_split_tile(const DevMesh& m, int64_t e0, int field, const T* __restrict__ u,
                                        T* __restrict__ flux, SplitShared<N, T>& S) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp, K2 = 2 * Np;
   T (*part)[kSplitTile] = S.part;
-  T (*trace2)[kSplitTile] = S.trace2;
   const int64_t E = m.E_int + m.E_bdy;
   const cptr<T> op = opbase<T>(m);
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's side
@@ -109,72 +110,64 @@ __device__ inline void edge_split_tile(const DevMesh& m, int64_t e0, int field, 
     for (int n = 0; n < Np; ++n) c[n] = t[n];
     if (m.conv) face_bernstein_to_nodal<N, T>(op, tr);
   } else {
-    matvec_pf<Np, Np, T>(op + L.n2b, t, c);
+    // 3 rows x 4 contiguous entries per step: one 32-byte scalar load per row
+    matvec_pf<Np, Np, T, 3>(op + L.n2b, t, c);
   }
   decasteljau<N, T>(c, mu);
   // Algorithm 1 reduces to D (U1 - U2) when every edge of the tile has
   // D1 == D2; both waves see the same tile and take the same branch
   const bool quad = ALG1 && __ballot(valid && D1d != D2d) != 0;
-  const int base = !ALG1 ? L.kr : (quad ? L.u1r : L.udr);
-  T gg[4 * Nfp];
-  if (quad)
-    matvec_ld<4 * Nfp, Np, K2, T>(op + base + s * Np, c, gg);
-  else
-    matvec_ld<2 * Nfp, Np, K2, T>(op + base + s * Np, c, gg);
-  if (s == 1) {
-    const int R = quad ? 4 * Nfp : 2 * Nfp;
-#pragma unroll
-    for (int r = 0; r < 4 * Nfp; ++r)
-      if (r < R) part[r][l] = gg[r];
-    if (m.conv) {
-#pragma unroll
-      for (int j = 0; j < Nfp; ++j) trace2[j][l] = tr[j];
-    }
-  }
-  __syncthreads();
-  if (s == 1 || !valid) return;
   const T gR = (T)g.x, gS = (T)g.y;
   T F[Nfp];
   if (quad) {
     const T D1 = (T)D1d, D2 = (T)D2d;
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) {
-      const T a0 = gg[j] + part[j][l], a1 = gg[Nfp + j] + part[Nfp + j][l];
-      const T a2 = gg[2 * Nfp + j] + part[2 * Nfp + j][l], a3 = gg[3 * Nfp + j] + part[3 * Nfp + j][l];
-      F[j] = D1 * (gR * a0 + gS * a1) - D2 * (gR * a2 + gS * a3);
-    }
+    const T a1 = D1 * gR, b1 = D1 * gS, a2 = -D2 * gR, b2 = -D2 * gS;
+    matvec_groups<4, Nfp, Nfp, Np, K2, T>(op + L.u1r + s * Np, c, [&](int j, const T* a) {
+      F[j] = a1 * a[0] + b1 * a[1] + a2 * a[2] + b2 * a[3];
+    });
   } else {
     const T D = ALG1 ? (T)D1d : (T)m.Dfield[field];
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j)
-      F[j] = D * (gR * (gg[j] + part[j][l]) + gS * (gg[Nfp + j] + part[Nfp + j][l]));
+    const T a1 = D * gR, b1 = D * gS;
+    auto emit = [&](int j, const T* a) { F[j] = a1 * a[0] + b1 * a[1]; };
+    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (ALG1 ? L.udr : L.kr) + s * Np, c, emit);
   }
   if (m.conv) {
+    // upwind: node j of side 1 meets node N - j of side 2
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
       const T tau = op[L.tau + j];
       const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
-      const T fs = (vnj > (T)0) ? vnj * tr[j] : vnj * trace2[N - j][l];
-      F[j] -= fs;
+      const bool up = s ? !(vnj > (T)0) : (vnj > (T)0);
+      F[j] -= up ? vnj * tr[s ? N - j : j] : T(0);
     }
   }
+  if (s == 1) {
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) part[j][l] = F[j];
+  }
+  __syncthreads();
+  if (s == 1 || !valid) return;
   T* out = flux + ((int64_t)field * E + e) * Nfp;
 #pragma unroll
-  for (int j = 0; j < Nfp; ++j) out[j] = F[j];
+  for (int j = 0; j < Nfp; ++j) out[j] = F[j] + part[j][l];
 }
 
 template <int N, typename T, bool ALG1, bool BERN>
 __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
-                                                                    T* __restrict__ flux, int nb_int) {
+                                                                    T* __restrict__ flux, int nb_bdy) {
   __shared__ SplitShared<N, T> S;
   const int b = blockIdx.x;
-  if (b >= nb_int) {
-    // boundary faces: mirror-ghost operator, one lane per face
-    const int64_t e = m.E_int + (int64_t)(b - nb_int) * (2 * kSplitTile) + threadIdx.x;
+  if (b < nb_bdy) {
+    // boundary faces: mirror-ghost operator, one lane per face.  Their serial
+    // chain is the longest of the launch, so they take the first blocks and
+    // run beside the interior tiles instead of after them
+    const int64_t e = m.E_int + (int64_t)b * (2 * kSplitTile) + threadIdx.x;
     if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, blockIdx.y, u, flux);
     return;
   }
-  edge_split_tile<N, T, ALG1, BERN>(m, xcd_block(b, nb_int) * kSplitTile, blockIdx.y, u, flux, S);
+  // nb_bdy is a multiple of 8, so b - nb_bdy keeps b's XCD
+  edge_split_tile<N, T, ALG1, BERN>(m, xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kSplitTile,
+                                    blockIdx.y, u, flux, S);
 }
 
 // Batched form: persistent blocks over items of many meshes (constant D, no
@@ -438,14 +431,14 @@ hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flu
   }
   if (split) {
     const int64_t nbi = (m.E_int + kSplitTile - 1) / kSplitTile;
-    const int64_t nbb = (m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile);
+    const int64_t nbb = ((m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile) + 7) / 8 * 8;
     dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
     if (m.alg1)
       hipLaunchKernelGGL((edge_split_kernel<N, T, true, BERN>), grid, dim3(2 * kSplitTile), 0, st, m,
-                         (const T*)u, (T*)flux, (int)nbi);
+                         (const T*)u, (T*)flux, (int)nbb);
     else
       hipLaunchKernelGGL((edge_split_kernel<N, T, false, BERN>), grid, dim3(2 * kSplitTile), 0, st, m,
-                         (const T*)u, (T*)flux, (int)nbi);
+                         (const T*)u, (T*)flux, (int)nbb);
     return hipGetLastError();
   }
   dim3 grid((unsigned)((E + 255) / 256), (unsigned)nfields);

@@ -211,7 +211,7 @@ template <int N, typename P, bool ALG1, bool CONV>
 __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
                                                               const typename Mma<P>::T* __restrict__ u,
                                                               typename Mma<P>::T* __restrict__ flux,
-                                                              int nb_int) {
+                                                              int nb_bdy) {
   using T = typename Mma<P>::T;
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
@@ -222,13 +222,15 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
   const int field = blockIdx.y;
   const int64_t E = m.E_int + m.E_bdy;
   const int b = blockIdx.x;
-  if (b >= nb_int) {
-    // boundary faces: mirror-ghost operator on the vector unit, one lane per face
-    const int64_t e = m.E_int + (int64_t)(b - nb_int) * kEdgeTile + l;
+  if (b < nb_bdy) {
+    // boundary faces: mirror-ghost operator on the vector unit, one lane per
+    // face, in the first blocks so that their long serial chain runs beside
+    // the interior tiles
+    const int64_t e = m.E_int + (int64_t)b * kEdgeTile + l;
     if (e < E) boundary_body<N, T, ALG1, false>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
-  const int64_t e0 = xcd_block(b, nb_int) * kEdgeTile;
+  const int64_t e0 = xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kEdgeTile;   // nb_bdy % 8 == 0
   const int nval = (int)((m.E_int - e0) < kEdgeTile ? (m.E_int - e0) : kEdgeTile);
   // rotated lattice node -> element node for faces 0 and 2 (face 1: identity)
   for (int n = l; n < Np; n += kEdgeTile) {
@@ -278,22 +280,22 @@ template <int N, typename P>
 hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   using T = typename Mma<P>::T;
   const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
-  const int64_t nbb = (m.E_bdy + kEdgeTile - 1) / kEdgeTile;
-  if (nbi + nbb == 0) return hipSuccess;
+  const int64_t nbb = ((m.E_bdy + kEdgeTile - 1) / kEdgeTile + 7) / 8 * 8;
+  if (m.E_int + m.E_bdy == 0) return hipSuccess;
   dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
   const T* uu = (const T*)u;
   T* ff = (T*)flux;
-  const int ni = (int)nbi;
+  const int nbd = (int)nbb;
   if (m.alg1) {
     if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
     else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
   } else {
     if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
     else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, ni);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
   }
   return hipGetLastError();
 }
