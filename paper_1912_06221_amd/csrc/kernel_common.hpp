@@ -230,7 +230,7 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
           const double r = (double)sh[i];
           A[i] = (s == 0) ? r : io.Ap[q] + 2.0 * r;
           const T x = (T)(io.Up[q] + c * r);
-          if (vn_lds) sh[i] = x; else vn[i] = x;
+          if (vn_lds) sh[i] = x; else if (vn) vn[i] = x;
         }
       }
     } else {

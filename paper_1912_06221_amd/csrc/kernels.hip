@@ -52,91 +52,113 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
   edge_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, blockIdx.y, u, flux);
 }
 
-// Interior edges split by side: a block of two waves takes 64 edges; wave s
-// (s = 0, 1) gathers, rotates, converts and subdivides element s+1 of every
-// edge and applies the columns of the reconstruction operator that act on
-// that side's sub-triangle coefficients.  The operator entries stay
-// wave-uniform (one column slice per wave), the serial chain of each wave is
-// half that of one lane per edge, and the two partial sums meet in LDS.
-// The first blocks take 128 boundary faces each (mirror-ghost operator, one
-// lane per face).
+// Interior edges split by side: a block of two waves takes a tile of 64
+// edges; wave s (s = 0, 1) gathers, rotates, converts and subdivides element
+// s+1 of every edge and applies the columns of the reconstruction operator
+// that act on that side's sub-triangle coefficients.  The operator entries
+// stay wave-uniform (one column slice per wave), the serial chain of each
+// wave is half that of one lane per edge, and the two partial sums meet in
+// LDS.
 constexpr int kSplitTile = 64;
 
 template <int N, typename T>
 struct SplitShared {
-  T part[N + 1][kSplitTile];
+  T part[N + 1][kSplitTile];   // side 2's flux shares
 };
 
-// One tile of 64 interior edges starting at edge e0 (all 128 threads of the
+// One side of one tile of 64 interior edges: what the wave gathers from
+// memory before any arithmetic.
+template <int N, typename T>
+struct SplitIn {
+  static constexpr int Np = (N + 1) * (N + 2) / 2;
+  T v[Np];               // the side's element values (nodal or Bernstein)
+  double2 mu, g, vn;     // apex weights of this side, (gamma_R, gamma_S) sJ, n.v sJ
+  double D1, D2;         // element D of both sides (Algorithm 1)
+  int f;                 // this side's face
+  bool valid;
+  int64_t e;
+};
+
+// Wave s of the block (side s + 1) issues the loads of the tile at e0.
+template <int N, typename T, bool ALG1, bool CONV>
+__device__ inline void edge_split_gather(const DevMesh& m, int64_t e0, int field, const T* __restrict__ u,
+                                         SplitIn<N, T>& in) {
+  constexpr int Np = SplitIn<N, T>::Np;
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  in.valid = e0 + l < m.E_int;
+  // lanes past the last edge read the tile's first edge (e0 < E_int)
+  in.e = in.valid ? e0 + l : e0;
+  const int2 ef = m.ef[in.e];
+  in.mu = s ? m.mu2[in.e] : m.mu1[in.e];
+  in.g = m.gam[in.e];
+  in.vn = make_double2(0.0, 0.0);
+  if (CONV) in.vn = m.vn[in.e];
+  const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
+  const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
+  const int k = s ? k2 : k1;
+  in.f = s ? fb : fa;
+  const T* uf = u + (int64_t)field * m.K * Np;
+#pragma unroll
+  for (int n = 0; n < Np; ++n) in.v[n] = uf[(int64_t)k * Np + n];
+  in.D1 = 0.0;
+  in.D2 = 0.0;
+  if (ALG1) {
+    in.D1 = m.Delem[k1];
+    in.D2 = m.Delem[k2];
+  }
+}
+
+// The flux of the tile from the gathered inputs (all 128 threads of the
 // block: wave s takes side s + 1).  The flux is linear in each side's
 // coefficients, so each wave forms its side's share of it -- the
 // reconstruction operator's columns of that side, contracted with the edge's
 // gamma and D one flux node at a time, and the upwind term where this side is
-// upstream -- and the two shares meet in LDS.
-template <int N, typename T, bool ALG1, bool BERN>
-__device__ inline void edge_split_tile(const DevMesh& m, int64_t e0, int field, const T* __restrict__ u,
-                                       T* __restrict__ flux, SplitShared<N, T>& S) {
+// upstream -- and the two shares meet in LDS (part, Nfp x 64).
+template <int N, typename T, bool ALG1, bool BERN, bool CONV>
+__device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restrict__ flux, const SplitIn<N, T>& in,
+                                         T (*part)[kSplitTile]) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp, K2 = 2 * Np;
-  T (*part)[kSplitTile] = S.part;
   const int64_t E = m.E_int + m.E_bdy;
   const cptr<T> op = opbase<T>(m);
-  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's side
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
-  const bool valid = e0 + l < m.E_int;
-  const int64_t e = valid ? e0 + l : e0;
-  const int2 ef = m.ef[e];
-  const double2 mu = s ? m.mu2[e] : m.mu1[e];
-  const double2 g = m.gam[e];
-  double2 vn = make_double2(0.0, 0.0);
-  if (m.conv) vn = m.vn[e];
-  const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
-  const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
-  const int k = s ? k2 : k1, f = s ? fb : fa;
-  const T* uf = u + (int64_t)field * m.K * Np;
-  T v[Np];
-#pragma unroll
-  for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
-  double D1d = 0.0, D2d = 0.0;
-  if (ALG1) {
-    D1d = m.Delem[k1];
-    D2d = m.Delem[k2];
-  }
   T t[Np], tr[Nfp], c[Np];
-  rotate_to_face<N, T>(v, f, t, tr);
+  rotate_to_face<N, T>(in.v, in.f, t, tr);
   if (BERN) {
     // the stage input holds Bernstein coefficients: rotation only
 #pragma unroll
     for (int n = 0; n < Np; ++n) c[n] = t[n];
-    if (m.conv) face_bernstein_to_nodal<N, T>(op, tr);
+    if (CONV) face_bernstein_to_nodal<N, T>(op, tr);
   } else {
     // 3 rows x 4 contiguous entries per step: one 32-byte scalar load per row
     matvec_pf<Np, Np, T, 3>(op + L.n2b, t, c);
   }
-  decasteljau<N, T>(c, mu);
+  decasteljau<N, T>(c, in.mu);
   // Algorithm 1 reduces to D (U1 - U2) when every edge of the tile has
   // D1 == D2; both waves see the same tile and take the same branch
-  const bool quad = ALG1 && __ballot(valid && D1d != D2d) != 0;
-  const T gR = (T)g.x, gS = (T)g.y;
+  const bool quad = ALG1 && __ballot(in.valid && in.D1 != in.D2) != 0;
+  const T gR = (T)in.g.x, gS = (T)in.g.y;
   T F[Nfp];
   if (quad) {
-    const T D1 = (T)D1d, D2 = (T)D2d;
+    const T D1 = (T)in.D1, D2 = (T)in.D2;
     const T a1 = D1 * gR, b1 = D1 * gS, a2 = -D2 * gR, b2 = -D2 * gS;
     matvec_groups<4, Nfp, Nfp, Np, K2, T>(op + L.u1r + s * Np, c, [&](int j, const T* a) {
       F[j] = a1 * a[0] + b1 * a[1] + a2 * a[2] + b2 * a[3];
     });
   } else {
-    const T D = ALG1 ? (T)D1d : (T)m.Dfield[field];
+    const T D = ALG1 ? (T)in.D1 : (T)m.Dfield[field];
     const T a1 = D * gR, b1 = D * gS;
     auto emit = [&](int j, const T* a) { F[j] = a1 * a[0] + b1 * a[1]; };
     matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (ALG1 ? L.udr : L.kr) + s * Np, c, emit);
   }
-  if (m.conv) {
+  if (CONV) {
     // upwind: node j of side 1 meets node N - j of side 2
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
       const T tau = op[L.tau + j];
-      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
+      const T vnj = (T)in.vn.x + tau * (T)(in.vn.y - in.vn.x);
       const bool up = s ? !(vnj > (T)0) : (vnj > (T)0);
       F[j] -= up ? vnj * tr[s ? N - j : j] : T(0);
     }
@@ -146,28 +168,32 @@ __device__ inline void edge_split_tile(const DevMesh& m, int64_t e0, int field, 
     for (int j = 0; j < Nfp; ++j) part[j][l] = F[j];
   }
   __syncthreads();
-  if (s == 1 || !valid) return;
-  T* out = flux + ((int64_t)field * E + e) * Nfp;
+  if (s == 0 && in.valid) {
+    T* out = flux + ((int64_t)field * E + in.e) * Nfp;
 #pragma unroll
-  for (int j = 0; j < Nfp; ++j) out[j] = F[j] + part[j][l];
+    for (int j = 0; j < Nfp; ++j) out[j] = F[j] + part[j][l];
+  }
 }
 
-template <int N, typename T, bool ALG1, bool BERN>
+// Blocks [0, nb_bdy) take the boundary faces, 128 each (mirror-ghost
+// operator, one lane per face): their serial chain is the longest of the
+// launch, so they start first and run beside the interior tiles.  The other
+// blocks take one tile of 64 interior edges each.
+template <int N, typename T, bool ALG1, bool BERN, bool CONV>
 __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
                                                                     T* __restrict__ flux, int nb_bdy) {
   __shared__ SplitShared<N, T> S;
   const int b = blockIdx.x;
   if (b < nb_bdy) {
-    // boundary faces: mirror-ghost operator, one lane per face.  Their serial
-    // chain is the longest of the launch, so they take the first blocks and
-    // run beside the interior tiles instead of after them
     const int64_t e = m.E_int + (int64_t)b * (2 * kSplitTile) + threadIdx.x;
     if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, blockIdx.y, u, flux);
     return;
   }
   // nb_bdy is a multiple of 8, so b - nb_bdy keeps b's XCD
-  edge_split_tile<N, T, ALG1, BERN>(m, xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kSplitTile,
-                                    blockIdx.y, u, flux, S);
+  const int64_t e0 = xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kSplitTile;
+  SplitIn<N, T> in;
+  edge_split_gather<N, T, ALG1, CONV>(m, e0, blockIdx.y, u, in);
+  edge_split_finish<N, T, ALG1, BERN, CONV>(m, blockIdx.y, flux, in, S.part);
 }
 
 // Batched form: persistent blocks over items of many meshes (constant D, no
@@ -184,7 +210,9 @@ __global__ __launch_bounds__(2 * kSplitTile) void batch_edge_split_kernel(const 
     const int t = __builtin_amdgcn_readfirstlane(w.y);
     const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
     if (t >= 0) {
-      edge_split_tile<N, T, false, false>(P->m, (int64_t)t * kSplitTile, 0, vin, (T*)P->flux, S);
+      SplitIn<N, T> in;
+      edge_split_gather<N, T, false, false>(P->m, (int64_t)t * kSplitTile, 0, vin, in);
+      edge_split_finish<N, T, false, false, false>(P->m, 0, (T*)P->flux, in, S.part);
     } else {
       const int64_t e = P->m.E_int + (int64_t)(-1 - t) * (2 * kSplitTile) + threadIdx.x;
       if (e < P->m.E_int + P->m.E_bdy) boundary_body<N, T, false, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
@@ -433,12 +461,17 @@ hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flu
     const int64_t nbi = (m.E_int + kSplitTile - 1) / kSplitTile;
     const int64_t nbb = ((m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile) + 7) / 8 * 8;
     dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
-    if (m.alg1)
-      hipLaunchKernelGGL((edge_split_kernel<N, T, true, BERN>), grid, dim3(2 * kSplitTile), 0, st, m,
-                         (const T*)u, (T*)flux, (int)nbb);
-    else
-      hipLaunchKernelGGL((edge_split_kernel<N, T, false, BERN>), grid, dim3(2 * kSplitTile), 0, st, m,
-                         (const T*)u, (T*)flux, (int)nbb);
+#define ARDG_SPLIT_LAUNCH(A, C)                                                                  \
+  hipLaunchKernelGGL((edge_split_kernel<N, T, A, BERN, C>), grid, dim3(2 * kSplitTile), 0, st, m, \
+                     (const T*)u, (T*)flux, (int)nbb)
+    if (m.alg1) {
+      if (m.conv) ARDG_SPLIT_LAUNCH(true, true);
+      else ARDG_SPLIT_LAUNCH(true, false);
+    } else {
+      if (m.conv) ARDG_SPLIT_LAUNCH(false, true);
+      else ARDG_SPLIT_LAUNCH(false, false);
+    }
+#undef ARDG_SPLIT_LAUNCH
     return hipGetLastError();
   }
   dim3 grid((unsigned)((E + 255) / 256), (unsigned)nfields);
