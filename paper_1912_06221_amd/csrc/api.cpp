@@ -258,7 +258,8 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
       // kernel implementations.  Element kernel: matrix cores (default) or one
       // thread per element (ARDG_ELEMENT_KERNEL=valu).  Edge kernel: chosen
       // per launch from the grid size (default), two waves per tile split by
-      // side (ARDG_EDGE_KERNEL=split), one thread per edge (=lane) or interior
+      // side (ARDG_EDGE_KERNEL=split), the same with the conversion on the
+      // matrix cores (=split-mfma), one thread per edge (=lane) or interior
       // edges on the matrix cores (=mfma).
       const char* ek = std::getenv("ARDG_ELEMENT_KERNEL");
       m->dm.elem_mfma = (ek && std::string(ek) == "valu") ? 0 : 1;
@@ -266,7 +267,8 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
       const std::string eds = ed ? ed : "";
       m->dm.edge_kernel = eds == "mfma" ? EDGE_MFMA
                           : eds == "lane" ? EDGE_LANE
-                          : eds == "split" ? EDGE_SPLIT : EDGE_AUTO;
+                          : eds == "split" ? EDGE_SPLIT
+                          : eds == "split-mfma" ? EDGE_SPLIT_MFMA : EDGE_AUTO;
       // stage vectors: nodal values (default), or Bernstein coefficients
       // emitted by the element kernel where the kernels allow it
       // (ARDG_STAGE_FORM=bernstein)
@@ -520,7 +522,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // matrix-core element kernel and a vector-unit edge kernel; FP64 and FP32.
 static bool use_bern(ardg_mesh mesh, int precision) {
   return mesh->dm.bern && mesh->dm.elem_mfma && mesh->dm.edge_kernel != EDGE_MFMA &&
-         precision != ARDG_BF16X3;
+         mesh->dm.edge_kernel != EDGE_SPLIT_MFMA && precision != ARDG_BF16X3;
 }
 
 ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,

@@ -55,7 +55,7 @@ struct OpLayout {
 // EDGE_AUTO picks EDGE_SPLIT where one thread per edge leaves the chip
 // latency-bound (few waves per SIMD, or high order with few waves resident)
 // and EDGE_LANE otherwise.
-enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3 };
+enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, EDGE_SPLIT_MFMA = 4 };
 
 struct DevMesh {
   int N = 0;
@@ -136,6 +136,10 @@ hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int ni
 // launch_edge_flux).
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st);
+// Side-split tiles with the nodal -> Bernstein conversion on the matrix cores
+// (nodal stage vectors).
+hipError_t launch_edge_split_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
+                                  hipStream_t st);
 // Batched element kernel on the matrix cores (64-element tiles).
 hipError_t launch_batch_element_mfma(int N, bool fp64, int grid, const BatchProb* probs, const int2* items,
                                      int nitems, const Epilogue& epi, int in_u, int write_v, hipStream_t st);

@@ -525,7 +525,13 @@ hipError_t elem_dispatch(const DevMesh& m, int nf, const void* vin, const void* 
 
 hipError_t launch_edge_flux(const DevMesh& m, int prec, bool bern, int nfields, const void* u, void* flux,
                             hipStream_t st) {
-  // split-BF16 products exist only on the matrix cores (nodal stage input)
+  // split-BF16 products exist only on the matrix cores (nodal stage input):
+  // side-split tiles up to N = 3, one wave per tile above (measured faster)
+  if (m.edge_kernel == EDGE_SPLIT_MFMA ||
+      (prec == PREC_BF16X3 && m.edge_kernel == EDGE_AUTO && m.N <= 3)) {
+    if (bern) return hipErrorInvalidValue;
+    return launch_edge_split_mfma(m, prec, nfields, u, flux, st);
+  }
   if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) {
     if (bern) return hipErrorInvalidValue;
     return launch_edge_mfma(m, prec, nfields, u, flux, st);

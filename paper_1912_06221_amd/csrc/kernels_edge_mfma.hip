@@ -276,6 +276,222 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
   }
 }
 
+// Side-split tile with the conversion on the matrix cores.  A block of two
+// waves takes 64 interior edges, wave s side s + 1.  The wave gathers its
+// side's element values straight into B fragments (16 edges per fragment,
+// rotated by the index remap), converts them to Bernstein coefficients with
+// one (Np x Np) x (Np x 16) product per 16 edges, and hands the coefficients
+// through its own LDS rows to one lane per edge for the subdivision and its
+// side's columns of the reconstruction operator (vector unit, scalar operands,
+// as in the vector-unit split kernel).  The conversion runs on the matrix pipe
+// beside the other waves' vector work.
+template <int N, typename P, bool ALG1, bool CONV>
+__global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
+                                                                   const typename Mma<P>::T* __restrict__ u,
+                                                                   typename Mma<P>::T* __restrict__ flux,
+                                                                   int nb_bdy) {
+  using M = Mma<P>;
+  using T = typename M::T;
+  typedef typename M::acc acc_t;
+  typedef typename M::frag frag_t;
+  constexpr int KPL = M::KPL, KS = M::KSTEP;
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp, K2 = 2 * Np;
+  constexpr int MT = (Np + 15) / 16;
+  constexpr int KC = (Np + KS - 1) / KS;
+  __shared__ T cbuf[2][Np * kEdgeTile];   // per wave: [coefficient][edge]; wave 1's rows then hold the flux shares
+  __shared__ int rot[2 * Np];
+  const int field = blockIdx.y;
+  const int64_t E = m.E_int + m.E_bdy;
+  const int b = blockIdx.x;
+  if (b < nb_bdy) {
+    // boundary faces first (mirror-ghost operator, one lane per face)
+    const int64_t e = m.E_int + (int64_t)b * (2 * kEdgeTile) + threadIdx.x;
+    if (e < E) boundary_body<N, T, ALG1, false>(m, opbase<T>(m), e, field, u, flux);
+    return;
+  }
+  const int64_t e0 = xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kEdgeTile;   // nb_bdy % 8 == 0
+  // rotated lattice node -> element node for faces 0 and 2 (face 1: identity)
+  for (int n = threadIdx.x; n < Np; n += 2 * kEdgeTile) {
+    int j = 0;
+    while (lat(N, 0, j + 1) <= n) ++j;
+    const int i = n - lat(N, 0, j);
+    rot[n] = lat(N, j, N - i - j);
+    rot[Np + n] = lat(N, N - i - j, i);
+  }
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's side
+  const int l = threadIdx.x & 63, col = l & 15, grp = l >> 4;
+  const bool valid = e0 + l < m.E_int;
+  const int64_t e = valid ? e0 + l : e0;
+  const int2 ef = m.ef[e];
+  const double2 mu = s ? m.mu2[e] : m.mu1[e];
+  const double2 g = m.gam[e];
+  double2 vn = make_double2(0.0, 0.0);
+  if (CONV) vn = m.vn[e];
+  const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
+  const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
+  const int k = s ? k2 : k1, f = s ? fb : fa;
+  double D1d = 0.0, D2d = 0.0;
+  if (ALG1) {
+    D1d = m.Delem[k1];
+    D2d = m.Delem[k2];
+  }
+  const T* uf = u + (int64_t)field * m.K * Np;
+  const cptr<T> op = opbase<T>(m);
+  const T* opg = (const T*)(const void*)opbase<T>(m);
+  // conversion matrix as A fragments: row 16 mt + col, columns kidx(c, grp, .)
+  frag_t aN[MT][KC];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      T v[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int i = 16 * mt + col, kk = kidx<M>(c, grp, t);
+        v[t] = (i < Np && kk < Np) ? opg[L.n2b + i * Np + kk] : T(0);
+      }
+      aN[mt][c] = M::make(v);
+    }
+  __syncthreads();   // rot
+
+  // gather + rotate + convert, 16 edges at a time; coefficients to LDS rows
+  T* cb = cbuf[s];
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb) {
+    const int el = 16 * sb + col;
+    const int kk = __shfl(k, el), ff = __shfl(f, el);
+    const T* ue = uf + (int64_t)kk * Np;
+    frag_t bu[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      T v[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int n = kidx<M>(c, grp, t);
+        const int nc = n < Np ? n : 0;
+        const T x = ue[ff == 1 ? nc : rot[(ff >> 1) * Np + nc]];
+        v[t] = n < Np ? x : T(0);
+      }
+      bu[c] = M::make(v);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      acc_t cm = M::zero();
+#pragma unroll
+      for (int c = 0; c < KC; ++c) cm = M::mma(aN[mt][c], bu[c], cm);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * mt + M::row(grp, r);
+        if (row < Np) cb[row * kEdgeTile + el] = cm[r];
+      }
+    }
+  }
+  // the rows were written by this wave's own lanes: a wave-level fence
+  // orders the LDS writes before the reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // one lane per edge: subdivision, reconstruction columns of this side
+  T c[Np], tr[Nfp];
+#pragma unroll
+  for (int n = 0; n < Np; ++n) c[n] = cb[n * kEdgeTile + l];
+  if (CONV) {
+    // nodal trace on the face (the hypotenuse of the rotated triangle)
+#pragma unroll
+    for (int j = 0; j <= N; ++j) tr[j] = c[lat(N, N - j, j)];
+    face_bernstein_to_nodal<N, T>(op, tr);
+  }
+  decasteljau<N, T>(c, mu);
+  const bool quad = ALG1 && __ballot(valid && D1d != D2d) != 0;
+  const T gR = (T)g.x, gS = (T)g.y;
+  T F[Nfp];
+  if (quad) {
+    const T D1 = (T)D1d, D2 = (T)D2d;
+    const T a1 = D1 * gR, b1 = D1 * gS, a2 = -D2 * gR, b2 = -D2 * gS;
+    matvec_groups<4, Nfp, Nfp, Np, K2, T>(op + L.u1r + s * Np, c, [&](int j, const T* a) {
+      F[j] = a1 * a[0] + b1 * a[1] + a2 * a[2] + b2 * a[3];
+    });
+  } else {
+    const T D = ALG1 ? (T)D1d : (T)m.Dfield[field];
+    const T a1 = D * gR, b1 = D * gS;
+    auto emit = [&](int j, const T* a) { F[j] = a1 * a[0] + b1 * a[1]; };
+    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (ALG1 ? L.udr : L.kr) + s * Np, c, emit);
+  }
+  if (CONV) {
+    // upwind: node j of side 1 meets node N - j of side 2
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T tau = op[L.tau + j];
+      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
+      const bool up = s ? !(vnj > (T)0) : (vnj > (T)0);
+      F[j] -= up ? vnj * tr[s ? N - j : j] : T(0);
+    }
+  }
+  // side 2's share into its own (already read) LDS rows
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  T* part = cbuf[1];
+  if (s == 1) {
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) part[j * kEdgeTile + l] = F[j];
+  }
+  __syncthreads();
+  if (s == 0 && valid) {
+    T* out = flux + ((int64_t)field * E + e) * Nfp;
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) out[j] = F[j] + part[j * kEdgeTile + l];
+  }
+}
+
+template <int N, typename P>
+hipError_t edge_smfma_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
+  using T = typename Mma<P>::T;
+  if (m.E_int + m.E_bdy == 0) return hipSuccess;
+  const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
+  const int64_t nbb = ((m.E_bdy + 2 * kEdgeTile - 1) / (2 * kEdgeTile) + 7) / 8 * 8;
+  dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
+  const T* uu = (const T*)u;
+  T* ff = (T*)flux;
+  const int nbd = (int)nbb;
+#define ARDG_SMFMA(A, C) \
+  hipLaunchKernelGGL((edge_smfma_kernel<N, P, A, C>), grid, dim3(2 * kEdgeTile), 0, st, m, uu, ff, nbd)
+  if (m.alg1) {
+    if (m.conv) ARDG_SMFMA(true, true);
+    else ARDG_SMFMA(true, false);
+  } else {
+    if (m.conv) ARDG_SMFMA(false, true);
+    else ARDG_SMFMA(false, false);
+  }
+#undef ARDG_SMFMA
+  return hipGetLastError();
+}
+
+template <typename P>
+hipError_t edge_smfma_dispatch(const DevMesh& m, int nf, const void* u, void* flux, hipStream_t st) {
+  switch (m.N) {
+    case 1: return edge_smfma_t<1, P>(m, nf, u, flux, st);
+    case 2: return edge_smfma_t<2, P>(m, nf, u, flux, st);
+    case 3: return edge_smfma_t<3, P>(m, nf, u, flux, st);
+    case 4: return edge_smfma_t<4, P>(m, nf, u, flux, st);
+    case 5: return edge_smfma_t<5, P>(m, nf, u, flux, st);
+    case 6: return edge_smfma_t<6, P>(m, nf, u, flux, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_edge_split_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
+                                  hipStream_t st) {
+  switch (prec) {
+    case PREC_FP64: return edge_smfma_dispatch<double>(m, nfields, u, flux, st);
+    case PREC_FP32: return edge_smfma_dispatch<float>(m, nfields, u, flux, st);
+    case PREC_BF16X3: return edge_smfma_dispatch<Bf16x3>(m, nfields, u, flux, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int N, typename P>
 hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   using T = typename Mma<P>::T;

@@ -248,10 +248,10 @@ def _blocks_D(mesh):
 def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
     """The kernel variants -- default (edge kernel chosen by grid size,
     matrix-core element kernel, nodal stage vectors), the same with
-    Bernstein-form stage vectors, edge tiles split by side, one thread per
-    edge with Bernstein input, one thread per edge / per element, all
-    matrix-core -- compute the same flux and RHS (to rounding), each matching
-    the oracle."""
+    Bernstein-form stage vectors, edge tiles split by side (conversion on the
+    vector unit or on the matrix cores), one thread per edge with Bernstein
+    input, one thread per edge / per element, all matrix-core -- compute the
+    same flux and RHS (to rounding), each matching the oracle."""
     import torch
     from paper_1912_06221_amd import ardg
     m, N, dk, vel = case
@@ -265,7 +265,8 @@ def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
     tol = TOL64 if prec == "fp64" else TOL32
     outs = {}
     variants = {"default": (None, None, None), "bernstein-stages": (None, None, "bernstein"),
-                "split": ("split", None, None), "lane-bernstein": ("lane", None, "bernstein"),
+                "split": ("split", None, None), "split-mfma": ("split-mfma", None, None),
+                "lane-bernstein": ("lane", None, "bernstein"),
                 "lane": ("lane", "valu", None), "mfma": ("mfma", "mfma", None)}
     for variant, (edge_k, elem_k, form) in variants.items():
         for var, val in (("ARDG_EDGE_KERNEL", edge_k), ("ARDG_ELEMENT_KERNEL", elem_k),
