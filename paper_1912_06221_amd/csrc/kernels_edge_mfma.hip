@@ -1,7 +1,7 @@
-// Edge kernel on the matrix cores (gfx950 MFMA, 16x16 tiles).
+// Edge kernels on the matrix cores (gfx950 MFMA, 16x16 tiles).
 //
-// One wave takes 64 consecutive interior edges, as four sub-tiles of 16 edges
-// (the 16 columns of the MFMA tiles).  Per side of the edges:
+// edge_mfma_kernel: one wave takes 64 consecutive interior edges, as four
+// sub-tiles of 16 edges (the 16 columns of the MFMA tiles).  Per side:
 //   1. gather + rotate: the B fragments are read straight from the stage
 //      vector, the face's node reordering (section "Reordering nodes in the
 //      reference domain") applied as an index remap;
@@ -19,6 +19,9 @@
 // same lane; the flux of the 64 edges is formed there, staged in LDS and
 // written as one contiguous block.  Boundary faces (mirror ghost) run the
 // vector-unit body in the same launch, one lane per face.
+//
+// edge_smfma_kernel: the side-split tile (two waves per 64 edges, one per
+// side) with only the conversion of step 2 on the matrix cores; see there.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
