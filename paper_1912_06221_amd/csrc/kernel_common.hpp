@@ -53,6 +53,16 @@ __device__ inline int64_t xcd_block(int64_t bid, int64_t nb) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+// Blocks of a launch over (tile, field) pairs, nb in all: each XCD takes a
+// contiguous range of pairs, fields fastest, so that the blocks of one
+// tile's fields run together under one L2 and read the tile's edge or element
+// tables from HBM once.
+__device__ inline void tile_and_field(int64_t bid, int64_t nb, int nf, int64_t& tile, int& field) {
+  const int64_t L = xcd_block(bid, nb);
+  tile = L / nf;
+  field = (int)(L - tile * nf);
+}
+
 // The operator pointer is wave-uniform; readfirstlane states that to the
 // compiler also when the descriptor was read from memory (batched kernels).
 template <typename P>

@@ -46,10 +46,13 @@ namespace ardg {
 
 template <int N, typename T, bool ALG1, bool BERN>
 __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __restrict__ u,
-                                                        T* __restrict__ flux) {
-  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+                                                        T* __restrict__ flux, int nf) {
+  int64_t tile;
+  int field;
+  tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
+  const int64_t e = tile * blockDim.x + threadIdx.x;
   if (e >= m.E_int + m.E_bdy) return;
-  edge_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, blockIdx.y, u, flux);
+  edge_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, field, u, flux);
 }
 
 // Interior edges split by side: a block of two waves takes a tile of 64
@@ -181,19 +184,23 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
 // blocks take one tile of 64 interior edges each.
 template <int N, typename T, bool ALG1, bool BERN, bool CONV>
 __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
-                                                                    T* __restrict__ flux, int nb_bdy) {
+                                                                    T* __restrict__ flux, int nb_bdy, int nf) {
   __shared__ SplitShared<N, T> S;
-  const int b = blockIdx.x;
-  if (b < nb_bdy) {
-    const int64_t e = m.E_int + (int64_t)b * (2 * kSplitTile) + threadIdx.x;
-    if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, blockIdx.y, u, flux);
+  const int64_t b = blockIdx.x;
+  const int64_t nbt = (int64_t)nb_bdy * nf;
+  if (b < nbt) {
+    const int field = (int)(b % nf);
+    const int64_t e = m.E_int + (b / nf) * (2 * kSplitTile) + threadIdx.x;
+    if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
-  // nb_bdy is a multiple of 8, so b - nb_bdy keeps b's XCD
-  const int64_t e0 = xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kSplitTile;
+  // nb_bdy is a multiple of 8, so b - nbt keeps b's XCD
+  int64_t tile;
+  int field;
+  tile_and_field(b - nbt, (int64_t)gridDim.x - nbt, nf, tile, field);
   SplitIn<N, T> in;
-  edge_split_gather<N, T, ALG1, CONV>(m, e0, blockIdx.y, u, in);
-  edge_split_finish<N, T, ALG1, BERN, CONV>(m, blockIdx.y, flux, in, S.part);
+  edge_split_gather<N, T, ALG1, CONV>(m, tile * kSplitTile, field, u, in);
+  edge_split_finish<N, T, ALG1, BERN, CONV>(m, field, flux, in, S.part);
 }
 
 // Batched form: persistent blocks over items of many meshes (constant D, no
@@ -366,11 +373,13 @@ __device__ inline void element_tile(const DevMesh& m, cptr<T> op, int64_t k0, in
 
 template <int N, typename T, bool CONV>
 __global__ __launch_bounds__(kElemBlock) __attribute__((amdgpu_waves_per_eu(ElemTune<N>::waves)))
-void element_kernel(DevMesh m, const T* __restrict__ vin, const T* __restrict__ flux, Epilogue epi) {
+void element_kernel(DevMesh m, const T* __restrict__ vin, const T* __restrict__ flux, Epilogue epi, int nf) {
   constexpr int Np = (N + 1) * (N + 2) / 2;
   __shared__ T sh[kElemBlock * Np];
-  const int64_t k0 = xcd_block(blockIdx.x, gridDim.x) * kElemBlock;
-  element_tile<N, T, CONV, kElemBlock>(m, opbase<T>(m), k0, blockIdx.y, vin, flux, epi, sh);
+  int64_t tile;
+  int field;
+  tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
+  element_tile<N, T, CONV, kElemBlock>(m, opbase<T>(m), tile * kElemBlock, field, vin, flux, epi, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,10 +469,10 @@ hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flu
   if (split) {
     const int64_t nbi = (m.E_int + kSplitTile - 1) / kSplitTile;
     const int64_t nbb = ((m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile) + 7) / 8 * 8;
-    dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
+    dim3 grid((unsigned)((nbi + nbb) * nfields));
 #define ARDG_SPLIT_LAUNCH(A, C)                                                                  \
   hipLaunchKernelGGL((edge_split_kernel<N, T, A, BERN, C>), grid, dim3(2 * kSplitTile), 0, st, m, \
-                     (const T*)u, (T*)flux, (int)nbb)
+                     (const T*)u, (T*)flux, (int)nbb, nfields)
     if (m.alg1) {
       if (m.conv) ARDG_SPLIT_LAUNCH(true, true);
       else ARDG_SPLIT_LAUNCH(true, false);
@@ -474,11 +483,13 @@ hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flu
 #undef ARDG_SPLIT_LAUNCH
     return hipGetLastError();
   }
-  dim3 grid((unsigned)((E + 255) / 256), (unsigned)nfields);
+  dim3 grid((unsigned)((E + 255) / 256 * nfields));
   if (m.alg1)
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, true, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux);
+    hipLaunchKernelGGL((edge_flux_kernel<N, T, true, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux,
+                       nfields);
   else
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, false, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux);
+    hipLaunchKernelGGL((edge_flux_kernel<N, T, false, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux,
+                       nfields);
   return hipGetLastError();
 }
 
@@ -491,13 +502,13 @@ hipError_t edge_launch_t(const DevMesh& m, bool bern, int nfields, const void* u
 template <int N, typename T>
 hipError_t elem_launch_t(const DevMesh& m, int nfields, const void* vin, const void* flux,
                          const Epilogue& epi, hipStream_t st) {
-  dim3 grid((unsigned)((m.K + kElemBlock - 1) / kElemBlock), (unsigned)nfields);
+  dim3 grid((unsigned)((m.K + kElemBlock - 1) / kElemBlock * nfields));
   if (m.conv)
     hipLaunchKernelGGL((element_kernel<N, T, true>), grid, dim3(kElemBlock), 0, st, m,
-                       (const T*)vin, (const T*)flux, epi);
+                       (const T*)vin, (const T*)flux, epi, nfields);
   else
     hipLaunchKernelGGL((element_kernel<N, T, false>), grid, dim3(kElemBlock), 0, st, m,
-                       (const T*)vin, (const T*)flux, epi);
+                       (const T*)vin, (const T*)flux, epi, nfields);
   return hipGetLastError();
 }
 

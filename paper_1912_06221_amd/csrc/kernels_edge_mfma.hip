@@ -214,7 +214,7 @@ template <int N, typename P, bool ALG1, bool CONV>
 __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
                                                               const typename Mma<P>::T* __restrict__ u,
                                                               typename Mma<P>::T* __restrict__ flux,
-                                                              int nb_bdy) {
+                                                              int nb_bdy, int nf) {
   using T = typename Mma<P>::T;
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
@@ -222,18 +222,22 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
   __shared__ T fl[kEdgeTile * Nfp];
   __shared__ int rot[2 * Np];
   const int l = threadIdx.x;
-  const int field = blockIdx.y;
   const int64_t E = m.E_int + m.E_bdy;
-  const int b = blockIdx.x;
-  if (b < nb_bdy) {
+  const int64_t b = blockIdx.x;
+  const int64_t nbt = (int64_t)nb_bdy * nf;
+  if (b < nbt) {
     // boundary faces: mirror-ghost operator on the vector unit, one lane per
     // face, in the first blocks so that their long serial chain runs beside
     // the interior tiles
-    const int64_t e = m.E_int + (int64_t)b * kEdgeTile + l;
+    const int field = (int)(b % nf);
+    const int64_t e = m.E_int + (b / nf) * kEdgeTile + l;
     if (e < E) boundary_body<N, T, ALG1, false>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
-  const int64_t e0 = xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kEdgeTile;   // nb_bdy % 8 == 0
+  int64_t tile;
+  int field;
+  tile_and_field(b - nbt, (int64_t)gridDim.x - nbt, nf, tile, field);   // nbt % 8 == 0
+  const int64_t e0 = tile * kEdgeTile;
   const int nval = (int)((m.E_int - e0) < kEdgeTile ? (m.E_int - e0) : kEdgeTile);
   // rotated lattice node -> element node for faces 0 and 2 (face 1: identity)
   for (int n = l; n < Np; n += kEdgeTile) {
@@ -292,7 +296,7 @@ template <int N, typename P, bool ALG1, bool CONV>
 __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
                                                                    const typename Mma<P>::T* __restrict__ u,
                                                                    typename Mma<P>::T* __restrict__ flux,
-                                                                   int nb_bdy) {
+                                                                   int nb_bdy, int nf) {
   using M = Mma<P>;
   using T = typename M::T;
   typedef typename M::acc acc_t;
@@ -304,16 +308,20 @@ __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
   constexpr int KC = (Np + KS - 1) / KS;
   __shared__ T cbuf[2][Np * kEdgeTile];   // per wave: [coefficient][edge]; wave 1's rows then hold the flux shares
   __shared__ int rot[2 * Np];
-  const int field = blockIdx.y;
   const int64_t E = m.E_int + m.E_bdy;
-  const int b = blockIdx.x;
-  if (b < nb_bdy) {
+  const int64_t b = blockIdx.x;
+  const int64_t nbt = (int64_t)nb_bdy * nf;
+  if (b < nbt) {
     // boundary faces first (mirror-ghost operator, one lane per face)
-    const int64_t e = m.E_int + (int64_t)b * (2 * kEdgeTile) + threadIdx.x;
+    const int field = (int)(b % nf);
+    const int64_t e = m.E_int + (b / nf) * (2 * kEdgeTile) + threadIdx.x;
     if (e < E) boundary_body<N, T, ALG1, false>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
-  const int64_t e0 = xcd_block(b - nb_bdy, (int64_t)gridDim.x - nb_bdy) * kEdgeTile;   // nb_bdy % 8 == 0
+  int64_t tile;
+  int field;
+  tile_and_field(b - nbt, (int64_t)gridDim.x - nbt, nf, tile, field);   // nbt % 8 == 0
+  const int64_t e0 = tile * kEdgeTile;
   // rotated lattice node -> element node for faces 0 and 2 (face 1: identity)
   for (int n = threadIdx.x; n < Np; n += 2 * kEdgeTile) {
     int j = 0;
@@ -455,12 +463,12 @@ hipError_t edge_smfma_t(const DevMesh& m, int nfields, const void* u, void* flux
   if (m.E_int + m.E_bdy == 0) return hipSuccess;
   const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
   const int64_t nbb = ((m.E_bdy + 2 * kEdgeTile - 1) / (2 * kEdgeTile) + 7) / 8 * 8;
-  dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
+  dim3 grid((unsigned)((nbi + nbb) * nfields));
   const T* uu = (const T*)u;
   T* ff = (T*)flux;
   const int nbd = (int)nbb;
 #define ARDG_SMFMA(A, C) \
-  hipLaunchKernelGGL((edge_smfma_kernel<N, P, A, C>), grid, dim3(2 * kEdgeTile), 0, st, m, uu, ff, nbd)
+  hipLaunchKernelGGL((edge_smfma_kernel<N, P, A, C>), grid, dim3(2 * kEdgeTile), 0, st, m, uu, ff, nbd, nfields)
   if (m.alg1) {
     if (m.conv) ARDG_SMFMA(true, true);
     else ARDG_SMFMA(true, false);
@@ -501,20 +509,20 @@ hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux,
   const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
   const int64_t nbb = ((m.E_bdy + kEdgeTile - 1) / kEdgeTile + 7) / 8 * 8;
   if (m.E_int + m.E_bdy == 0) return hipSuccess;
-  dim3 grid((unsigned)(nbi + nbb), (unsigned)nfields);
+  dim3 grid((unsigned)((nbi + nbb) * nfields));
   const T* uu = (const T*)u;
   T* ff = (T*)flux;
   const int nbd = (int)nbb;
   if (m.alg1) {
     if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
     else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
   } else {
     if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
     else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd);
+      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
   }
   return hipGetLastError();
 }

@@ -439,10 +439,12 @@ template <int N, typename P, bool CONV, bool BERN>
 __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
                                                                     const typename Mma<P>::T* __restrict__ vin,
                                                                     const typename Mma<P>::T* __restrict__ flux,
-                                                                    Epilogue epi) {
+                                                                    Epilogue epi, int nf) {
   __shared__ ElemShared<N, P, CONV, BERN> S;
-  const int64_t k0 = xcd_block(blockIdx.x, gridDim.x) * kMfmaTile;
-  element_mfma_tile<N, P, CONV, BERN>(m, k0, blockIdx.y, vin, flux, epi, S);
+  int64_t tile;
+  int field;
+  tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
+  element_mfma_tile<N, P, CONV, BERN>(m, tile * kMfmaTile, field, vin, flux, epi, S);
 }
 
 // Batched form: persistent blocks over (problem, 64-element tile) items of
@@ -495,13 +497,13 @@ template <int N, typename P, bool BERN>
 hipError_t elem_mfma_t(const DevMesh& m, int nfields, const void* vin, const void* flux,
                        const Epilogue& epi, hipStream_t st) {
   using T = typename Mma<P>::T;
-  dim3 grid((unsigned)((m.K + kMfmaTile - 1) / kMfmaTile), (unsigned)nfields);
+  dim3 grid((unsigned)((m.K + kMfmaTile - 1) / kMfmaTile * nfields));
   if (m.conv)
     hipLaunchKernelGGL((element_mfma_kernel<N, P, true, BERN>), grid, dim3(kMfmaThreads), 0, st, m,
-                       (const T*)vin, (const T*)flux, epi);
+                       (const T*)vin, (const T*)flux, epi, nfields);
   else
     hipLaunchKernelGGL((element_mfma_kernel<N, P, false, BERN>), grid, dim3(kMfmaThreads), 0, st, m,
-                       (const T*)vin, (const T*)flux, epi);
+                       (const T*)vin, (const T*)flux, epi, nfields);
   return hipGetLastError();
 }
 
