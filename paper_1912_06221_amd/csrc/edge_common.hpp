@@ -16,15 +16,14 @@ namespace ardg {
 // y_v = A x_v (v < NV) for the ROWS x COLS block of a constant row-major
 // operator with leading dimension LD.  The entries are wave-uniform scalar
 // loads feeding scalar-operand FMAs, walked in steps of RB rows x CC columns
-// (RB*CC <= 12 entries): the RB rows' accumulators are
+// (RB*CC <= E entries): the RB rows' accumulators are
 // independent, so consecutive FMAs do not wait on each other, and the loads
 // of the next step are issued before the FMAs of the current one, so their
 // latency is covered by arithmetic.  The fence between steps keeps at most
 // two steps of entries in SGPRs (without it the whole operator is hoisted
 // into SGPRs and spilled).  With NV = 2 every loaded entry feeds two vectors.
-template <int ROWS, int COLS, int LD, int NV, typename T, typename XA, typename YA, int RBX = 4>
+template <int ROWS, int COLS, int LD, int NV, typename T, typename XA, typename YA, int RBX = 4, int E = 12>
 __device__ inline void matvec_blk(cptr<T> A0, XA x, YA y) {
-  constexpr int E = 12;
   constexpr int RB = ROWS < RBX ? ROWS : RBX;
   constexpr int CC = E / RB;
   constexpr int NRB = (ROWS + RB - 1) / RB;
@@ -86,9 +85,9 @@ struct OneVec {
   __device__ P operator[](int) const { return p; }
 };
 
-template <int ROWS, int COLS, typename T, int RBX = 4>
+template <int ROWS, int COLS, typename T, int RBX = 4, int E = 12>
 __device__ inline void matvec_pf(cptr<T> A0, const T* x, T* y) {
-  matvec_blk<ROWS, COLS, COLS, 1, T, OneVec<const T*>, OneVec<T*>, RBX>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
+  matvec_blk<ROWS, COLS, COLS, 1, T, OneVec<const T*>, OneVec<T*>, RBX, E>(A0, OneVec<const T*>{x}, OneVec<T*>{y});
 }
 
 // column slice of a wider row-major operator (leading dimension LD)

@@ -65,6 +65,7 @@ CASES = [
     (8, 0.2, 6, "element", None, 1),
     (12, 0.2, 3, "const", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0), 3),
     (10, 0.2, 2, "const", (0.6, -0.4, 0.2, -1.0, 1.0, 0.1), 2),
+    (10, 0.2, 4, "const", (0.3, -0.2, 0.0, -1.0, 1.0, 0.0), 2),
 ]
 
 
