@@ -184,14 +184,16 @@ ardg_status ardg_rk_workspace_bytes(ardg_mesh mesh, int32_t scheme, int32_t prec
  * The state update is FP64 in every precision; in ARDG_FP32 the operators act
  * on an FP32 copy of each stage's input.  work_dev: caller-owned device memory
  * of ardg_rk_workspace_bytes bytes, 256-byte aligned.  The step loop is
- * captured once per (scheme, precision, nfields, buffers, nsteps, dt) into a
- * HIP graph and replayed.  Errors: E_INVALID_ARG, E_UNSUPPORTED, E_HIP. */
+ * captured once per (scheme, precision, nfields, buffers, step count, dt)
+ * into HIP graphs of at most 256 steps, replayed as often as nsteps needs
+ * (plus one graph for the remainder).  Errors: E_INVALID_ARG, E_UNSUPPORTED,
+ * E_HIP. */
 ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
                          double* u_dev, void* work_dev, double t0, double dt, int32_t nsteps,
                          void* hip_stream);
 
-/* Capture and instantiate the graph that ardg_rk_step replays for exactly
- * these arguments (nsteps >= 1) without running it, so that a caller can
+/* Capture and instantiate the graphs that ardg_rk_step replays for exactly
+ * these arguments (nsteps >= 1) without running them, so that a caller can
  * keep the capture cost out of a latency-critical or timed region.  Nothing
  * is enqueued.  Errors as ardg_rk_step. */
 ardg_status ardg_rk_prepare(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,

@@ -158,11 +158,18 @@ struct ardg_mesh_s {
     }
   }
   void drop_graphs() {
+    // earlier launches of these graphs may still run
+    (void)hipDeviceSynchronize();
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
     ++version;
   }
 };
+
+// Steps per captured graph: a longer run replays the graph of kGraphSteps
+// steps (and one graph for the remainder), so that a graph stays a few
+// thousand nodes whatever the step count.
+constexpr int kGraphSteps = 256;
 
 extern "C" {
 
@@ -708,11 +715,34 @@ static ardg_status step_graph(ardg_mesh mesh, int scheme, int precision, int nfi
     hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
-    if (mesh->graphs.size() >= 8) mesh->drop_graphs();
+    if (mesh->graphs.size() >= 8) {
+      mesh->drop_graphs();
+      key.version = mesh->version;
+    }
     it = mesh->graphs.emplace(key, exec).first;
   }
   *out = it->second;
   return ARDG_OK;
+}
+
+// The graphs that run nsteps steps: *full of min(nsteps, kGraphSteps) steps,
+// replayed nsteps / that many times, and *rem (null if none) of the
+// remainder.  If capturing one of them evicted the cache, the other is
+// captured again (the cache then holds room for both).
+static ardg_status step_graphs(ardg_mesh mesh, int scheme, int precision, int nfields, double* u_dev,
+                               void* work_dev, double dt, int nsteps, hipGraphExec_t* full, hipGraphExec_t* rem) {
+  const int chunk = std::min<int>(nsteps, kGraphSteps);
+  const int nrem = nsteps % chunk;
+  *rem = nullptr;
+  ardg_status s = ARDG_OK;
+  if (nrem) {
+    s = step_graph(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nrem, rem);
+    if (s != ARDG_OK) return s;
+  }
+  const uint64_t v0 = mesh->version;
+  s = step_graph(mesh, scheme, precision, nfields, u_dev, work_dev, dt, chunk, full);
+  if (s != ARDG_OK || !nrem || mesh->version == v0) return s;
+  return step_graph(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nrem, rem);
 }
 
 ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields, double* u_dev,
@@ -726,10 +756,13 @@ ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int3
   if (nsteps < 0 || !std::isfinite(dt)) return fail(ARDG_E_INVALID_ARG, "rk_step: bad nsteps or dt");
   if (nsteps == 0) return ARDG_OK;
   DeviceGuard g(mesh->device);
-  hipGraphExec_t exec = nullptr;
-  s = step_graph(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nsteps, &exec);
+  hipGraphExec_t ex_full = nullptr, ex_rem = nullptr;
+  s = step_graphs(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nsteps, &ex_full, &ex_rem);
   if (s != ARDG_OK) return s;
-  HIP_TRY(hipGraphLaunch(exec, (hipStream_t)hip_stream), "hipGraphLaunch");
+  const int chunk = std::min<int>(nsteps, kGraphSteps);
+  for (int i = 0; i < nsteps / chunk; ++i)
+    HIP_TRY(hipGraphLaunch(ex_full, (hipStream_t)hip_stream), "hipGraphLaunch");
+  if (ex_rem) HIP_TRY(hipGraphLaunch(ex_rem, (hipStream_t)hip_stream), "hipGraphLaunch");
   return ARDG_OK;
 }
 
@@ -742,8 +775,8 @@ ardg_status ardg_rk_prepare(ardg_mesh mesh, int32_t scheme, int32_t precision, i
   if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "rk_prepare: work_dev not 256-byte aligned");
   if (nsteps < 1 || !std::isfinite(dt)) return fail(ARDG_E_INVALID_ARG, "rk_prepare: bad nsteps or dt");
   DeviceGuard g(mesh->device);
-  hipGraphExec_t exec = nullptr;
-  return step_graph(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nsteps, &exec);
+  hipGraphExec_t ex_full = nullptr, ex_rem = nullptr;
+  return step_graphs(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nsteps, &ex_full, &ex_rem);
 }
 
 // One graph of `reps` stages of the step sequence (edge kernel + element
@@ -896,6 +929,8 @@ struct ardg_batch_s {
     if (dprobs) (void)hipFree(dprobs);
   }
   void drop_graphs() {
+    // earlier launches of these graphs may still run
+    (void)hipDeviceSynchronize();
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
     ++version;
@@ -1209,42 +1244,9 @@ ardg_status ardg_batch_tiles(ardg_batch batch, int32_t precision, int32_t N, int
   return fail(ARDG_E_INVALID_ARG, "batch_tiles: no mesh of that order in the batch");
 }
 
-ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision, double* const* u_devs,
-                            void* work_dev, const double* dt, int32_t nsteps, void* hip_stream) {
-  if (!batch || !u_devs || !work_dev || !dt) return fail(ARDG_E_INVALID_ARG, "batch_step: null argument");
-  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
-  if (precision != ARDG_FP64 && precision != ARDG_FP32)
-    return fail(ARDG_E_UNSUPPORTED, "batched stepping is built for FP64 and FP32");
-  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "batch_step: work_dev not 256-byte aligned");
-  if (nsteps < 0) return fail(ARDG_E_INVALID_ARG, "batch_step: nsteps < 0");
-  const size_t n = batch->meshes.size();
-  for (size_t i = 0; i < n; ++i)
-    if (!u_devs[i] || !std::isfinite(dt[i])) return fail(ARDG_E_INVALID_ARG, "batch_step: bad state pointer or dt");
-  if (nsteps == 0) return ARDG_OK;
-  DeviceGuard g(batch->device);
-  ardg_status s = tune(batch, precision);
-  if (s != ARDG_OK) return s;
-  std::vector<size_t> offs;
-  batch_layout(batch, precision, &offs, nullptr);
-  std::vector<BatchProb> hp(n);
-  char* w = (char*)work_dev;
-  for (size_t i = 0; i < n; ++i) {
-    hp[i].m = batch->meshes[i]->dm;
-    hp[i].u = u_devs[i];
-    hp[i].acc = (double*)(w + offs[3 * i]);
-    hp[i].v = w + offs[3 * i + 1];
-    hp[i].flux = w + offs[3 * i + 2];
-    hp[i].dt = dt[i];
-  }
-  if (batch->hprobs.size() != n ||
-      std::memcmp(batch->hprobs.data(), hp.data(), n * sizeof(BatchProb)) != 0) {
-    // earlier graph launches may still read the descriptors being replaced
-    HIP_TRY(hipDeviceSynchronize(), "batch_step: synchronise");
-    HIP_TRY(hipMemcpy(batch->dprobs, hp.data(), n * sizeof(BatchProb), hipMemcpyHostToDevice),
-            "batch_step: descriptor upload");
-    batch->hprobs = hp;
-    batch->drop_graphs();
-  }
+// The graph of nsteps steps of the whole batch (captured on first use).
+static ardg_status batch_graph(ardg_batch batch, int scheme, int precision, void* work_dev, int nsteps,
+                               hipGraphExec_t* out) {
   const int pi = precision == ARDG_FP64 ? 0 : 1;
   const bool f64 = precision == ARDG_FP64;
   GraphKey key{scheme, precision, 1, nsteps, nullptr, work_dev, 0.0, batch->version};
@@ -1281,10 +1283,71 @@ ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
     hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) return hip_fail(e3, "hipGraphInstantiate");
-    if (batch->graphs.size() >= 8) batch->drop_graphs();
+    if (batch->graphs.size() >= 8) {
+      batch->drop_graphs();
+      key.version = batch->version;
+    }
     it = batch->graphs.emplace(key, exec).first;
   }
-  HIP_TRY(hipGraphLaunch(it->second, (hipStream_t)hip_stream), "hipGraphLaunch");
+  *out = it->second;
+  return ARDG_OK;
+}
+
+ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision, double* const* u_devs,
+                            void* work_dev, const double* dt, int32_t nsteps, void* hip_stream) {
+  if (!batch || !u_devs || !work_dev || !dt) return fail(ARDG_E_INVALID_ARG, "batch_step: null argument");
+  if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
+  if (precision != ARDG_FP64 && precision != ARDG_FP32)
+    return fail(ARDG_E_UNSUPPORTED, "batched stepping is built for FP64 and FP32");
+  if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "batch_step: work_dev not 256-byte aligned");
+  if (nsteps < 0) return fail(ARDG_E_INVALID_ARG, "batch_step: nsteps < 0");
+  const size_t n = batch->meshes.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!u_devs[i] || !std::isfinite(dt[i])) return fail(ARDG_E_INVALID_ARG, "batch_step: bad state pointer or dt");
+  if (nsteps == 0) return ARDG_OK;
+  DeviceGuard g(batch->device);
+  ardg_status s = tune(batch, precision);
+  if (s != ARDG_OK) return s;
+  std::vector<size_t> offs;
+  batch_layout(batch, precision, &offs, nullptr);
+  std::vector<BatchProb> hp(n);
+  char* w = (char*)work_dev;
+  for (size_t i = 0; i < n; ++i) {
+    hp[i].m = batch->meshes[i]->dm;
+    hp[i].u = u_devs[i];
+    hp[i].acc = (double*)(w + offs[3 * i]);
+    hp[i].v = w + offs[3 * i + 1];
+    hp[i].flux = w + offs[3 * i + 2];
+    hp[i].dt = dt[i];
+  }
+  if (batch->hprobs.size() != n ||
+      std::memcmp(batch->hprobs.data(), hp.data(), n * sizeof(BatchProb)) != 0) {
+    // earlier graph launches may still read the descriptors being replaced
+    HIP_TRY(hipDeviceSynchronize(), "batch_step: synchronise");
+    HIP_TRY(hipMemcpy(batch->dprobs, hp.data(), n * sizeof(BatchProb), hipMemcpyHostToDevice),
+            "batch_step: descriptor upload");
+    batch->hprobs = hp;
+    batch->drop_graphs();
+  }
+  // the graph of min(nsteps, kGraphSteps) steps, replayed, and one of the
+  // remainder (captured again if capturing the first evicted it)
+  const int chunk = std::min<int>(nsteps, kGraphSteps);
+  const int nrem = nsteps % chunk;
+  hipGraphExec_t ex_full = nullptr, ex_rem = nullptr;
+  if (nrem) {
+    s = batch_graph(batch, scheme, precision, work_dev, nrem, &ex_rem);
+    if (s != ARDG_OK) return s;
+  }
+  const uint64_t v0 = batch->version;
+  s = batch_graph(batch, scheme, precision, work_dev, chunk, &ex_full);
+  if (s != ARDG_OK) return s;
+  if (nrem && batch->version != v0) {
+    s = batch_graph(batch, scheme, precision, work_dev, nrem, &ex_rem);
+    if (s != ARDG_OK) return s;
+  }
+  for (int i = 0; i < nsteps / chunk; ++i)
+    HIP_TRY(hipGraphLaunch(ex_full, (hipStream_t)hip_stream), "hipGraphLaunch");
+  if (ex_rem) HIP_TRY(hipGraphLaunch(ex_rem, (hipStream_t)hip_stream), "hipGraphLaunch");
   return ARDG_OK;
 }
 

@@ -192,6 +192,28 @@ def test_time_stepping_heat_8x8(scheme, prec, form, monkeypatch):
     assert l2 < 2e-3
 
 
+def test_long_run_equals_short_runs():
+    """A run longer than one captured graph (graphs of at most 256 steps,
+    replayed, plus a remainder graph) gives the same state as the same steps
+    taken in shorter calls."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    mesh = W.split_square_mesh(6, 0.2, seed=3)
+    N = 2
+    ops, lm = library_mesh(mesh, N, "const", 0.5, None, 1)
+    u0 = W.random_nodal((1, mesh.K, ops.Np), seed=4)
+    dt = 1e-5
+    a = to_dev(u0)
+    b = to_dev(u0)
+    work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, ardg.FP64, 1), a.device)
+    lm.rk_step(a, work, dt, 600, scheme=ardg.RK4, precision=ardg.FP64)
+    for _ in range(6):
+        lm.rk_step(b, work, dt, 100, scheme=ardg.RK4, precision=ardg.FP64)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert bool(torch.isfinite(a).all())
+
+
 def test_determinism():
     import torch
     from paper_1912_06221_amd import ardg
