@@ -229,8 +229,8 @@ def main():
                     help="run one device copy of 512 MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              f"(multi-GPU sharding is design-only)", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding the mesh over several GPUs is a design, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
