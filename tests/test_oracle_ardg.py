@@ -305,3 +305,56 @@ def test_boundary_flux_reproduces_odd_polynomials(N):
             assert np.abs(Fb[e] - ex).max() < 1e-10 * max(1.0, np.abs(ex).max())
             checked += 1
     assert checked == 3
+
+
+def _alg1_bruteforce_errors(N, D1v, D2v, mutate=None, seed=13):
+    """Largest relative difference between the oracle's Algorithm 1 flux and
+    the physical-domain brute force over every interior and boundary face of
+    a jittered mesh whose elements alternate between two coefficients."""
+    from physical_bruteforce import physical_edge_flux_alg1
+    mesh = W.split_square_mesh(3, 0.25, seed=seed)
+    K = mesh.K
+    D = np.where(np.arange(K) % 2 == 0, D1v, D2v).astype(float)
+    pr = Problem(mesh.vxy, mesh.etov, N, D, D_mode="element", build_edges=False)
+    ops, g = pr.ops, pr.geom
+    rng = np.random.default_rng(100 + N)
+    u = rng.standard_normal((K, ops.Np))
+    xy = pr.nodal_xy()
+    rs = nodes(N)
+    worst = 0.0
+    for (k1, f1, k2, f2) in g.interior:
+        eg = ardg.interior_edge_geometry(g, k1, f1, k2, f2)
+        Da, Db = D[k1], D[k2]
+        if mutate == "swap":
+            Da, Db = Db, Da
+        if mutate == "frame":
+            # side 2 differentiated with side 1's parallelogram factors
+            eg.Rx2, eg.Ry2, eg.Sx2, eg.Sy2 = eg.Rx, eg.Ry, eg.Sx, eg.Sy
+        W1, W2 = ardg.edge_operator_alg1(ops, eg, f1, f2, Da, Db)
+        F = W1 @ u[k1] + W2 @ u[k2]
+        Fb = physical_edge_flux_alg1(N, eg, rs, xy[k1], u[k1], xy[k2], u[k2], D[k1], D[k2])
+        worst = max(worst, np.abs(F - Fb).max() / max(np.abs(Fb).max(), 1e-300))
+    for (k1, f1) in g.boundary:
+        eg = ardg.boundary_edge_geometry(g, k1, f1)
+        F = ardg.boundary_edge_operator_alg1(ops, g, k1, f1, eg, D[k1]) @ u[k1]
+        Fb = physical_edge_flux_alg1(N, eg, rs, xy[k1], u[k1], None, None, D[k1], D[k1])
+        worst = max(worst, np.abs(F - Fb).max() / max(np.abs(Fb).max(), 1e-300))
+    return worst
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_flux_alg1_matches_physical_bruteforce_unequal_D(N):
+    """Algorithm 1 with D1 != D2 (contrast 1e4) equals the same five steps
+    carried out with physical monomials and physical quadrature: separation at
+    the sub-triangles' physical nodes, physical gradients times each
+    element's D, a second physical least-squares fit, n1 . (result) on the
+    diagonal.  Boundary faces use the mirror ghost with the element's D."""
+    assert _alg1_bruteforce_errors(N, 1e-2, 1e2) < 1e-9
+
+
+@pytest.mark.parametrize("mutate", ["swap", "frame"])
+def test_flux_alg1_bruteforce_detects_planted_mistakes(mutate):
+    """The pin above is not vacuous: exchanging D1 and D2, or differentiating
+    side 2 with side 1's parallelogram factors, moves the oracle's flux far
+    from the brute force."""
+    assert _alg1_bruteforce_errors(2, 1e-2, 1e2, mutate=mutate) > 1e-2
