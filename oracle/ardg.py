@@ -10,7 +10,9 @@ reconstruction on the parallelogram (subsection "Reconstruction", Algorithm
 aRDG) and the reconstructed gradient on the diagonal with the constant
 parallelogram factors (eq. lift_physicalDomain_ardg and the gradient formula
 after it).  Algorithm 1 (element-wise diffusion coefficients) is
-``edge_operator_alg1``.
+``edge_operator_alg1``; the alternative form with a reconstructed
+coefficient (eq. NDG_diffusion_once_matrixForm_reference_general_alternative,
+Algorithm nonconstDiff2) is ``edge_operator_alg2``.
 
 Readings of places the paper leaves open:
 
@@ -36,6 +38,14 @@ Readings of places the paper leaves open:
   factors; the second RDG takes the nodal products D_k grad(u~_k) already on
   the sub-triangles (so no second V_p) and the flux is n1 . (result on the
   diagonal).  At a boundary face the ghost carries the element's own D.
+* Algorithm 2 (the alternative form): D~ = RDG(D^1, D^2) is the same
+  least-squares reconstruction applied to the coefficient's nodal data of the
+  two elements (projected onto the sub-triangles like u), Grad(u~) is the
+  gradient of the reconstruction u~ on the parallelogram, and "Product" is
+  the pointwise product at the diagonal nodes, so the flux is
+  D~(d_j) n1 . grad u~(d_j).  At a boundary face the ghost's coefficient is
+  the element's own D at the mirrored points (a coefficient is reflected
+  evenly, the solution oddly).
 """
 from __future__ import annotations
 
@@ -406,3 +416,50 @@ def boundary_edge_operator_alg1(ops: RefOps, geom, k1, f1, eg: EdgeGeometry, D1:
     P1 = total_projection(ops, eg.pi1, f1)
     P2 = ops.Vinv @ _boundary_ghost_data_operator(ops, geom, k1, eg)
     return _alg1_from_subtriangle_modal(ops, eg, P1, P2, D1, D1)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 2: reconstructed coefficient times the reconstructed gradient
+# ----------------------------------------------------------------------------
+
+def coefficient_on_diagonal(ops: RefOps, eg: EdgeGeometry, f1: int, f2: int, D1n, D2n) -> np.ndarray:
+    """D~ = RDG(D^1, D^2) at the diagonal nodes d_j [Nfp], from the nodal
+    coefficient values D^k [Np] of the two elements (Algorithm nonconstDiff2:
+    the reconstruction of the coefficient, exactly as for u)."""
+    N, Np = ops.N, ops.Np
+    P1 = total_projection(ops, eg.pi1, f1)
+    P2 = total_projection(ops, eg.pi2, f2)
+    R = recon_pinv(N)
+    c = R[:, :Np] @ (P1 @ np.asarray(D1n, dtype=np.float64)) + R[:, Np:] @ (P2 @ np.asarray(D2n, dtype=np.float64))
+    E0, _, _ = diagonal_eval(N)
+    return E0 @ c
+
+
+def edge_operator_alg2(ops: RefOps, eg: EdgeGeometry, f1: int, f2: int, D1: float, D2: float):
+    """Algorithm 2 for element-wise constant D: the flux D~(d_j) n1 . grad u~(d_j).
+    Returns (W1, W2), [Nfp, Np] each; the flux includes D~."""
+    W1, W2 = edge_operator(ops, eg, f1, f2)
+    one = np.ones(ops.Np)
+    Dt = coefficient_on_diagonal(ops, eg, f1, f2, D1 * one, D2 * one)
+    return Dt[:, None] * W1, Dt[:, None] * W2
+
+
+def boundary_coefficient_on_diagonal(ops: RefOps, eg: EdgeGeometry, f1: int, D1n) -> np.ndarray:
+    """D~ at the diagonal nodes of a boundary face: side 1 projected as usual,
+    the mirror ghost's coefficient on Omega'_2 is the element's D at the
+    mirrored points (constant D: the constant itself)."""
+    N, Np = ops.N, ops.Np
+    D1n = np.asarray(D1n, dtype=np.float64)
+    if np.ptp(D1n) != 0.0:
+        raise ValueError("boundary coefficient: only element-wise constant D")
+    P1 = total_projection(ops, eg.pi1, f1)
+    R = recon_pinv(N)
+    c = R[:, :Np] @ (P1 @ D1n) + R[:, Np:] @ (ops.Vinv @ D1n)
+    E0, _, _ = diagonal_eval(N)
+    return E0 @ c
+
+
+def boundary_edge_operator_alg2(ops: RefOps, geom, k1, f1, eg: EdgeGeometry, D1: float):
+    W = boundary_edge_operator(ops, geom, k1, f1, eg)
+    Dt = boundary_coefficient_on_diagonal(ops, eg, f1, D1 * np.ones(ops.Np))
+    return Dt[:, None] * W

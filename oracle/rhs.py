@@ -11,7 +11,9 @@ TEST INFRASTRUCTURE ONLY.
   1D mass matrix on [-1, 1] (reading of "ratio between the lengths").  The
   element's own geometric factors are kept in the volume term (eq. for S^k).
   With an element-wise D the volume term carries D_k and the flux comes from
-  Algorithm 1 (eq. NDG_diffusion_once_matrixForm_reference_general).
+  Algorithm 1 (eq. NDG_diffusion_once_matrixForm_reference_general) or, with
+  alg=2, from Algorithm 2 (eq.
+  NDG_diffusion_once_matrixForm_reference_general_alternative).
 * Convection (the v.grad part of eq. convection_diffusion): nodal collocation
   of v u, weak form, upwind numerical flux f* = max(n.v,0) u- + min(n.v,0) u+,
   with u+ = 0 outside the domain.  The velocity is affine, v(x) = v0 + W x.
@@ -33,16 +35,20 @@ class Problem:
     """A mesh, an order N, diffusion coefficients and an optional velocity.
 
     D_mode: "const" (D is a float, or a list with one value per field) or
-    "element" (D is an array [K], Algorithm 1).
+    "element" (D is an array [K]; flux by Algorithm 1, or Algorithm 2 when
+    alg=2).
     """
 
     def __init__(self, vxy, etov, N: int, D, D_mode: str = "const",
-                 velocity=None, nfields: int = 1, build_edges: bool = True):
+                 velocity=None, nfields: int = 1, build_edges: bool = True, alg: int = 1):
         self.geom = Geometry(vxy, etov)
         self.ops = RefOps(N)
         self.N = N
         self.nfields = nfields
         self.D_mode = D_mode
+        if alg not in (1, 2):
+            raise ValueError("alg must be 1 or 2")
+        self.alg = alg
         if D_mode == "const":
             Dv = np.atleast_1d(np.asarray(D, dtype=np.float64))
             if Dv.size == 1:
@@ -69,7 +75,7 @@ class Problem:
             eg = ardg.interior_edge_geometry(g, k1, f1, k2, f2)
             self.edge_geom.append(eg)
             if self.D_mode == "element":
-                W1, W2 = ardg.edge_operator_alg1(ops, eg, f1, f2, self.Delem[k1], self.Delem[k2])
+                W1, W2 = self._element_edge_operator(eg, f1, f2, k1, k2)
             else:
                 W1, W2 = ardg.edge_operator(ops, eg, f1, f2)
             E1.append(W1)
@@ -82,10 +88,18 @@ class Problem:
             eg = ardg.boundary_edge_geometry(g, k1, f1)
             self.bdy_geom.append(eg)
             if self.D_mode == "element":
-                B.append(ardg.boundary_edge_operator_alg1(ops, g, k1, f1, eg, self.Delem[k1]))
+                B.append(self._element_boundary_operator(k1, f1, eg))
             else:
                 B.append(ardg.boundary_edge_operator(ops, g, k1, f1, eg))
         self.WB = np.array(B).reshape(-1, ops.Nfp, ops.Np)
+
+    def _element_edge_operator(self, eg, f1, f2, k1, k2):
+        alg = ardg.edge_operator_alg2 if self.alg == 2 else ardg.edge_operator_alg1
+        return alg(self.ops, eg, f1, f2, self.Delem[k1], self.Delem[k2])
+
+    def _element_boundary_operator(self, k1, f1, eg):
+        alg = ardg.boundary_edge_operator_alg2 if self.alg == 2 else ardg.boundary_edge_operator_alg1
+        return alg(self.ops, self.geom, k1, f1, eg, self.Delem[k1])
 
     # -- fluxes -----------------------------------------------------------------
     def diffusive_flux(self, u: np.ndarray, field: int = 0):
@@ -199,8 +213,7 @@ class Problem:
         if k2 < 0:
             eg = ardg.boundary_edge_geometry(g, k, f)
             if self.D_mode == "element":
-                W = ardg.boundary_edge_operator_alg1(ops, g, k, f, eg, self.Delem[k])
-                F = W @ u[k]
+                F = self._element_boundary_operator(k, f, eg) @ u[k]
             else:
                 F = self.Dfield[field] * (ardg.boundary_edge_operator(ops, g, k, f, eg) @ u[k])
             return F
@@ -208,7 +221,7 @@ class Problem:
         k1, fa, kb, fb = (k, f, k2, f2) if k < k2 else (k2, f2, k, f)
         eg = ardg.interior_edge_geometry(g, k1, fa, kb, fb)
         if self.D_mode == "element":
-            W1, W2 = ardg.edge_operator_alg1(ops, eg, fa, fb, self.Delem[k1], self.Delem[kb])
+            W1, W2 = self._element_edge_operator(eg, fa, fb, k1, kb)
             F = W1 @ u[k1] + W2 @ u[kb]
         else:
             W1, W2 = ardg.edge_operator(ops, eg, fa, fb)

@@ -358,3 +358,87 @@ def test_flux_alg1_bruteforce_detects_planted_mistakes(mutate):
     side 2 with side 1's parallelogram factors, moves the oracle's flux far
     from the brute force."""
     assert _alg1_bruteforce_errors(2, 1e-2, 1e2, mutate=mutate) > 1e-2
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 2: reconstructed coefficient times the reconstructed gradient
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 6])
+def test_alg2_coefficient_is_arithmetic_mean_on_diagonal(N):
+    """For element-wise constant D the reconstructed coefficient on the
+    diagonal is (D1 + D2) / 2 at every node.  Closed form: the map
+    (R, S) -> (-S, -R) swaps the two sub-triangles, fixes every diagonal point
+    and leaves Q_N and the least-squares system invariant, so the fit of the
+    odd part (D1 - D2)/2 * (indicator of side 1 - indicator of side 2) is odd
+    under it and vanishes on the diagonal; the even part (D1 + D2)/2 is a
+    constant, reproduced exactly."""
+    mesh = W.split_square_mesh(4, 0.25, seed=17)
+    g = Geometry(mesh.vxy, mesh.etov)
+    ops = RefOps(N)
+    one = np.ones(ops.Np)
+    for (k1, f1, k2, f2) in g.interior:
+        eg = ardg.interior_edge_geometry(g, k1, f1, k2, f2)
+        Dt = ardg.coefficient_on_diagonal(ops, eg, f1, f2, 1e-2 * one, 1e2 * one)
+        assert np.abs(Dt - 0.5 * (1e-2 + 1e2)).max() < 1e-11 * 1e2
+    for (k1, f1) in g.boundary:
+        eg = ardg.boundary_edge_geometry(g, k1, f1)
+        Dt = ardg.boundary_coefficient_on_diagonal(ops, eg, f1, 3.0 * one)
+        assert np.abs(Dt - 3.0).max() < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_alg2_matches_physical_bruteforce(N):
+    """Algorithm 2 assembled in physical coordinates: the coefficient fitted by
+    physical least squares on the parallelogram (data D1 on (P1, A, B), D2 on
+    (P2, B, A)) times n1 . grad u~ of the physical fit, at the diagonal's LGL
+    points; boundary faces with the mirror ghost carrying the element's D."""
+    from physical_bruteforce import ParallelogramLS, physical_edge_flux
+    mesh = W.split_square_mesh(3, 0.25, seed=19)
+    K = mesh.K
+    D = np.where(np.arange(K) % 2 == 0, 1e-2, 1e2)
+    pr = Problem(mesh.vxy, mesh.etov, N, D, D_mode="element", alg=2)
+    rng = np.random.default_rng(200 + N)
+    u = rng.standard_normal((K, pr.ops.Np))
+    Fi, Fb = pr.diffusive_flux(u)
+    xy = pr.nodal_xy()
+    for e, (k1, f1, k2, f2) in enumerate(pr.int_edges):
+        eg = pr.edge_geom[e]
+        ls = ParallelogramLS(N, eg)
+        cD = ls.fit(lambda X: np.full(len(X), D[k1]), lambda X: np.full(len(X), D[k2]))
+        Dt = ls.value(cD, ls.diagonal())
+        Fbf = Dt * physical_edge_flux(N, eg, xy[k1], u[k1], None, xy[k2], u[k2], None)
+        assert np.abs(Fbf - Fi[e]).max() < 1e-9 * max(1.0, np.abs(Fi[e]).max())
+    for e, (k1, f1) in enumerate(pr.bdy_edges):
+        eg = pr.bdy_geom[e]
+        Fbf = D[k1] * physical_edge_flux(N, eg, xy[k1], u[k1], None, None, None, None)
+        assert np.abs(Fbf - Fb[e]).max() < 1e-9 * max(1.0, np.abs(Fb[e]).max())
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_alg2_equal_D_reduces_to_constant_form(N):
+    """D1 = D2 = D: Algorithm 2 is D times the constant-coefficient flux."""
+    mesh = W.split_square_mesh(4, 0.2, seed=23)
+    pc = Problem(mesh.vxy, mesh.etov, N, 2.5)
+    p2 = Problem(mesh.vxy, mesh.etov, N, np.full(mesh.K, 2.5), D_mode="element", alg=2)
+    u = np.random.default_rng(N).standard_normal((mesh.K, pc.ops.Np))
+    assert np.abs(p2.rhs(u) - pc.rhs(u)).max() < 1e-12 * np.abs(pc.rhs(u)).max()
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_alg2_swap_symmetry(N):
+    """Exchanging the sides gives the negated flux in reverse order."""
+    mesh = W.split_square_mesh(3, 0.2, seed=29)
+    g = Geometry(mesh.vxy, mesh.etov)
+    ops = RefOps(N)
+    rng = np.random.default_rng(N)
+    D = rng.uniform(0.1, 10.0, g.K)
+    u = rng.standard_normal((g.K, ops.Np))
+    for (k1, f1, k2, f2) in g.interior:
+        e12 = ardg.interior_edge_geometry(g, k1, f1, k2, f2)
+        e21 = ardg.interior_edge_geometry(g, k2, f2, k1, f1)
+        a1, a2 = ardg.edge_operator_alg2(ops, e12, f1, f2, D[k1], D[k2])
+        b1, b2 = ardg.edge_operator_alg2(ops, e21, f2, f1, D[k2], D[k1])
+        F12 = a1 @ u[k1] + a2 @ u[k2]
+        F21 = b1 @ u[k2] + b2 @ u[k1]
+        assert np.abs(F12 + F21[::-1]).max() < 1e-10 * max(1.0, np.abs(F12).max())

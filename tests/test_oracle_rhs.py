@@ -86,14 +86,14 @@ def test_weak_equals_strong_form(N):
 
 
 @pytest.mark.parametrize("N", [2, 3, 4])
-@pytest.mark.parametrize("alg1", [False, True])
-def test_conservation(N, alg1):
+@pytest.mark.parametrize("alg", [0, 1, 2])
+def test_conservation(N, alg):
     """sum_k J_k 1^T M rhs_k equals the integral of the boundary fluxes:
-    interior edges cancel pairwise."""
+    interior edges cancel pairwise (constant D, Algorithm 1, Algorithm 2)."""
     mesh = W.split_square_mesh(4, 0.2, seed=4)
     rng = np.random.default_rng(N)
-    D = rng.uniform(0.1, 2.0, mesh.K) if alg1 else 1.3
-    pr = Problem(mesh.vxy, mesh.etov, N, D, D_mode="element" if alg1 else "const")
+    D = rng.uniform(0.1, 2.0, mesh.K) if alg else 1.3
+    pr = Problem(mesh.vxy, mesh.etov, N, D, D_mode="element" if alg else "const", alg=max(alg, 1))
     ops, g = pr.ops, pr.geom
     u = rng.standard_normal((g.K, ops.Np))
     r = pr.rhs(u)

@@ -29,14 +29,17 @@ def _cases():
         ("const", [1e-3, 0.5], ROT, 2),
         ("element", "loguniform", None, 1),
         ("element", "loguniform", ROT_SHIFT, 1),
+        ("element2", "loguniform", None, 1),
     ]
 
 
 def _problem(N, mode, D, vel, nf, m=4, seed=41):
     mesh = W.split_square_mesh(m, 0.2, seed=seed)
-    if mode == "element":
+    alg = 2 if mode == "element2" else 1
+    if mode.startswith("element"):
+        mode = "element"
         D = W.loguniform_per_element(mesh.K, 1e-3, 1e1, seed=seed + 1)
-    return mesh, Problem(mesh.vxy, mesh.etov, N, D, D_mode=mode, velocity=vel, nfields=nf)
+    return mesh, Problem(mesh.vxy, mesh.etov, N, D, D_mode=mode, velocity=vel, nfields=nf, alg=alg)
 
 
 def _sample(pr):
@@ -47,7 +50,7 @@ def _sample(pr):
 
 
 @pytest.mark.parametrize("N", [2, 3])
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(5))
 def test_rhs_elements_equals_assembled_rhs(N, case):
     mode, D, vel, nf = _cases()[case]
     mesh, pr = _problem(N, mode, D, vel, nf)
@@ -61,7 +64,7 @@ def test_rhs_elements_equals_assembled_rhs(N, case):
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(full[f]).max()
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(5))
 def test_rk4_step_elements_equals_full_step(case):
     N = 2
     mode, D, vel, nf = _cases()[case]
