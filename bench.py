@@ -1,21 +1,29 @@
 """Benchmark: DOF x RK-stage per second of the aRDG right-hand side on one MI355X.
 
-Workload (default): unit square 256 x 256 x 2 = 131072 triangles, interior
-vertices jittered by +-0.2 h (seeded), N = 4 (Np = 15), element-wise D with
-contrast 1e4 (1e-2 outside, 1e2 inside a circle of radius 0.25; Algorithm 1
-flux), initial data a seeded sum of 16 Fourier modes, classic RK4.  The FP64
-path is the headline value; the mixed modes (FP32 operators and arithmetic,
-and split-BF16 products on the matrix cores with FP32 accumulation, both with
-the FP64 RK state) are reported beside it with their L2 difference to the
-FP64 path.
+Headline workload: 4 independent scalar fields on the unit square cut into
+708 x 708 cells of two triangles (1,002,528 elements, interior vertices
+jittered by +-0.2 h, seeded), N = 3 (Np = 10), rotating velocity v = (-y, x)
+with upwind convective flux, per-field constant D in {1e-4, 1e-3, 1e-2, 1},
+initial data a seeded sum of 16 Fourier modes per field, classic RK4.  The
+FP64 path is `value`; the reduced-precision modes (FP32 operators and
+arithmetic, and split-BF16 products on the matrix cores with FP32
+accumulation, both with the FP64 RK state) are reported beside it with their
+L2 error after the workload's 200 steps.
 
 One bench step = one RK4 time step = 4 passes of the whole hot path (edge
 reconstruction kernel + element kernel with the fused RK update).  Inputs are
-resident in HBM before timing starts; the K timed steps are one HIP graph,
-captured before the timed region and launched once inside it.
+resident in HBM before timing starts; the K timed steps are HIP graphs
+captured before the timed region and launched inside it.
 
-`cpu_baseline` times the FP64 NumPy oracle (test infrastructure) on a bounded
-sample: one RHS stage on the first S elements of the same workload.
+Extra keys: the 256 x 256 x 2, N = 4 workload with element-wise D (contrast
+1e4, Algorithm 1 flux), the 512 x 512 x 2, N = 6 workload with log-uniform D
+(the precision workload: every mode's L2 error after 50 steps), and the 512
+independent problems advanced as one batch.
+
+`cpu_baseline` times the FP64 NumPy oracle (test infrastructure): its
+assembled right-hand side with the per-edge operators prebuilt, on strips of
+the headline mesh, one strip per worker process on the host's cores, before
+the GPU is used.
 """
 from __future__ import annotations
 
@@ -34,7 +42,9 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+HEADLINE = "convdiff_708x708_N3_4f"
+ROTATION = (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)
 
 
 def log(msg):
@@ -56,32 +66,30 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary of
-    this workload (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel
-    calibration), or None when there is none or the kernels changed since."""
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+def stored_counters(workload):
+    """Per-launch counter values of the committed profile summary of this
+    workload (`profiles/counters_<workload>.md`: lines `name: value`), or {}
+    when there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.md")
     if not os.path.exists(path):
-        return None
-    src, val = None, None
+        return {}
+    src, vals = None, {}
     with open(path) as fh:
         for line in fh:
             line = line.strip().strip("`")
             if line.startswith("kernel-source-sha256:"):
                 src = line.split(":", 1)[1].strip()
-            elif line.startswith(f"traffic-bytes-per-launch {kernel}:"):
-                val = float(line.split(":", 1)[1])
-    if src is None or val is None or src != kernel_source_hash():
-        return None
-    return val
+            elif line.startswith("per-launch "):
+                k, v = line[len("per-launch "):].split(":", 1)
+                vals[k.strip()] = float(v)
+    if src != kernel_source_hash():
+        return {}
+    return vals
 
 
-def build_workload(name):
-    spec = W.WORKLOADS[name]
-    cfg = spec["config"]
-    mesh = W.split_square_mesh(spec["m"], spec["jitter"], seed=W.seed_for(cfg, "mesh"))
-    return spec, mesh
-
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
 
 def nodal_xy(mesh, rs):
     v = mesh.vxy[mesh.etov]
@@ -91,45 +99,231 @@ def nodal_xy(mesh, rs):
     return x, y
 
 
-def algorithmic_bytes(K, Np, Nfp, E_int, E_bdy, s, alg1, nfields=1):
-    """Bytes each kernel must move per launch (each value counted once).
+def workload_D(spec, mesh):
+    """(D values, "element" | "const") of a named workload."""
+    cfg = spec["config"]
+    if spec["D"] == "circle":
+        return W.circle_contrast_D(mesh), "element"
+    if spec["D"] == "loguniform":
+        return W.loguniform_per_element(mesh.K, spec["Dlo"], spec["Dhi"], W.seed_for(cfg, "D")), "element"
+    return np.array(spec.get("Dfield", [spec.get("Dval", 1.0)]), dtype=float), "const"
 
-    edge kernel:    state read F*K*Np*s, edge table 56 B per interior edge
-                    (int2 elements+faces, 3 x double2: apex weights of both
-                    sides, gamma_R/gamma_S), 36 B per boundary face, D per
-                    element (Algorithm 1) 8K, flux write F*E*Nfp*s.
-    element kernel: RK4 stage averaged over the 4 stages: stage input read
-                    F*K*Np*s, flux read F*E*Nfp*s, vertices 48K, face map
-                    12K, D 8K, FP64 state/accumulator traffic 34 B per DOF on
-                    average (stage 0: u, acc w, v w; 1-2: v, u, acc r/w, v w;
-                    3: v, u r/w, acc r) with the FP64 v counted in the 34 B
-                    when s = 8, and 26 + 4*... per DOF otherwise.
-    """
-    E = E_int + E_bdy
+
+def algorithmic_bytes(K, Np, Nfp, E_int, s, alg1, nfields):
+    """Bytes each kernel must move per launch, each value counted once:
+    edge    F K Np s (state) + 60 E_int (edge table) + 8 K (element D,
+            Algorithm 1) + F E_int Nfp s (flux write);
+    element F K Np s (stage input) + F E_int Nfp s (flux) + 48 K (affine map)
+            + F K Np (8 + 16) (u^n read, accumulator read and write, FP64)
+            + F K Np s (next stage input)."""
     dof = nfields * K * Np
-    edge = dof * s + 56 * E_int + 36 * E_bdy + (8 * K if alg1 else 0) + nfields * E * Nfp * s
-    if s == 8:
-        state = 34.0 * dof          # includes the FP64 stage vector
-        vin = 0.0
-    else:
-        # FP32: v read (4), u read 8 (stages 0-2) / r+w 16 (stage 3), acc as FP64,
-        # v write 4 (all stages)
-        state = (8 + 16 + 16 + 8) / 4.0 * dof + (8 * 3 + 16) / 4.0 * dof + 4.0 * dof
-        vin = 4.0 * dof
-    elem = vin + state + nfields * E * Nfp * s + 48 * K + 12 * K + (8 * K if alg1 else 0)
+    edge = dof * s + 60 * E_int + (8 * K if alg1 else 0) + nfields * E_int * Nfp * s
+    elem = dof * s + nfields * E_int * Nfp * s + 48 * K + dof * 24 + dof * s
     return edge, elem
 
 
-def edge_flops(K, Np, Nfp, N, E_int, E_bdy, alg1, nfields=1):
-    """Algorithmic FLOPs of the edge kernel per launch: nodal->Bernstein and
-    de Casteljau on both sides, the constant operator(s), the gamma/D combine."""
-    dec = 3 * N * (N + 1) * (N + 2) // 6 * 2
-    per_side = 2 * Np * Np + dec
+def algorithmic_flops(K, Np, Nfp, N, E_int, alg1, nfields):
+    """FLOPs per launch: edge, per field and interior edge, 2*2*(Np^2 +
+    N(N+1)(N+2)/2) (nodal -> Bernstein and de Casteljau, both sides) +
+    2*(2 Nfp)(2 Np)*c (c = 2 with Algorithm 1); element, per field and
+    element, 2*(4 Np^2 + 3 Np Nfp)."""
     c = 2 if alg1 else 1
-    per_edge = 2 * per_side + 2 * 2 * Nfp * 2 * Np * c + 6 * Nfp
-    per_bdy = per_side + 2 * 2 * Nfp * Np + 6 * Nfp
-    return nfields * (E_int * per_edge + E_bdy * per_bdy)
+    edge = nfields * E_int * (4 * (Np * Np + N * (N + 1) * (N + 2) // 2) + 2 * (2 * Nfp) * (2 * Np) * c)
+    elem = nfields * K * 2 * (4 * Np * Np + 3 * Np * Nfp)
+    return edge, elem
 
+
+class Case:
+    """One workload on the device: library mesh, initial data, time step."""
+
+    def __init__(self, name, dev, power_iters):
+        import torch
+        from paper_1912_06221_amd import ardg
+        self.name = name
+        spec = W.WORKLOADS[name]
+        self.spec = spec
+        cfg = spec["config"]
+        t0 = time.time()
+        self.mesh = W.split_square_mesh(spec["m"], spec["jitter"], seed=W.seed_for(cfg, "mesh"))
+        self.N = spec["N"]
+        self.nf = spec["fields"]
+        self.ops = ardg.Ops(self.N)
+        self.lm = ardg.Mesh(self.ops, self.mesh.vxy, self.mesh.etov, device=0)
+        self.D, self.D_mode = workload_D(spec, self.mesh)
+        self.alg1 = self.D_mode == "element"
+        if self.alg1:
+            self.lm.set_diffusion_element(self.D)
+        else:
+            self.lm.set_diffusion_const(self.D)
+        self.vel = ROTATION if spec.get("velocity") == "rotation" else None
+        if self.vel is not None:
+            self.lm.set_velocity(self.vel)
+        rs = self.ops.export(ardg.OPS_NODES).reshape(-1, 2)
+        x, y = nodal_xy(self.mesh, rs)
+        self.u0 = np.stack([W.fourier_modes(x, y, seed=W.seed_for(cfg, "IC") + 10 * f)
+                            for f in range(self.nf)])
+        self.K, self.Np, self.Nfp = self.mesh.K, self.ops.Np, self.ops.Nfp
+        self.dof = self.nf * self.K * self.Np
+        self.setup_s = time.time() - t0
+        # time step: the explicit limit from a power-iteration estimate of the
+        # spectral radius (setup, outside any timing)
+        v = torch.from_numpy(W.random_nodal((self.nf, self.K, self.Np), seed=7)).to(dev)
+        w = torch.empty_like(v)
+        rho = 0.0
+        for _ in range(power_iters):
+            self.lm.rhs_eval(v, w, nfields=self.nf)
+            nrm = float(torch.linalg.vector_norm(w))
+            rho = nrm / float(torch.linalg.vector_norm(v))
+            v = w / nrm
+        self.rho = rho
+        # RK4's stability region reaches 2.78/|lambda| on the negative real
+        # axis and less off it, and the power iteration approaches rho from
+        # below: take 1/rho (halved by run_steps if a run still blows up)
+        self.dt = 1.0 / rho
+        log(f"bench: {name}: K={self.K} N={self.N} fields={self.nf} setup {self.setup_s:.1f} s, "
+            f"rho~{rho:.3e}, dt={self.dt:.3e}")
+
+    def config(self):
+        return {"workload": self.name, "K": self.K, "N": self.N, "Np": self.Np, "DOF": self.dof,
+                "E_int": self.lm.E_int, "E_bdy": self.lm.E_bdy, "fields": self.nf,
+                "D": self.spec["D"], "velocity": self.spec.get("velocity"), "scheme": "RK4",
+                "dt": self.dt, "config_steps": self.spec["steps"]}
+
+    def time_mode(self, prec, steps, warmup, dev):
+        """ms per RK4 step over `steps` graph-replayed steps, and the per-kernel
+        average durations (HIP events on the launch stream, from replays of a
+        40-stage graph and of its element kernels alone)."""
+        import torch
+        from paper_1912_06221_amd import ardg
+        u = torch.from_numpy(self.u0.copy()).to(dev)
+        work = ardg.alloc_workspace(self.lm.workspace_bytes(ardg.RK4, prec, self.nf), dev)
+        for _ in range(warmup):
+            self.lm.rk_step(u, work, self.dt, 1, scheme=ardg.RK4, precision=prec, nfields=self.nf)
+        self.lm.rk_prepare(u, work, self.dt, steps, scheme=ardg.RK4, precision=prec, nfields=self.nf)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        self.lm.rk_step(u, work, self.dt, steps, scheme=ardg.RK4, precision=prec, nfields=self.nf)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        self.lm.check(u, nfields=self.nf)
+        t_edge, t_elem = self.lm.stage_timing(u, work, self.dt, 40, scheme=ardg.RK4, precision=prec,
+                                              nfields=self.nf)
+        return ms, t_edge, t_elem
+
+    def run_steps(self, prec, nsteps, dev, dt):
+        """The state after nsteps RK4 steps of size dt from u0 (host array), or
+        None if it is not finite (dt beyond the stability limit)."""
+        import torch
+        from paper_1912_06221_amd import ardg
+        u = torch.from_numpy(self.u0.copy()).to(dev)
+        work = ardg.alloc_workspace(self.lm.workspace_bytes(ardg.RK4, prec, self.nf), dev)
+        self.lm.rk_step(u, work, dt, nsteps, scheme=ardg.RK4, precision=prec, nfields=self.nf)
+        try:
+            self.lm.check(u, nfields=self.nf)
+        except ardg.ArdgError as e:
+            if e.status != -9:
+                raise
+            return None
+        return u.cpu().numpy()
+
+    def rhs_vs_oracle(self, prec, dev, nsample=12):
+        """max |rhs_mode - rhs_oracle| / scale on sampled elements per field
+        (scale: max |L u_r| for random data of the same amplitude, the size of
+        the operator's terms), one RHS of the initial data."""
+        import torch
+        from oracle.rhs import Problem
+        from paper_1912_06221_amd import ardg
+        if getattr(self, "_pr", None) is None:
+            self._pr = Problem(self.mesh.vxy, self.mesh.etov, self.N, self.D, D_mode=self.D_mode,
+                               velocity=self.vel, nfields=self.nf, build_edges=False)
+        pr = self._pr
+        rng = np.random.default_rng(3)
+        els = sorted(set(rng.choice(self.K, size=nsample, replace=False).tolist()) | {0, self.K - 1})
+        dt = torch.float64 if prec == ardg.FP64 else torch.float32
+        x = torch.from_numpy(self.u0).to(dev).to(dt)
+        out = torch.empty_like(x)
+        self.lm.rhs_eval(x, out, precision=prec, nfields=self.nf)
+        got = out.double().cpu().numpy()
+        ur = W.random_nodal(self.u0.shape, seed=9)
+        worst = 0.0
+        for f in range(self.nf):
+            ref = pr.rhs_elements(self.u0[f], els, field=f)
+            scale = np.abs(pr.rhs_elements(ur[f] * np.abs(self.u0[f]).max(), els, field=f)).max()
+            worst = max(worst, float(np.abs(got[f, els] - ref).max() / scale))
+        return worst
+
+
+def kernel_rates(case, t_edge_ms, t_elem_ms, s, prec_name):
+    b_edge, b_elem = algorithmic_bytes(case.K, case.Np, case.Nfp, case.lm.E_int, s, case.alg1, case.nf)
+    f_edge, f_elem = algorithmic_flops(case.K, case.Np, case.Nfp, case.N, case.lm.E_int, case.alg1, case.nf)
+    te, tl = t_edge_ms * 1e-3, t_elem_ms * 1e-3
+    peak = PEAK_TFLOPS[prec_name]
+    return {
+        "edge_us": t_edge_ms * 1e3, "element_us": t_elem_ms * 1e3,
+        "edge_bytes": b_edge, "element_bytes": b_elem,
+        "edge_GBps": b_edge / te / 1e9, "element_GBps": b_elem / tl / 1e9,
+        "edge_frac": b_edge / te / 1e9 / HBM_PEAK_GBS, "element_frac": b_elem / tl / 1e9 / HBM_PEAK_GBS,
+        "edge_TFLOPs": f_edge / te / 1e12, "element_TFLOPs": f_elem / tl / 1e12,
+        "edge_flop_frac": f_edge / te / 1e12 / peak, "element_flop_frac": f_elem / tl / 1e12 / peak,
+    }
+
+
+def mode_errors(case, states, u0):
+    """L2 differences of each mode's state to the FP64 state after the
+    workload's steps, relative to the state and to how far the FP64 state
+    moved from the initial data."""
+    u64 = states["fp64"]
+    inc = float(np.linalg.norm(u64 - u0))
+    out = {"fp64_evolution_rel_l2": inc / float(np.linalg.norm(u0))}
+    for mode, u in states.items():
+        if mode == "fp64":
+            continue
+        d = float(np.linalg.norm(u - u64))
+        out[mode] = {"rel_l2_vs_fp64_state": d / float(np.linalg.norm(u64)),
+                     "rel_l2_vs_fp64_increment": d / inc if inc > 0 else None}
+    return out
+
+
+def measure_case(case, args, dev, modes, error_steps):
+    from paper_1912_06221_amd import ardg
+    prec_of = {"fp64": ardg.FP64, "fp32": ardg.FP32, "bf16x3": ardg.BF16X3}
+    res = {}
+    for mode in modes:
+        ms, te, tl = case.time_mode(prec_of[mode], args.steps, args.warmup, dev)
+        s = 8 if mode == "fp64" else 4
+        r = {"ms_per_step": ms, "value": case.dof * 4 / (ms * 1e-3)}
+        r.update(kernel_rates(case, te, tl, s, mode))
+        res[mode] = r
+        log(f"bench: {case.name} {mode}: {ms:.3f} ms/step, edge {te*1e3:.1f} us "
+            f"({r['edge_frac']*100:.1f}% HBM), element {tl*1e3:.1f} us ({r['element_frac']*100:.1f}% HBM)")
+    if error_steps:
+        dt = case.dt
+        while True:
+            states = {m: case.run_steps(prec_of[m], error_steps, dev, dt) for m in modes}
+            if all(s is not None for s in states.values()) or dt < case.dt / 64:
+                break
+            log(f"bench: {case.name}: dt={dt:.3e} is beyond the stability limit; halving it")
+            dt *= 0.5
+        if any(s is None for s in states.values()):
+            raise RuntimeError(f"{case.name}: no stable time step found")
+        err = mode_errors(case, states, case.u0)
+        err["steps"] = error_steps
+        err["dt"] = dt
+        for m in modes:
+            err.setdefault(m, {})
+            err[m]["rhs_err_vs_oracle_sampled"] = case.rhs_vs_oracle(prec_of[m], dev)
+        res["errors"] = err
+        log(f"bench: {case.name} errors after {error_steps} steps: "
+            + ", ".join(f"{m} {err[m].get('rel_l2_vs_fp64_increment', 0.0) or 0.0:.2e}" for m in modes))
+    return res
+
+
+# ---------------------------------------------------------------------------
+# Batched workload
+# ---------------------------------------------------------------------------
 
 def bench_batch(args, dev):
     """512 independent heat problems of 200-20000 triangles, N in {2,3,4},
@@ -155,6 +349,7 @@ def bench_batch(args, dev):
     out = {"workload": "512 heat problems, K_i 200-20000 (log-uniform), N in {2,3,4}, D per problem",
            "problems": len(specs), "DOF": dof}
     b = ardg.Batch(meshes)
+    finals = {}
     for name, prec in (("fp64", ardg.FP64), ("fp32", ardg.FP32)):
         us = [torch.from_numpy(u.copy()).to(dev) for u in states]
         work = ardg.alloc_workspace(b.workspace_bytes(ardg.RK4, prec), dev)
@@ -169,12 +364,16 @@ def bench_batch(args, dev):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        finals[name] = [u.cpu().numpy() for u in us]
         out[f"batched_{name}"] = {"ms_per_step": ms, "value": dof * 4 / (ms * 1e-3)}
         tiles = {}
         for N in (2, 3, 4):
             et, lt, gm = b.tiles(prec, N)
             tiles[f"N{N}"] = {"edge_tile": et, "elem_tile": lt, "grid_per_cu": gm}
         out[f"batched_{name}"]["tiles"] = tiles
+    num = sum(float(np.sum((a - c) ** 2)) for a, c in zip(finals["fp32"], finals["fp64"]))
+    den = sum(float(np.sum(c ** 2)) for c in finals["fp64"])
+    out["batched_fp32"]["rel_l2_vs_batched_fp64_state"] = math.sqrt(num / den)
     # plain path: one graph launch per mesh per step, FP64
     us = [torch.from_numpy(u.copy()).to(dev) for u in states]
     works = [ardg.alloc_workspace(m.workspace_bytes(ardg.RK4, ardg.FP64, 1), dev) for m in meshes]
@@ -192,39 +391,107 @@ def bench_batch(args, dev):
     ms = e0.elapsed_time(e1) / steps
     out["per_mesh_fp64"] = {"ms_per_step": ms, "value": dof * 4 / (ms * 1e-3)}
     out["speedup_batched_fp32_vs_per_mesh_fp64"] = ms / out["batched_fp32"]["ms_per_step"]
+    out["speedup_batched_fp64_vs_per_mesh_fp64"] = ms / out["batched_fp64"]["ms_per_step"]
     return out
 
 
-def cpu_baseline(spec, mesh, D, u, budget_s=12.0):
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on the host's cores
+# ---------------------------------------------------------------------------
+
+def _strip(mesh, m, j0, rows):
+    """Sub-mesh of the cell rows [j0, j0 + rows) of an m x m split-square mesh
+    (cell-major element numbering), vertices renumbered."""
+    e = mesh.etov[2 * j0 * m: 2 * (j0 + rows) * m]
+    used, inv = np.unique(e, return_inverse=True)
+    return mesh.vxy[used], inv.reshape(e.shape).astype(np.int32)
+
+
+def _oracle_worker(vxy, etov, N, D, D_mode, vel, nf, reps, seed, barrier, queue):
+    os.environ["OMP_NUM_THREADS"] = "1"
     from oracle.rhs import Problem
     t0 = time.time()
-    pr = Problem(mesh.vxy, mesh.etov, spec["N"], D, D_mode="element", build_edges=False)
+    pr = Problem(vxy, etov, N, D, D_mode=D_mode, velocity=vel, nfields=nf)
     setup = time.time() - t0
-    # calibrate on 50 elements, then run a sample sized to the budget
+    u = np.random.default_rng(seed).standard_normal((nf, etov.shape[0], pr.ops.Np))
+    barrier.wait()
     t0 = time.time()
-    pr.rhs_elements(u, list(range(50)))
-    per = (time.time() - t0) / 50
-    S = int(max(200, min(mesh.K, budget_s / max(per, 1e-6))))
-    t0 = time.time()
-    pr.rhs_elements(u, list(range(S)))
-    dt = time.time() - t0
-    Np = pr.ops.Np
-    return {"value": S * Np / dt, "unit": "DOF*stage/s", "cores": 1, "kind": "oracle",
-            "sample": f"one RHS stage (literal per-edge aRDG / Algorithm 1 operators) on the first "
-                      f"{S} of {mesh.K} elements of the same workload; {dt:.1f} s; geometry setup "
-                      f"{setup:.1f} s excluded; single-threaded NumPy"}
+    for _ in range(reps):
+        pr.rhs(u)
+    queue.put((setup, time.time() - t0, reps * u.size))
 
+
+def cpu_baseline(name, rows_per_worker=2, reps=4):
+    """The oracle's assembled RHS (edge operators prebuilt, setup reported
+    apart) on strips of cell rows of the workload's mesh, one strip per worker
+    process on the host's cores; DOF*stage/s = DOF evaluated / wall time
+    between the common start and the last worker's end."""
+    import multiprocessing as mp
+    spec = W.WORKLOADS[name]
+    cfg = spec["config"]
+    m = spec["m"]
+    mesh = W.split_square_mesh(m, spec["jitter"], seed=W.seed_for(cfg, "mesh"))
+    D, D_mode = workload_D(spec, mesh)
+    vel = ROTATION if spec.get("velocity") == "rotation" else None
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu))
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(workers + 1)
+    queue = ctx.Queue()
+    procs = []
+    for w in range(workers):
+        j0 = (w * rows_per_worker * 7) % (m - rows_per_worker)
+        vxy, etov = _strip(mesh, m, j0, rows_per_worker)
+        Dw = D if D_mode == "const" else D[2 * j0 * m: 2 * (j0 + rows_per_worker) * m]
+        p = ctx.Process(target=_oracle_worker, args=(vxy, etov, spec["N"], Dw, D_mode, vel, spec["fields"],
+                                                     reps, w, barrier, queue))
+        p.start()
+        procs.append(p)
+    barrier.wait()
+    t0 = time.time()
+    res = [queue.get() for _ in range(workers)]
+    wall = time.time() - t0
+    for p in procs:
+        p.join()
+    dof = sum(r[2] for r in res)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    K_strip = 2 * m * rows_per_worker
+    return {"value": dof / wall, "unit": "DOF*stage/s", "cores": workers, "kind": "oracle",
+            "cpu_model": model, "host_cpus": ncpu,
+            "sample": (f"{workers} worker processes (one thread each), each evaluating the oracle's assembled "
+                       f"RHS (literal per-edge aRDG operators prebuilt, weak-form volume term, upwind "
+                       f"convection, {spec['fields']} fields) {reps} times on its own strip of "
+                       f"{rows_per_worker} cell rows ({K_strip} elements) of the {name} mesh; "
+                       f"{wall:.1f} s wall for {dof:.3g} DOF*stage; operator setup "
+                       f"{max(r[0] for r in res):.1f} s per worker excluded")}
+
+
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="contrast_256x256_N4")
+    ap.add_argument("--workload", default=HEADLINE, help="headline workload")
+    ap.add_argument("--extras", default="contrast_256x256_N4,loguniformD_512x512_N6",
+                    help="comma-separated extra workloads ('' for none)")
+    ap.add_argument("--modes", default="fp64,fp32,bf16x3")
+    ap.add_argument("--no-errors", action="store_true", help="skip the error runs (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--skip-fp32", action="store_true", help="time the FP64 path only")
-    ap.add_argument("--power-iters", type=int, default=30)
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched workload")
+    ap.add_argument("--power-iters", type=int, default=60)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of 512 MiB first (counter calibration)")
     args = ap.parse_args()
@@ -233,36 +500,15 @@ def main():
               f"(sharding the mesh over several GPUs is a design, not implemented)", file=sys.stderr)
         sys.exit(2)
 
+    # the oracle's worker processes start before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host cores (cpu_baseline)")
+        cpu = cpu_baseline(args.workload)
+        log(f"bench: cpu_baseline {cpu['value']:.3e} DOF*stage/s on {cpu['cores']} cores")
+
     import torch
-    from paper_1912_06221_amd import ardg
-
     dev = torch.device("cuda:0")
-    spec, mesh = build_workload(args.workload)
-    N = spec["N"]
-    cfg = spec["config"]
-    log(f"bench: workload {args.workload} K={mesh.K} N={N}")
-    ops = ardg.Ops(N)
-    lm = ardg.Mesh(ops, mesh.vxy, mesh.etov, device=0)
-    alg1 = spec["D"] in ("circle", "loguniform")
-    if spec["D"] == "circle":
-        D = W.circle_contrast_D(mesh)
-    elif spec["D"] == "loguniform":
-        D = W.loguniform_per_element(mesh.K, spec["Dlo"], spec["Dhi"], W.seed_for(cfg, "D"))
-    else:
-        D = np.array(spec.get("Dfield", [spec.get("Dval", 1.0)]))
-    nf = spec["fields"]
-    if alg1:
-        lm.set_diffusion_element(D)
-    else:
-        lm.set_diffusion_const(D)
-    if spec.get("velocity") == "rotation":
-        lm.set_velocity([0.0, 0.0, 0.0, -1.0, 1.0, 0.0])
-    rs = ops.export(ardg.OPS_NODES).reshape(-1, 2)
-    x, y = nodal_xy(mesh, rs)
-    u0 = np.stack([W.fourier_modes(x, y, seed=W.seed_for(cfg, "IC") + 10 * f) for f in range(nf)])
-    K, Np, Nfp = mesh.K, ops.Np, ops.Nfp
-    dof = nf * K * Np
-
     if args.calib_copy:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -272,109 +518,74 @@ def main():
         log(f"bench: calibration copy of {a.numel() * 8} bytes done")
         del a, b
 
-    # time step from a power-iteration estimate of the spectral radius (setup)
-    v = torch.from_numpy(W.random_nodal((nf, K, Np), seed=7)).to(dev)
-    w = torch.empty_like(v)
-    rho = 0.0
-    for _ in range(args.power_iters):
-        lm.rhs_eval(v, w, nfields=nf)
-        nrm = float(torch.linalg.vector_norm(w))
-        rho = nrm / float(torch.linalg.vector_norm(v))
-        v = w / nrm
-    # half the explicit limit of the estimate: power iteration approaches the
-    # spectral radius from below, and the L2 differences between precisions
-    # are only meaningful on a stable run
-    dt = 0.5 / rho
-    log(f"bench: spectral radius ~{rho:.3e}, dt={dt:.3e}")
-
-    results = {}
-    for prec_name, prec in (("fp64", ardg.FP64), ("fp32", ardg.FP32), ("bf16x3", ardg.BF16X3)):
-        if prec_name != "fp64" and args.skip_fp32:
-            continue
-        u = torch.from_numpy(u0.copy()).to(dev)
-        work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, prec, nf), dev)
-        for _ in range(args.warmup):
-            lm.rk_step(u, work, dt, 1, scheme=ardg.RK4, precision=prec, nfields=nf)
-        # the K timed steps are one graph (captured here, outside the timing)
-        lm.rk_prepare(u, work, dt, args.steps, scheme=ardg.RK4, precision=prec, nfields=nf)
-        torch.cuda.synchronize()
-        st = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        lm.rk_step(u, work, dt, args.steps, scheme=ardg.RK4, precision=prec, nfields=nf)
-        e1.record(st)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        lm.check(u, nfields=nf)
-        un = u.detach().cpu().numpy()
-        # per-kernel durations: HIP events on the launch stream around replays
-        # of a 40-stage graph and of its element kernels alone (alters u, so
-        # it comes after the state is read)
-        t_edge, t_elem = lm.stage_timing(u, work, dt, 40, scheme=ardg.RK4, precision=prec, nfields=nf)
-        results[prec_name] = dict(ms=ms, t_edge=t_edge, t_elem=t_elem, u=un,
-                                  norm_ratio=float(np.linalg.norm(un) / np.linalg.norm(u0)))
-        log(f"bench: {prec_name}: {ms:.3f} ms/step, edge {t_edge*1e3:.1f} us, elem {t_elem*1e3:.1f} us")
-
-    r64 = results["fp64"]
-    value = dof * 4 / (r64["ms"] * 1e-3)
-    s64 = 8
-    b_edge, b_elem = algorithmic_bytes(K, Np, Nfp, lm.E_int, lm.E_bdy, s64, alg1, nf)
-    bw_edge = b_edge / (r64["t_edge"] * 1e-3) / 1e9
-    bw_elem = b_elem / (r64["t_elem"] * 1e-3) / 1e9
-    dom = "element" if r64["t_elem"] >= r64["t_edge"] else "edge"
-    bw = bw_elem if dom == "element" else bw_edge
-    traffic = stored_traffic(args.workload, f"{dom}-fp64")
-    fl = edge_flops(K, Np, Nfp, N, lm.E_int, lm.E_bdy, alg1, nf)
+    modes = [m for m in args.modes.split(",") if m]
+    head = Case(args.workload, dev, args.power_iters)
+    hr = measure_case(head, args, dev, modes, 0 if args.no_errors else head.spec["steps"])
+    r64 = hr["fp64"]
+    dom = "element" if r64["element_us"] >= r64["edge_us"] else "edge"
+    ctr = stored_counters(args.workload)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": r64[f"{dom}_GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": r64[f"{dom}_frac"],
+            "traffic": ctr.get(f"{dom}-fp64 hbm_bytes"),
+            "edge_frac": r64["edge_frac"], "edge_GBps": r64["edge_GBps"], "edge_us": r64["edge_us"],
+            "edge_bytes": r64["edge_bytes"], "edge_traffic": ctr.get("edge-fp64 hbm_bytes"),
+            "element_frac": r64["element_frac"], "element_GBps": r64["element_GBps"],
+            "element_us": r64["element_us"], "element_bytes": r64["element_bytes"],
+            "element_traffic": ctr.get("element-fp64 hbm_bytes"),
+            "edge_fp64_flop_frac": r64["edge_flop_frac"], "element_fp64_flop_frac": r64["element_flop_frac"]}
+    mf = ctr.get("element-fp64 mfma_flops")
+    if mf is not None:
+        roof["element_mfma_fp64_frac"] = mf / (r64["element_us"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"]
+    vf = ctr.get("edge-fp64 valu_flops")
+    if vf is not None:
+        roof["edge_valu_fp64_frac"] = vf / (r64["edge_us"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"]
     line = {
-        "metric": "DOF*RK-stage/s per MI355X (FP64 path; mixed FP32 and BF16x3 paths beside it with L2 difference)",
-        "value": value,
+        "metric": "DOF*RK-stage/s per MI355X (FP64 path; FP32 and split-BF16 paths beside it with their L2 "
+                  "error after the workload's steps); % HBM roofline",
+        "value": r64["value"],
         "unit": "DOF*stage/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r64["ms"],
+        "ms_per_step": r64["ms_per_step"],
         "step": "one classic RK4 time step = 4 RHS stages (edge kernel + element kernel each)",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded jittered mesh, seeded D field and Fourier initial data)",
-        "config": {"workload": args.workload, "K": K, "N": N, "Np": Np, "DOF": dof,
-                   "E_int": lm.E_int, "E_bdy": lm.E_bdy, "D": spec["D"], "scheme": "RK4",
-                   "dt": dt, "fields": nf},
-        "state_norm_ratio": r64["norm_ratio"],
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": bw, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": bw / HBM_PEAK_GBS, "traffic": traffic,
-                     "edge_kernel_us": r64["t_edge"] * 1e3, "element_kernel_us": r64["t_elem"] * 1e3,
-                     "edge_GBps": bw_edge, "element_GBps": bw_elem,
-                     "edge_algorithmic_bytes": b_edge, "element_algorithmic_bytes": b_elem,
-                     "edge_TFLOPs": fl / (r64["t_edge"] * 1e-3) / 1e12,
-                     "edge_fp64_frac": fl / (r64["t_edge"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+        "data": "synthetic (seeded jittered mesh, seeded Fourier initial data per field)",
+        "config": head.config(),
+        "roofline": roof,
+        "modes": {m: hr[m] for m in modes},
     }
-    for mode in ("fp32", "bf16x3"):
-        if mode not in results:
-            continue
-        r32 = results[mode]
-        d = r32["u"] - r64["u"]
-        l2 = float(np.sqrt(np.sum(d * d) / np.sum(r64["u"] ** 2)))
-        b_edge32, b_elem32 = algorithmic_bytes(K, Np, Nfp, lm.E_int, lm.E_bdy, 4, alg1, nf)
-        line["mixed_" + mode] = {
-            "value": dof * 4 / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"],
-            "speedup_vs_fp64": r64["ms"] / r32["ms"],
-            "rel_l2_diff_vs_fp64_after_steps": l2,
-            "edge_kernel_us": r32["t_edge"] * 1e3, "element_kernel_us": r32["t_elem"] * 1e3,
-            "edge_GBps": b_edge32 / (r32["t_edge"] * 1e-3) / 1e9,
-            "element_GBps": b_elem32 / (r32["t_elem"] * 1e-3) / 1e9,
-        }
+    for m in modes:
+        if m != "fp64":
+            line["modes"][m]["speedup_vs_fp64"] = r64["ms_per_step"] / hr[m]["ms_per_step"]
+    if "errors" in hr:
+        line["errors"] = hr["errors"]
+    extras = {}
+    for name in [x for x in args.extras.split(",") if x]:
+        c = Case(name, dev, args.power_iters)
+        # the precision workload states every mode's error after its steps
+        steps = c.spec["steps"] if (not args.no_errors and name.startswith("loguniform")) else 0
+        r = measure_case(c, args, dev, modes, steps)
+        r["config"] = c.config()
+        for m in modes:
+            if m != "fp64":
+                r[m]["speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r[m]["ms_per_step"]
+        extras[name] = r
+        del c
+        torch.cuda.empty_cache()
+    if extras:
+        line["extra_workloads"] = extras
     if not args.no_batch:
         log("bench: batched workload (512 problems)")
         line["batch"] = bench_batch(args, dev)
         bb = line["batch"]
         log(f"bench: batch fp64 {bb['batched_fp64']['ms_per_step']:.3f} ms, fp32 "
             f"{bb['batched_fp32']['ms_per_step']:.3f} ms, per-mesh fp64 {bb['per_mesh_fp64']['ms_per_step']:.3f} ms")
-    if not args.no_cpu_baseline:
-        log("bench: timing the oracle on a bounded sample (cpu_baseline)")
-        line["cpu_baseline"] = cpu_baseline(spec, mesh, D, u0[0])
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

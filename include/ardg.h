@@ -63,6 +63,14 @@ enum { ARDG_FP64 = 0, ARDG_FP32 = 1, ARDG_BF16X3 = 2 };
 enum { ARDG_RK4 = 0, ARDG_LSERK54 = 1 };
 enum { ARDG_D_CONST = 0, ARDG_D_ELEMENT = 1 };
 enum { ARDG_VEL_NONE = 0, ARDG_VEL_AFFINE = 1 };
+/* Edge kernel implementations (ardg_mesh_set_kernels). */
+enum {
+  ARDG_EDGE_AUTO = 0,        /* chosen per launch (default)                                 */
+  ARDG_EDGE_SPLIT = 1,       /* two waves per 64-edge tile, one per side, vector unit        */
+  ARDG_EDGE_LANE = 2,        /* one lane per edge, vector unit                               */
+  ARDG_EDGE_MFMA = 3,        /* one wave per 64 edges on the matrix cores                    */
+  ARDG_EDGE_SPLIT_MFMA = 4   /* side-split tiles, nodal -> Bernstein on the matrix cores     */
+};
 
 /* ardg_ops_export selectors (row-major double arrays). */
 enum {
@@ -148,6 +156,17 @@ void ardg_mesh_destroy(ardg_mesh mesh);
  * Algorithm 1's reconstruction of D grad u~.  All values must be finite > 0. */
 ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfields,
                                     const double* D);
+
+/* Edge kernel implementation for this mesh's launches (ARDG_EDGE_*).  All
+ * compute the same flux up to rounding (Algorithm aRDG, Algorithm 1); the
+ * default ARDG_EDGE_AUTO takes the side-split tiles where one lane per edge
+ * would leave the chip latency-bound (fewer than ~8 waves per SIMD, or
+ * N >= 5) and one lane per edge otherwise, and for ARDG_BF16X3 the
+ * matrix-core kernels (side-split up to N = 3).  Split-BF16 products exist
+ * only on the matrix cores, so with ARDG_BF16X3 the vector-unit choices
+ * (ARDG_EDGE_SPLIT, ARDG_EDGE_LANE) run ARDG_EDGE_MFMA.  Drops the mesh's
+ * captured step graphs.  Errors: E_INVALID_ARG. */
+ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel);
 
 /* Velocity of the convective term of eq. convection_diffusion, for every
  * field: ARDG_VEL_NONE, or ARDG_VEL_AFFINE with v(x,y) = (p0 + p2 x + p3 y,

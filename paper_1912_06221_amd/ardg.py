@@ -13,15 +13,14 @@ from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
 
-# ARDG_LIB may point at another build of the same library (A/B timing).
-LIB_PATH = os.environ.get("ARDG_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                      "libardg.so")
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libardg.so")
 
 OK = 0
 FP64, FP32, BF16X3 = 0, 1, 2
 RK4, LSERK54 = 0, 1
 D_CONST, D_ELEMENT = 0, 1
 VEL_NONE, VEL_AFFINE = 0, 1
+EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA = 0, 1, 2, 3, 4
 
 OPS_NODES, OPS_V, OPS_DR, OPS_DS, OPS_MASS, OPS_LIFT = 0, 1, 2, 3, 4, 5
 OPS_FACE_NODES, OPS_ROT_PERM, OPS_RECON_A, OPS_RECON_R = 6, 7, 8, 9
@@ -55,6 +54,7 @@ SIGNATURES = {
     "ardg_mesh_destroy": (None, [c_void_p]),
     "ardg_mesh_set_diffusion": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
     "ardg_mesh_set_velocity": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
+    "ardg_mesh_set_kernels": (c_int32, [c_void_p, c_int32]),
     "ardg_rhs_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
     "ardg_edge_flux_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "ardg_rk_workspace_bytes": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_int64)]),
@@ -190,6 +190,9 @@ class Mesh:
         else:
             p = np.ascontiguousarray(params, dtype=np.float64)
             _check(lib().ardg_mesh_set_velocity(self.handle, VEL_AFFINE, _dptr(p)))
+
+    def set_kernels(self, edge_kernel: int = EDGE_AUTO):
+        _check(lib().ardg_mesh_set_kernels(self.handle, edge_kernel))
 
     # ---- device calls (torch tensors on this mesh's device) ---------------
     def rhs_eval(self, u, out, precision: int = FP64, nfields: int = 1, stream=None):

@@ -81,9 +81,6 @@ void pack_into(const RefOps& o, std::vector<double>& out) {
     out[L.nr + n] = o.r[n];
     out[L.ns + n] = o.s[n];
   }
-  put(L.b2n, o.Bv);
-  put(L.drb, matmul(o.Dr, o.Bv));
-  put(L.dsb, matmul(o.Ds, o.Bv));
   // 1D Bernstein basis of degree N at the face's LGL nodes, tau = (x + 1)/2
   // measured from the face's first (counter-clockwise) vertex
   for (int j = 0; j < o.Nfp; ++j) {
@@ -261,27 +258,7 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
     int st = build_host_mesh(vxy, Nv, etov, K, m->hm, err);
     if (st != ARDG_OK) return fail(st, err);
     m->dm.N = m->N;
-    {
-      // kernel implementations.  Element kernel: matrix cores (default) or one
-      // thread per element (ARDG_ELEMENT_KERNEL=valu).  Edge kernel: chosen
-      // per launch from the grid size (default), two waves per tile split by
-      // side (ARDG_EDGE_KERNEL=split), the same with the conversion on the
-      // matrix cores (=split-mfma), one thread per edge (=lane) or interior
-      // edges on the matrix cores (=mfma).
-      const char* ek = std::getenv("ARDG_ELEMENT_KERNEL");
-      m->dm.elem_mfma = (ek && std::string(ek) == "valu") ? 0 : 1;
-      const char* ed = std::getenv("ARDG_EDGE_KERNEL");
-      const std::string eds = ed ? ed : "";
-      m->dm.edge_kernel = eds == "mfma" ? EDGE_MFMA
-                          : eds == "lane" ? EDGE_LANE
-                          : eds == "split" ? EDGE_SPLIT
-                          : eds == "split-mfma" ? EDGE_SPLIT_MFMA : EDGE_AUTO;
-      // stage vectors: nodal values (default), or Bernstein coefficients
-      // emitted by the element kernel where the kernels allow it
-      // (ARDG_STAGE_FORM=bernstein)
-      const char* sf = std::getenv("ARDG_STAGE_FORM");
-      m->dm.bern = (sf && std::string(sf) == "bernstein") ? 1 : 0;
-    }
+    m->dm.edge_kernel = EDGE_AUTO;
     m->dm.K = m->hm.K;
     m->dm.E_int = m->hm.E_int;
     m->dm.E_bdy = m->hm.E_bdy;
@@ -524,12 +501,13 @@ static ardg_status ensure_scratch(ardg_mesh mesh, size_t bytes) {
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Stage vectors as Bernstein coefficients: the edge kernel then skips the
-// conversion (the element kernel emits the coefficients).  Needs the
-// matrix-core element kernel and a vector-unit edge kernel; FP64 and FP32.
-static bool use_bern(ardg_mesh mesh, int precision) {
-  return mesh->dm.bern && mesh->dm.elem_mfma && mesh->dm.edge_kernel != EDGE_MFMA &&
-         mesh->dm.edge_kernel != EDGE_SPLIT_MFMA && precision != ARDG_BF16X3;
+ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel) {
+  if (!mesh) return fail(ARDG_E_INVALID_ARG, "set_kernels: null handle");
+  if (edge_kernel < ARDG_EDGE_AUTO || edge_kernel > ARDG_EDGE_SPLIT_MFMA)
+    return fail(ARDG_E_INVALID_ARG, "set_kernels: unknown edge kernel");
+  mesh->dm.edge_kernel = edge_kernel;
+  mesh->drop_graphs();
+  return ARDG_OK;
 }
 
 ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
@@ -539,17 +517,7 @@ ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfiel
   if (!u_dev || !flux_dev) return fail(ARDG_E_INVALID_ARG, "edge_flux_eval: null buffer");
   DeviceGuard g(mesh->device);
   hipStream_t st = (hipStream_t)hip_stream;
-  const bool f64 = precision == ARDG_FP64;
-  const bool bern = use_bern(mesh, precision);
-  const void* vin = u_dev;
-  if (bern) {
-    const size_t nb = (size_t)nfields * mesh->hm.K * mesh->ro.Np * (f64 ? 8 : 4);
-    s = ensure_scratch(mesh, nb);
-    if (s != ARDG_OK) return s;
-    HIP_TRY(launch_to_bernstein(mesh->dm, f64, f64, nfields, u_dev, mesh->flux_scratch, st), "conversion launch");
-    vin = mesh->flux_scratch;
-  }
-  HIP_TRY(launch_edge_flux(mesh->dm, precision, bern, nfields, vin, flux_dev, st), "edge flux launch");
+  HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux_dev, st), "edge flux launch");
   return ARDG_OK;
 }
 
@@ -560,29 +528,19 @@ ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, co
   if (s != ARDG_OK) return s;
   if (!u_dev || !rhs_dev) return fail(ARDG_E_INVALID_ARG, "rhs_eval: null buffer");
   DeviceGuard g(mesh->device);
-  const bool f64 = precision == ARDG_FP64;
-  const bool bern = use_bern(mesh, precision);
-  const size_t ts = f64 ? 8 : 4;
+  const size_t ts = precision == ARDG_FP64 ? 8 : 4;
   const size_t fb = align256((size_t)nfields * (mesh->hm.E_int + mesh->hm.E_bdy) * mesh->ro.Nfp * ts);
-  const size_t nb = bern ? (size_t)nfields * mesh->hm.K * mesh->ro.Np * ts : 0;
-  s = ensure_scratch(mesh, fb + nb);
+  s = ensure_scratch(mesh, fb);
   if (s != ARDG_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   void* flux = mesh->flux_scratch;
-  const void* vin = u_dev;
-  if (bern) {
-    void* vb = (char*)mesh->flux_scratch + fb;
-    HIP_TRY(launch_to_bernstein(mesh->dm, f64, f64, nfields, u_dev, vb, st), "conversion launch");
-    vin = vb;
-  }
-  HIP_TRY(launch_edge_flux(mesh->dm, precision, bern, nfields, vin, flux, st), "edge flux launch");
+  HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux, st), "edge flux launch");
   Epilogue epi;
   epi.kind = EPI_RHS;
   epi.rhs_out = rhs_dev;
-  HIP_TRY(launch_element(mesh->dm, precision, bern, nfields, vin, flux, epi, st), "element launch");
+  HIP_TRY(launch_element(mesh->dm, precision, nfields, u_dev, flux, epi, st), "element launch");
   return ARDG_OK;
 }
-
 
 struct Work {
   double* acc;
@@ -625,23 +583,22 @@ static const double kLsB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.
                                1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                                2277821191437.0 / 14882151754819.0};
 
-// Stage input and next-stage output of stage s.  Nodal FP64 stages read the
-// state itself at RK4 stage 0 and at every LSERK stage and need no stage
-// vector after the last RK4 stage; everything else goes through the stage
-// vector v (FP32 copies, or Bernstein coefficients).
+// Stage input and next-stage output of stage s.  FP64 stages read the state
+// itself at RK4 stage 0 and at every LSERK stage and need no stage vector
+// after the last RK4 stage; everything else goes through the stage vector v
+// (FP32 copies in the reduced precisions).
 struct StageIO {
   const void* vin;
   void* vnext;
 };
 
-static StageIO stage_io(int scheme, bool f64, bool bern, int s, double* u, void* v) {
+static StageIO stage_io(int scheme, bool f64, int s, double* u, void* v) {
   StageIO io;
-  const bool nodal64 = f64 && !bern;
-  io.vin = (nodal64 && (scheme == ARDG_LSERK54 || s == 0)) ? (const void*)u : v;
+  io.vin = (f64 && (scheme == ARDG_LSERK54 || s == 0)) ? (const void*)u : v;
   if (scheme == ARDG_RK4)
-    io.vnext = (s < 3 || !nodal64) ? v : nullptr;
+    io.vnext = (s < 3 || !f64) ? v : nullptr;
   else
-    io.vnext = nodal64 ? nullptr : v;
+    io.vnext = f64 ? nullptr : v;
   return io;
 }
 
@@ -656,22 +613,18 @@ static void stage_epilogue(int scheme, int s, Epilogue& epi) {
   }
 }
 
-// First stage input from the FP64 state: an FP32 copy, or Bernstein
-// coefficients in the compute type; nothing for nodal FP64.
-static hipError_t stage_vector_init(ardg_mesh mesh, int precision, bool bern, int nfields, const double* u,
-                                    void* v, hipStream_t st) {
-  const bool f64 = precision == ARDG_FP64;
+// First stage input from the FP64 state: an FP32 copy (nothing for FP64).
+static hipError_t stage_vector_init(ardg_mesh mesh, int precision, int nfields, const double* u, void* v,
+                                    hipStream_t st) {
   const int64_t n = (int64_t)nfields * mesh->hm.K * mesh->ro.Np;
-  if (bern) return launch_to_bernstein(mesh->dm, true, f64, nfields, u, v, st);
-  if (!f64) return launch_to_f32(u, (float*)v, n, st);
+  if (precision != ARDG_FP64) return launch_to_f32(u, (float*)v, n, st);
   return hipSuccess;
 }
 
 static hipError_t enqueue_steps(ardg_mesh mesh, int scheme, int precision, int nfields, double* u,
                                 const Work& w, double dt, int nsteps, hipStream_t st) {
   const bool f64 = precision == ARDG_FP64;
-  const bool bern = use_bern(mesh, precision);
-  hipError_t e = stage_vector_init(mesh, precision, bern, nfields, u, w.v, st);
+  hipError_t e = stage_vector_init(mesh, precision, nfields, u, w.v, st);
   if (e != hipSuccess) return e;
   Epilogue epi;
   epi.u = u;
@@ -680,12 +633,12 @@ static hipError_t enqueue_steps(ardg_mesh mesh, int scheme, int precision, int n
   const int nst = scheme == ARDG_RK4 ? 4 : 5;
   for (int step = 0; step < nsteps; ++step) {
     for (int s = 0; s < nst; ++s) {
-      const StageIO io = stage_io(scheme, f64, bern, s, u, w.v);
-      e = launch_edge_flux(mesh->dm, precision, bern, nfields, io.vin, w.flux, st);
+      const StageIO io = stage_io(scheme, f64, s, u, w.v);
+      e = launch_edge_flux(mesh->dm, precision, nfields, io.vin, w.flux, st);
       if (e != hipSuccess) return e;
       stage_epilogue(scheme, s, epi);
       epi.vnext = io.vnext;
-      e = launch_element(mesh->dm, precision, bern, nfields, io.vin, w.flux, epi, st);
+      e = launch_element(mesh->dm, precision, nfields, io.vin, w.flux, epi, st);
       if (e != hipSuccess) return e;
     }
   }
@@ -784,23 +737,22 @@ ardg_status ardg_rk_prepare(ardg_mesh mesh, int32_t scheme, int32_t precision, i
 static hipError_t capture_stages(ardg_mesh mesh, int scheme, int precision, int nfields, double* u_dev,
                                  const Work& w, double dt, int reps, bool with_edge, hipGraphExec_t* out) {
   const bool f64 = precision == ARDG_FP64;
-  const bool bern = use_bern(mesh, precision);
   const int nst = scheme == ARDG_RK4 ? 4 : 5;
   hipStream_t cs = mesh->cap_stream;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t ec = stage_vector_init(mesh, precision, bern, nfields, u_dev, w.v, cs);
+  hipError_t ec = stage_vector_init(mesh, precision, nfields, u_dev, w.v, cs);
   Epilogue epi;
   epi.u = u_dev;
   epi.acc = w.acc;
   epi.dt = dt;
   for (int r = 0; r < reps && ec == hipSuccess; ++r) {
     const int sidx = r % nst;
-    const StageIO io = stage_io(scheme, f64, bern, sidx, u_dev, w.v);
+    const StageIO io = stage_io(scheme, f64, sidx, u_dev, w.v);
     stage_epilogue(scheme, sidx, epi);
     epi.vnext = io.vnext;
-    if (with_edge) ec = launch_edge_flux(mesh->dm, precision, bern, nfields, io.vin, w.flux, cs);
-    if (ec == hipSuccess) ec = launch_element(mesh->dm, precision, bern, nfields, io.vin, w.flux, epi, cs);
+    if (with_edge) ec = launch_edge_flux(mesh->dm, precision, nfields, io.vin, w.flux, cs);
+    if (ec == hipSuccess) ec = launch_element(mesh->dm, precision, nfields, io.vin, w.flux, epi, cs);
   }
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs, &graph);

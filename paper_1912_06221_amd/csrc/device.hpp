@@ -15,13 +15,11 @@ constexpr int kMaxFields = 16;
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 
 // Offsets of the packed constant operators (same layout in FP64 and FP32).
-// b2n: Bernstein coefficients -> nodal values; drb, dsb: Dr and Ds acting on
-// Bernstein coefficients (Dr b2n, Ds b2n); bf2n: 1D Bernstein coefficients of
-// a face -> values at its LGL nodes.
+// bf2n: 1D Bernstein coefficients of a face -> values at its LGL nodes.
 struct OpLayout {
   int Np, Nfp;
   int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, drsh, lift, tau, nr, ns;
-  int b2n, drb, dsb, bf2n, total;
+  int bf2n, total;
   __host__ __device__ constexpr OpLayout(int N)
       : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
         n2b(0),
@@ -44,17 +42,15 @@ struct OpLayout {
         tau(lift + Np * 3 * Nfp),
         nr(tau + Nfp),
         ns(nr + Np),
-        b2n(ns + Np),
-        drb(b2n + Np * Np),
-        dsb(drb + Np * Np),
-        bf2n(dsb + Np * Np),
+        bf2n(ns + Np),
         total(bf2n + Nfp * Nfp) {}
 };
 
-// Edge kernel implementations.
+// Edge kernel implementations (values as ARDG_EDGE_* in the C ABI).
 // EDGE_AUTO picks EDGE_SPLIT where one thread per edge leaves the chip
 // latency-bound (few waves per SIMD, or high order with few waves resident)
-// and EDGE_LANE otherwise.
+// and EDGE_LANE otherwise; split-BF16 products run on EDGE_SPLIT_MFMA up to
+// N = 3 and on EDGE_MFMA above.
 enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, EDGE_SPLIT_MFMA = 4 };
 
 struct DevMesh {
@@ -75,9 +71,7 @@ struct DevMesh {
   const double* ops64 = nullptr;
   const float* ops32 = nullptr;
   int alg1 = 0;                   // element-wise D (Algorithm 1)
-  int elem_mfma = 1;              // element kernel on the matrix cores
   int edge_kernel = EDGE_AUTO;    // EdgeKernel
-  int bern = 0;                   // stage vectors as Bernstein coefficients where the kernels allow
   int conv = 0;                   // convective term on
   double Dfield[kMaxFields] = {};
   double vel[6] = {};             // v = (p0 + p2 x + p3 y, p1 + p4 x + p5 y)
@@ -108,14 +102,10 @@ struct BatchProb {
 };
 
 // Edge fluxes of all interior and boundary edges for nfields fields.
-// bern: the stage input holds Bernstein coefficients (else nodal values).
-hipError_t launch_edge_flux(const DevMesh& m, int prec, bool bern, int nfields, const void* u, void* flux,
-                            hipStream_t st);
-// Element volume + LIFT of the fluxes + epilogue.
-// bern: the stage input holds Bernstein coefficients, and the next stage
-// input (epi.vnext) is written as Bernstein coefficients too.
-hipError_t launch_element(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
-                          const void* flux, const Epilogue& epi, hipStream_t st);
+hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux, hipStream_t st);
+// Element volume + LIFT of the fluxes + epilogue (matrix cores).
+hipError_t launch_element(const DevMesh& m, int prec, int nfields, const void* vin, const void* flux,
+                          const Epilogue& epi, hipStream_t st);
 // Batched (persistent) kernels over work items (problem, tile).  tile is the
 // number of edges / elements per item and the block size (64, 128 or 256),
 // or 0: side-split edge tiles (64 interior edges per item, items with a
@@ -136,21 +126,15 @@ hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int ni
 // launch_edge_flux).
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st);
-// Side-split tiles with the nodal -> Bernstein conversion on the matrix cores
-// (nodal stage vectors).
+// Side-split tiles with the nodal -> Bernstein conversion on the matrix cores.
 hipError_t launch_edge_split_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                                   hipStream_t st);
 // Batched element kernel on the matrix cores (64-element tiles).
 hipError_t launch_batch_element_mfma(int N, bool fp64, int grid, const BatchProb* probs, const int2* items,
                                      int nitems, const Epilogue& epi, int in_u, int write_v, hipStream_t st);
 // Element kernel on the matrix cores (same contract as launch_element).
-hipError_t launch_element_mfma(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
-                               const void* flux, const Epilogue& epi, hipStream_t st);
-
-// Bernstein coefficients of nodal data (double or float in, double or float
-// out): the first stage input when stage vectors are kept in Bernstein form.
-hipError_t launch_to_bernstein(const DevMesh& m, bool fp64_in, bool fp64_out, int nfields, const void* u,
-                               void* out, hipStream_t st);
+hipError_t launch_element_mfma(const DevMesh& m, int prec, int nfields, const void* vin, const void* flux,
+                               const Epilogue& epi, hipStream_t st);
 // Copy an FP64 state into an FP32 copy (stage input of the FP32 mode).
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // Count non-finite values of an FP64 array into *count_dev (int).

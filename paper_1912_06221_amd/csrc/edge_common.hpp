@@ -223,7 +223,7 @@ __device__ inline void matvec_sel(cptr<T> A0, const T* x, T* y) {
 // element's sub-triangle on its mirror-ghost rhombus and the boundary
 // reconstruction operator.  F receives sJ * flux, trace the element's values
 // on the face, vn the stored n.v (convection).
-template <int N, typename T, bool ALG1, bool BERN>
+template <int N, typename T, bool ALG1>
 __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ uf, T* F, T* trace, double2& vn) {
   constexpr OpLayout L(N);
@@ -239,13 +239,7 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
   const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
   T t[Np], c[Np];
   rotate_to_face<N, T>(v, fa, t, trace);
-  if (BERN) {
-#pragma unroll
-    for (int n = 0; n < Np; ++n) c[n] = t[n];
-    if (m.conv) face_bernstein_to_nodal<N, T>(op, trace);
-  } else {
-    matvec<Np, Np, T>(op + L.n2b, t, c);
-  }
+  matvec<Np, Np, T>(op + L.n2b, t, c);
   decasteljau<N, T>(c, mu);
   const T gR = (T)g.x, gS = (T)g.y;
   T gb[2 * Nfp];
@@ -256,7 +250,7 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
 
 // Boundary face e with its upwind convective flux (u+ = 0 outside), written
 // to the flux array.
-template <int N, typename T, bool ALG1, bool BERN>
+template <int N, typename T, bool ALG1>
 __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -265,7 +259,7 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   const T* uf = u + (int64_t)field * m.K * Np;
   T F[Nfp], tr[Nfp];
   double2 vn = make_double2(0.0, 0.0);
-  boundary_flux<N, T, ALG1, BERN>(m, op, e, field, uf, F, tr, vn);
+  boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr, vn);
   if (m.conv) {
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
@@ -279,10 +273,8 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   for (int j = 0; j < Nfp; ++j) out[j] = F[j];
 }
 
-// One lane per edge.  BERN: the stage input holds Bernstein coefficients
-// (the conversion to Bernstein form is skipped; rotation is the same index
-// permutation), else nodal values.
-template <int N, typename T, bool ALG1, bool BERN>
+// One lane per edge.
+template <int N, typename T, bool ALG1>
 __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                  const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -318,15 +310,7 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       for (int n = 0; n < Np; ++n) v[1][n] = uf[(int64_t)k2 * Np + n];
       rotate_to_face<N, T>(v[0], fa, t[0], tr1);
       rotate_to_face<N, T>(v[1], fb, t[1], tr2);
-      if (BERN) {
-#pragma unroll
-        for (int n = 0; n < Np; ++n) {
-          c[0][n] = t[0][n];
-          c[1][n] = t[1][n];
-        }
-      } else {
-        matvec_n<Np, Np, 2, T>(op + L.n2b, t, c);
-      }
+      matvec_n<Np, Np, 2, T>(op + L.n2b, t, c);
     } else {
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
@@ -335,17 +319,8 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
 #pragma unroll
         for (int n = 0; n < Np; ++n) v[n] = uf[kk * Np + n];
         rotate_to_face<N, T>(v, sd ? fb : fa, t, sd ? tr2 : tr1);
-        if (BERN) {
-#pragma unroll
-          for (int n = 0; n < Np; ++n) c[sd][n] = t[n];
-        } else {
-          matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c[sd]);
-        }
+        matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c[sd]);
       }
-    }
-    if (BERN && m.conv) {
-      face_bernstein_to_nodal<N, T>(op, tr1);
-      face_bernstein_to_nodal<N, T>(op, tr2);
     }
     decasteljau<N, T>(c[0], mu1);
     decasteljau<N, T>(c[1], mu2);
@@ -374,7 +349,7 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gg[j] + gS * gg[Nfp + j]);
     }
   } else {
-    boundary_flux<N, T, ALG1, BERN>(m, op, e, field, uf, F, tr1, vn);
+    boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr1, vn);
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
   }

@@ -195,11 +195,9 @@ __device__ inline void tile_begin(const DevMesh& m, int64_t k0, int field, const
   }
 }
 
-// vn_lds: the next stage input is left in sh (same positions) instead of
-// being stored, for a caller that transforms it before storing.
 template <int N, typename T, int TILE, int NT = TILE>
 __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, TILE, NT>::Q>& io,
-                                bool prefetched, bool vn_lds = false) {
+                                bool prefetched) {
   constexpr int Q = TileShape<N, TILE, NT>::Q;
   const int t = threadIdx.x;
   const int ndof = io.ndof;
@@ -239,8 +237,7 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
         if (i < ndof) {
           const double r = (double)sh[i];
           A[i] = (s == 0) ? r : io.Ap[q] + 2.0 * r;
-          const T x = (T)(io.Up[q] + c * r);
-          if (vn_lds) sh[i] = x; else if (vn) vn[i] = x;
+          if (vn) vn[i] = (T)(io.Up[q] + c * r);
         }
       }
     } else {
@@ -250,9 +247,7 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
         if (i < ndof) {
           const double un = io.Up[q] + dt / 6.0 * (io.Ap[q] + (double)sh[i]);
           U[i] = un;
-          if (vn) {
-            if (vn_lds) sh[i] = (T)un; else vn[i] = (T)un;
-          }
+          if (vn) vn[i] = (T)un;
         }
       }
     }
@@ -266,88 +261,8 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
         A[i] = res;
         const double un = io.Up[q] + epi.b * res;
         U[i] = un;
-        if (vn) {
-          if (vn_lds) sh[i] = (T)un; else vn[i] = (T)un;
-        }
+        if (vn) vn[i] = (T)un;
       }
-    }
-  }
-}
-
-// The Runge-Kutta update of tile_end in two parts, for a caller that passes
-// the next stage input through LDS (and transforms it) before storing: no
-// barrier may follow a global store without waiting for it, so tile_update
-// leaves the new state and accumulator in registers and the next stage input
-// in sh, and tile_store writes state and accumulator after the caller's last
-// barrier.
-template <int Q>
-struct TileNew {
-  double U[Q], A[Q];
-};
-
-template <int N, typename T, int TILE, int NT>
-__device__ inline void tile_update(const Epilogue& epi, T* sh, TileIO<TileShape<N, TILE, NT>::Q>& io,
-                                   bool prefetched, TileNew<TileShape<N, TILE, NT>::Q>& nw) {
-  constexpr int Q = TileShape<N, TILE, NT>::Q;
-  const int t = threadIdx.x;
-  const int ndof = io.ndof;
-  const double dt = epi.dt;
-  if (!prefetched) {
-    const double* U = epi.u + io.base;
-    const double* Asrc = io.need_acc ? epi.acc + io.base : epi.u + io.base;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int i = t + q * NT;
-      const int ic = i < ndof ? i : 0;
-      io.Up[q] = U[ic];
-      io.Ap[q] = Asrc[ic];
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (!io.need_acc) io.Ap[q] = 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int i = t + q * NT;
-    const double r = (double)sh[(i < ndof) ? i : 0];
-    double vnext;
-    if (epi.kind == EPI_RK4) {
-      const int s = epi.stage;
-      if (s < 3) {
-        nw.A[q] = (s == 0) ? r : io.Ap[q] + 2.0 * r;
-        nw.U[q] = io.Up[q];
-        vnext = io.Up[q] + ((s < 2) ? 0.5 * dt : dt) * r;
-      } else {
-        nw.A[q] = io.Ap[q];
-        nw.U[q] = io.Up[q] + dt / 6.0 * (io.Ap[q] + r);
-        vnext = nw.U[q];
-      }
-    } else {
-      const double res = (epi.stage == 0) ? dt * r : epi.a * io.Ap[q] + dt * r;
-      nw.A[q] = res;
-      nw.U[q] = io.Up[q] + epi.b * res;
-      vnext = nw.U[q];
-    }
-    if (i < ndof) sh[i] = (T)vnext;
-  }
-}
-
-template <int N, typename T, int TILE, int NT>
-__device__ inline void tile_store(const Epilogue& epi, const TileIO<TileShape<N, TILE, NT>::Q>& io,
-                                  const TileNew<TileShape<N, TILE, NT>::Q>& nw) {
-  constexpr int Q = TileShape<N, TILE, NT>::Q;
-  const int t = threadIdx.x;
-  double* U = epi.u + io.base;
-  double* A = epi.acc + io.base;
-  // RK4 stages 0-2 leave the state alone; stage 3 leaves the accumulator
-  const bool wU = epi.kind != EPI_RK4 || epi.stage == 3;
-  const bool wA = epi.kind != EPI_RK4 || epi.stage < 3;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int i = t + q * NT;
-    if (i < io.ndof) {
-      if (wU) U[i] = nw.U[q];
-      if (wA) A[i] = nw.A[q];
     }
   }
 }

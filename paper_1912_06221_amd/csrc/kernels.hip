@@ -9,8 +9,7 @@
 //      permutation;
 //   2. project onto the sub-triangle (eq. NodalToModalProjection, eq.
 //      totalProjection): nodal -> Bernstein coefficients on I (constant
-//      matrix; skipped when the stage vector already holds Bernstein
-//      coefficients), then an in-place de Casteljau subdivision at the apex's
+//      matrix), then an in-place de Casteljau subdivision at the apex's
 //      barycentric weights.  After the subdivision, lattice slot (i,j) holds
 //      the Bernstein coefficient of the sub-triangle (apex, a2, a3) with
 //      multi-index (N-i-j, i, j): the restriction of the polynomial, exactly;
@@ -24,11 +23,12 @@
 //      owns its slot).
 // edge_flux_kernel runs one lane per edge; edge_split_kernel gives each side
 // of a 64-edge tile its own wave.
-// element_kernel (one thread per element, the block's elements staged through
+// element_tile (one thread per element, the block's elements staged through
 // LDS): strong-form volume term with the element's affine factors, LIFT of
-// the face jumps, optional convective volume term, and a fused Runge-Kutta
-// update in FP64 over the block's degrees of freedom.
-// batch_* kernels: the same bodies over work items of many meshes.
+// the face jumps and a fused Runge-Kutta update in FP64 over the block's
+// degrees of freedom; one of the element tiles the batched stepping chooses
+// from (the single-mesh element kernel runs on the matrix cores).
+// batch_* kernels: the edge and element bodies over work items of many meshes.
 //
 // Constant operators are read through the constant address space with
 // compile-time offsets, so every matrix entry is a wave-uniform scalar load
@@ -44,7 +44,7 @@
 
 namespace ardg {
 
-template <int N, typename T, bool ALG1, bool BERN>
+template <int N, typename T, bool ALG1>
 __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __restrict__ u,
                                                         T* __restrict__ flux, int nf) {
   int64_t tile;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
   tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
   const int64_t e = tile * blockDim.x + threadIdx.x;
   if (e >= m.E_int + m.E_bdy) return;
-  edge_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, field, u, flux);
+  edge_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
 }
 
 // Interior edges split by side: a block of two waves takes a tile of 64
@@ -74,7 +74,7 @@ struct SplitShared {
 template <int N, typename T>
 struct SplitIn {
   static constexpr int Np = (N + 1) * (N + 2) / 2;
-  T v[Np];               // the side's element values (nodal or Bernstein)
+  T v[Np];               // the side's element values
   double2 mu, g, vn;     // apex weights of this side, (gamma_R, gamma_S) sJ, n.v sJ
   double D1, D2;         // element D of both sides (Algorithm 1)
   int f;                 // this side's face
@@ -118,7 +118,7 @@ __device__ inline void edge_split_gather(const DevMesh& m, int64_t e0, int field
 // reconstruction operator's columns of that side, contracted with the edge's
 // gamma and D one flux node at a time, and the upwind term where this side is
 // upstream -- and the two shares meet in LDS (part, Nfp x 64).
-template <int N, typename T, bool ALG1, bool BERN, bool CONV>
+template <int N, typename T, bool ALG1, bool CONV>
 __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restrict__ flux, const SplitIn<N, T>& in,
                                          T (*part)[kSplitTile]) {
   constexpr OpLayout L(N);
@@ -129,15 +129,8 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
   const int l = threadIdx.x & 63;
   T t[Np], tr[Nfp], c[Np];
   rotate_to_face<N, T>(in.v, in.f, t, tr);
-  if (BERN) {
-    // the stage input holds Bernstein coefficients: rotation only
-#pragma unroll
-    for (int n = 0; n < Np; ++n) c[n] = t[n];
-    if (CONV) face_bernstein_to_nodal<N, T>(op, tr);
-  } else {
-    // 3 rows x 4 contiguous entries per step: one 32-byte scalar load per row
-    matvec_pf<Np, Np, T, 3>(op + L.n2b, t, c);
-  }
+  // 3 rows x 4 contiguous entries per step: one 32-byte scalar load per row
+  matvec_pf<Np, Np, T, 3>(op + L.n2b, t, c);
   decasteljau<N, T>(c, in.mu);
   // Algorithm 1 reduces to D (U1 - U2) when every edge of the tile has
   // D1 == D2; both waves see the same tile and take the same branch
@@ -182,7 +175,7 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
 // operator, one lane per face): their serial chain is the longest of the
 // launch, so they start first and run beside the interior tiles.  The other
 // blocks take one tile of 64 interior edges each.
-template <int N, typename T, bool ALG1, bool BERN, bool CONV>
+template <int N, typename T, bool ALG1, bool CONV>
 __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
                                                                     T* __restrict__ flux, int nb_bdy, int nf) {
   __shared__ SplitShared<N, T> S;
@@ -191,7 +184,7 @@ __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, c
   if (b < nbt) {
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * (2 * kSplitTile) + threadIdx.x;
-    if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1, BERN>(m, opbase<T>(m), e, field, u, flux);
+    if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   // nb_bdy is a multiple of 8, so b - nbt keeps b's XCD
@@ -200,7 +193,7 @@ __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, c
   tile_and_field(b - nbt, (int64_t)gridDim.x - nbt, nf, tile, field);
   SplitIn<N, T> in;
   edge_split_gather<N, T, ALG1, CONV>(m, tile * kSplitTile, field, u, in);
-  edge_split_finish<N, T, ALG1, BERN, CONV>(m, field, flux, in, S.part);
+  edge_split_finish<N, T, ALG1, CONV>(m, field, flux, in, S.part);
 }
 
 // Batched form: persistent blocks over items of many meshes (constant D, no
@@ -219,10 +212,10 @@ __global__ __launch_bounds__(2 * kSplitTile) void batch_edge_split_kernel(const 
     if (t >= 0) {
       SplitIn<N, T> in;
       edge_split_gather<N, T, false, false>(P->m, (int64_t)t * kSplitTile, 0, vin, in);
-      edge_split_finish<N, T, false, false, false>(P->m, 0, (T*)P->flux, in, S.part);
+      edge_split_finish<N, T, false, false>(P->m, 0, (T*)P->flux, in, S.part);
     } else {
       const int64_t e = P->m.E_int + (int64_t)(-1 - t) * (2 * kSplitTile) + threadIdx.x;
-      if (e < P->m.E_int + P->m.E_bdy) boundary_body<N, T, false, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+      if (e < P->m.E_int + P->m.E_bdy) boundary_body<N, T, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
     }
     __syncthreads();
   }
@@ -371,17 +364,6 @@ __device__ inline void element_tile(const DevMesh& m, cptr<T> op, int64_t k0, in
   tile_end<N, T, TILE>(epi, sh, io, kPre);
 }
 
-template <int N, typename T, bool CONV>
-__global__ __launch_bounds__(kElemBlock) __attribute__((amdgpu_waves_per_eu(ElemTune<N>::waves)))
-void element_kernel(DevMesh m, const T* __restrict__ vin, const T* __restrict__ flux, Epilogue epi, int nf) {
-  constexpr int Np = (N + 1) * (N + 2) / 2;
-  __shared__ T sh[kElemBlock * Np];
-  int64_t tile;
-  int field;
-  tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
-  element_tile<N, T, CONV, kElemBlock>(m, opbase<T>(m), tile * kElemBlock, field, vin, flux, epi, sh);
-}
-
 // ---------------------------------------------------------------------------
 // Batching: many independent meshes.  Persistent blocks walk a list of work
 // items (problem, tile); every item reads its problem's descriptor (tables,
@@ -399,7 +381,7 @@ __global__ __launch_bounds__(TILE) void batch_edge_kernel(const BatchProb* __res
     const int64_t e = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * TILE + threadIdx.x;
     if (e < P->m.E_int + P->m.E_bdy) {
       const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
-      edge_body<N, T, false, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+      edge_body<N, T, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
     }
   }
 }
@@ -454,8 +436,8 @@ __global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* c
 // launchers
 // ---------------------------------------------------------------------------
 
-template <int N, typename T, bool BERN>
-hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
+template <int N, typename T>
+hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   const int64_t E = m.E_int + m.E_bdy;
   if (E == 0) return hipSuccess;
   bool split = m.edge_kernel == EDGE_SPLIT;
@@ -471,7 +453,7 @@ hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flu
     const int64_t nbb = ((m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile) + 7) / 8 * 8;
     dim3 grid((unsigned)((nbi + nbb) * nfields));
 #define ARDG_SPLIT_LAUNCH(A, C)                                                                  \
-  hipLaunchKernelGGL((edge_split_kernel<N, T, A, BERN, C>), grid, dim3(2 * kSplitTile), 0, st, m, \
+  hipLaunchKernelGGL((edge_split_kernel<N, T, A, C>), grid, dim3(2 * kSplitTile), 0, st, m,       \
                      (const T*)u, (T*)flux, (int)nbb, nfields)
     if (m.alg1) {
       if (m.conv) ARDG_SPLIT_LAUNCH(true, true);
@@ -485,30 +467,9 @@ hipError_t edge_launch_b(const DevMesh& m, int nfields, const void* u, void* flu
   }
   dim3 grid((unsigned)((E + 255) / 256 * nfields));
   if (m.alg1)
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, true, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux,
-                       nfields);
+    hipLaunchKernelGGL((edge_flux_kernel<N, T, true>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux, nfields);
   else
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, false, BERN>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux,
-                       nfields);
-  return hipGetLastError();
-}
-
-template <int N, typename T>
-hipError_t edge_launch_t(const DevMesh& m, bool bern, int nfields, const void* u, void* flux, hipStream_t st) {
-  return bern ? edge_launch_b<N, T, true>(m, nfields, u, flux, st)
-              : edge_launch_b<N, T, false>(m, nfields, u, flux, st);
-}
-
-template <int N, typename T>
-hipError_t elem_launch_t(const DevMesh& m, int nfields, const void* vin, const void* flux,
-                         const Epilogue& epi, hipStream_t st) {
-  dim3 grid((unsigned)((m.K + kElemBlock - 1) / kElemBlock * nfields));
-  if (m.conv)
-    hipLaunchKernelGGL((element_kernel<N, T, true>), grid, dim3(kElemBlock), 0, st, m,
-                       (const T*)vin, (const T*)flux, epi, nfields);
-  else
-    hipLaunchKernelGGL((element_kernel<N, T, false>), grid, dim3(kElemBlock), 0, st, m,
-                       (const T*)vin, (const T*)flux, epi, nfields);
+    hipLaunchKernelGGL((edge_flux_kernel<N, T, false>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux, nfields);
   return hipGetLastError();
 }
 
@@ -524,87 +485,23 @@ hipError_t elem_launch_t(const DevMesh& m, int nfields, const void* vin, const v
   }
 
 template <typename T>
-hipError_t edge_dispatch(const DevMesh& m, bool bern, int nf, const void* u, void* flux, hipStream_t st) {
-  ARDG_DISPATCH_N(edge_launch_t, m, bern, nf, u, flux, st)
+hipError_t edge_dispatch(const DevMesh& m, int nf, const void* u, void* flux, hipStream_t st) {
+  ARDG_DISPATCH_N(edge_launch_t, m, nf, u, flux, st)
 }
 
-template <typename T>
-hipError_t elem_dispatch(const DevMesh& m, int nf, const void* vin, const void* flux,
-                         const Epilogue& epi, hipStream_t st) {
-  ARDG_DISPATCH_N(elem_launch_t, m, nf, vin, flux, epi, st)
-}
-
-hipError_t launch_edge_flux(const DevMesh& m, int prec, bool bern, int nfields, const void* u, void* flux,
-                            hipStream_t st) {
-  // split-BF16 products exist only on the matrix cores (nodal stage input):
-  // side-split tiles up to N = 3, one wave per tile above (measured faster)
-  if (m.edge_kernel == EDGE_SPLIT_MFMA ||
-      (prec == PREC_BF16X3 && m.edge_kernel == EDGE_AUTO && m.N <= 3)) {
-    if (bern) return hipErrorInvalidValue;
+hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux, hipStream_t st) {
+  // split-BF16 products exist only on the matrix cores: side-split tiles up
+  // to N = 3, one wave per tile above (measured faster)
+  if (m.edge_kernel == EDGE_SPLIT_MFMA || (prec == PREC_BF16X3 && m.edge_kernel == EDGE_AUTO && m.N <= 3))
     return launch_edge_split_mfma(m, prec, nfields, u, flux, st);
-  }
-  if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) {
-    if (bern) return hipErrorInvalidValue;
-    return launch_edge_mfma(m, prec, nfields, u, flux, st);
-  }
-  return prec == PREC_FP64 ? edge_dispatch<double>(m, bern, nfields, u, flux, st)
-                           : edge_dispatch<float>(m, bern, nfields, u, flux, st);
+  if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) return launch_edge_mfma(m, prec, nfields, u, flux, st);
+  return prec == PREC_FP64 ? edge_dispatch<double>(m, nfields, u, flux, st)
+                           : edge_dispatch<float>(m, nfields, u, flux, st);
 }
 
-hipError_t launch_element(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
-                          const void* flux, const Epilogue& epi, hipStream_t st) {
-  if (m.elem_mfma || prec == PREC_BF16X3) return launch_element_mfma(m, prec, bern, nfields, vin, flux, epi, st);
-  if (bern) return hipErrorInvalidValue;   // the thread-per-element kernel takes nodal values
-  return prec == PREC_FP64 ? elem_dispatch<double>(m, nfields, vin, flux, epi, st)
-                           : elem_dispatch<float>(m, nfields, vin, flux, epi, st);
-}
-
-// nodal values -> Bernstein coefficients, one thread per element (FP64
-// arithmetic, rounded once at the store)
-template <int N, typename TI, typename TO>
-__global__ __launch_bounds__(256) void to_bernstein_kernel(DevMesh m, int64_t nel, const TI* __restrict__ u,
-                                                           TO* __restrict__ out) {
-  constexpr OpLayout L(N);
-  constexpr int Np = L.Np;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nel) return;
-  double v[Np], b[Np];
-#pragma unroll
-  for (int n = 0; n < Np; ++n) v[n] = (double)u[k * Np + n];
-  matvec<Np, Np, double>(opbase<double>(m) + L.n2b, v, b);
-#pragma unroll
-  for (int n = 0; n < Np; ++n) out[k * Np + n] = (TO)b[n];
-}
-
-template <int N, typename TI, typename TO>
-hipError_t to_bern_t(const DevMesh& m, int nfields, const void* u, void* out, hipStream_t st) {
-  const int64_t nel = (int64_t)nfields * m.K;
-  if (nel == 0) return hipSuccess;
-  hipLaunchKernelGGL((to_bernstein_kernel<N, TI, TO>), dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, st, m,
-                     nel, (const TI*)u, (TO*)out);
-  return hipGetLastError();
-}
-
-template <typename TI, typename TO>
-hipError_t to_bern_dispatch(const DevMesh& m, int nf, const void* u, void* out, hipStream_t st) {
-  switch (m.N) {
-    case 1: return to_bern_t<1, TI, TO>(m, nf, u, out, st);
-    case 2: return to_bern_t<2, TI, TO>(m, nf, u, out, st);
-    case 3: return to_bern_t<3, TI, TO>(m, nf, u, out, st);
-    case 4: return to_bern_t<4, TI, TO>(m, nf, u, out, st);
-    case 5: return to_bern_t<5, TI, TO>(m, nf, u, out, st);
-    case 6: return to_bern_t<6, TI, TO>(m, nf, u, out, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_to_bernstein(const DevMesh& m, bool fp64_in, bool fp64_out, int nfields, const void* u,
-                               void* out, hipStream_t st) {
-  if (fp64_in)
-    return fp64_out ? to_bern_dispatch<double, double>(m, nfields, u, out, st)
-                    : to_bern_dispatch<double, float>(m, nfields, u, out, st);
-  return fp64_out ? to_bern_dispatch<float, double>(m, nfields, u, out, st)
-                  : to_bern_dispatch<float, float>(m, nfields, u, out, st);
+hipError_t launch_element(const DevMesh& m, int prec, int nfields, const void* vin, const void* flux,
+                          const Epilogue& epi, hipStream_t st) {
+  return launch_element_mfma(m, prec, nfields, vin, flux, epi, st);
 }
 
 template <int N, typename T>

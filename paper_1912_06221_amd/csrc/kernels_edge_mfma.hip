@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
     // the interior tiles
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * kEdgeTile + l;
-    if (e < E) boundary_body<N, T, ALG1, false>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   int64_t tile;
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
     // boundary faces first (mirror-ghost operator, one lane per face)
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * (2 * kEdgeTile) + threadIdx.x;
-    if (e < E) boundary_body<N, T, ALG1, false>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   int64_t tile;

@@ -34,15 +34,9 @@ namespace ardg {
 constexpr int kMfmaTile = 64;     // elements per block
 constexpr int kMfmaThreads = 256; // four waves, one 16-element sub-tile each
 
-// BERN: the stage input holds Bernstein coefficients (Dr b2n and Ds b2n give
-// its nodal derivatives, b2n its nodal values where convection needs them;
-// the divergence still applies Dr and Ds to nodal quantities),
-// and the next stage input is converted to Bernstein coefficients by one
-// more product per sub-tile before it is stored.
 // LDS of one 64-element tile: the tile's stage input (then its du/dt), each
-// wave's transpose rows, and the Bernstein conversions (nodal -> Bernstein
-// for the next stage input, Bernstein -> nodal for convection) when used.
-template <int N, typename P, bool CONV, bool BERN>
+// wave's transpose rows, and (FP32 data) the operators.
+template <int N, typename P>
 struct ElemShared {
   using M = Mma<P>;
   using T = typename M::T;
@@ -55,17 +49,15 @@ struct ElemShared {
   T sqa[4][2][SQ];            // per wave: w_r, w_s, then q_x, q_y of its sub-tile, [node][column]
   // FP32 data: Dr, Ds, LIFT read once per block, fragments built from here
   T opl[sizeof(T) == 4 ? 2 * Np * Np + Np * 3 * (N + 1) : 1];
-  T n2b_s[BERN ? Np * Np : 1];
-  T b2n_s[(BERN && CONV) ? Np * Np : 1];
 };
 
 // One 64-element tile starting at element k0 of field `field`; all 256
 // threads of the block take part (wave w: sub-tile w).
-template <int N, typename P, bool CONV, bool BERN>
+template <int N, typename P, bool CONV>
 __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field,
                                          const typename Mma<P>::T* __restrict__ vin,
                                          const typename Mma<P>::T* __restrict__ flux, const Epilogue& epi,
-                                         ElemShared<N, P, CONV, BERN>& S) {
+                                         ElemShared<N, P>& S) {
   using M = Mma<P>;
   using T = typename M::T;
   typedef typename M::acc acc_t;
@@ -78,11 +70,9 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
   constexpr int NJ = 3 * Nfp;            // face values lifted
   constexpr int KL = (NJ + KS - 1) / KS; // K steps over face values
   constexpr int RW = 16 * MT;            // padded node rows
-  constexpr int SQ = ElemShared<N, P, CONV, BERN>::SQ;
+  constexpr int SQ = ElemShared<N, P>::SQ;
   constexpr bool kPre = N <= 4;
   T* sh = S.sh;
-  T* n2b_s = S.n2b_s;
-  T* b2n_s = S.b2n_s;
   const int l = threadIdx.x & 63, col = l & 15, grp = l >> 4;
   const int st = threadIdx.x >> 6;       // this wave's sub-tile
   T (*sq)[SQ] = S.sqa[st];
@@ -99,12 +89,6 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
 #pragma unroll
   for (int f = 0; f < 3; ++f) code[f] = m.elem_face[f * m.K + k];
 
-  if (BERN) {
-    for (int i = threadIdx.x; i < Np * Np; i += kMfmaThreads) {
-      n2b_s[i] = opg[L.n2b + i];
-      if (CONV) b2n_s[(BERN && CONV) ? i : 0] = opg[L.b2n + i];
-    }
-  }
   // FP32 data: Dr and Ds (adjacent in the operator buffer) and LIFT into LDS
   // with coalesced loads, and each wave builds its fragments from there after
   // the barrier instead of gathering them from the cache once per lane
@@ -137,11 +121,8 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       G[c][t] = sgn * x;
     }
 
-  // operator fragments: row 16 mt + col, columns kidx(c, grp, .).  Dr and Ds
-  // act on nodal quantities (the divergence); with Bernstein input the first
-  // product takes Dr b2n and Ds b2n instead
+  // operator fragments: row 16 mt + col, columns kidx(c, grp, .)
   frag_t aDr[MT][KC], aDs[MT][KC], aL[MT][KL];
-  frag_t aDrb[BERN ? MT : 1][BERN ? KC : 1], aDsb[BERN ? MT : 1][BERN ? KC : 1];
   auto build_frags = [&](const T* odr, const T* ods, const T* olift) {
   #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -158,17 +139,6 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
         }
         aDr[mt][c] = M::make(vr);
         aDs[mt][c] = M::make(vs);
-        if (BERN) {
-  #pragma unroll
-          for (int t = 0; t < KPL; ++t) {
-            const int kk = kidx<M>(c, grp, t);
-            const bool ok = row < Np && kk < Np;
-            vr[t] = ok ? opg[L.drb + row * Np + kk] : T(0);
-            vs[t] = ok ? opg[L.dsb + row * Np + kk] : T(0);
-          }
-          aDrb[BERN ? mt : 0][BERN ? c : 0] = M::make(vr);
-          aDsb[BERN ? mt : 0][BERN ? c : 0] = M::make(vs);
-        }
       }
   #pragma unroll
       for (int c = 0; c < KL; ++c) {
@@ -236,40 +206,9 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
     us[mt] = M::zero();
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      if (BERN) {
-        ur[mt] = M::mma(aDrb[BERN ? mt : 0][BERN ? c : 0], bu[c], ur[mt]);
-        us[mt] = M::mma(aDsb[BERN ? mt : 0][BERN ? c : 0], bu[c], us[mt]);
-      } else {
-        ur[mt] = M::mma(aDr[mt][c], bu[c], ur[mt]);
-        us[mt] = M::mma(aDs[mt][c], bu[c], us[mt]);
-      }
+      ur[mt] = M::mma(aDr[mt][c], bu[c], ur[mt]);
+      us[mt] = M::mma(aDs[mt][c], bu[c], us[mt]);
     }
-  }
-  // nodal values (convection with Bernstein input): b2n u, kept in sh for the
-  // face terms (each wave rewrites only its own sub-tile's elements)
-  acc_t un_b[MT];
-  if (CONV && BERN) {
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      un_b[mt] = M::zero();
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        T vb[KPL];
-#pragma unroll
-        for (int t = 0; t < KPL; ++t) {
-          const int row = 16 * mt + col, kk = kidx<M>(c, grp, t);
-          vb[t] = (row < Np && kk < Np) ? b2n_s[(BERN && CONV) ? row * Np + kk : 0] : T(0);
-        }
-        un_b[mt] = M::mma(M::make(vb), bu[c], un_b[mt]);
-      }
-    }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int node = 16 * mt + M::row(grp, r);
-        if (valid && node < Np) sh[el * Np + node] = un_b[mt][r];
-      }
   }
   // accumulator layout: node 16 mt + M::row(grp, r) of element `col`.  w_r and
   // w_s go through LDS to become B fragments; q stays in registers until the
@@ -289,8 +228,7 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       if (CONV) {
         const T vx = (T)ev.x1 + r1a[mt][r] * (T)ev.xr + s1a[mt][r] * (T)ev.xs;
         const T vy = (T)ev.y1 + r1a[mt][r] * (T)ev.yr + s1a[mt][r] * (T)ev.ys;
-        const T un = BERN ? un_b[mt][r]
-                          : ((valid && node < Np) ? sh[el * Np + (node < Np ? node : 0)] : T(0));
+        const T un = (valid && node < Np) ? sh[el * Np + (node < Np ? node : 0)] : T(0);
         wr -= (rx * vx + ry * vy) * un;
         ws -= (sx * vx + sy * vy) * un;
       }
@@ -380,71 +318,19 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       if (valid && node < Np) sh[el * Np + node] = rhs[mt][r];
     }
   __syncthreads();
-  const bool v_bern = BERN && epi.kind != EPI_RHS && epi.vnext != nullptr;
-  if (!v_bern) {
-    tile_end<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre);
-  } else {
-    // next stage input: nodal values in sh -> Bernstein coefficients; state
-    // and accumulator are stored after the last barrier
-    TileNew<TileShape<N, kMfmaTile, kMfmaThreads>::Q> nw;
-    tile_update<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre, nw);
-    __syncthreads();
-    frag_t bv[KC];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      T v[KPL];
-#pragma unroll
-      for (int t = 0; t < KPL; ++t) {
-        const int n = kidx<M>(c, grp, t);
-        v[t] = (valid && n < Np) ? sh[el * Np + n] : T(0);
-      }
-      bv[c] = M::make(v);
-    }
-    acc_t cb[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      cb[mt] = M::zero();
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        T va[KPL];
-#pragma unroll
-        for (int t = 0; t < KPL; ++t) {
-          const int row = 16 * mt + col, kk = kidx<M>(c, grp, t);
-          va[t] = (row < Np && kk < Np) ? n2b_s[BERN ? row * Np + kk : 0] : T(0);
-        }
-        cb[mt] = M::mma(M::make(va), bv[c], cb[mt]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int node = 16 * mt + M::row(grp, r);
-        if (valid && node < Np) sh[el * Np + node] = cb[mt][r];
-      }
-    __syncthreads();
-    T* vo = (T*)epi.vnext + io.base;
-    constexpr int Q = TileShape<N, kMfmaTile, kMfmaThreads>::Q;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int i = threadIdx.x + q * kMfmaThreads;
-      if (i < io.ndof) vo[i] = sh[i];
-    }
-    tile_store<N, T, kMfmaTile, kMfmaThreads>(epi, io, nw);
-  }
+  tile_end<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre);
 }
 
-template <int N, typename P, bool CONV, bool BERN>
+template <int N, typename P, bool CONV>
 __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
                                                                     const typename Mma<P>::T* __restrict__ vin,
                                                                     const typename Mma<P>::T* __restrict__ flux,
                                                                     Epilogue epi, int nf) {
-  __shared__ ElemShared<N, P, CONV, BERN> S;
+  __shared__ ElemShared<N, P> S;
   int64_t tile;
   int field;
   tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
-  element_mfma_tile<N, P, CONV, BERN>(m, tile * kMfmaTile, field, vin, flux, epi, S);
+  element_mfma_tile<N, P, CONV>(m, tile * kMfmaTile, field, vin, flux, epi, S);
 }
 
 // Batched form: persistent blocks over (problem, 64-element tile) items of
@@ -455,7 +341,7 @@ __global__ __launch_bounds__(kMfmaThreads) void batch_element_mfma_kernel(const 
                                                                           const int2* __restrict__ items,
                                                                           int nitems, Epilogue epi0, int in_u,
                                                                           int write_v) {
-  __shared__ ElemShared<N, T, false, false> S;
+  __shared__ ElemShared<N, T> S;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
     const BatchProb* Pb = probs + __builtin_amdgcn_readfirstlane(w.x);
@@ -466,7 +352,7 @@ __global__ __launch_bounds__(kMfmaThreads) void batch_element_mfma_kernel(const 
     epi.dt = Pb->dt;
     const T* vin = in_u ? (const T*)(const void*)Pb->u : (const T*)Pb->v;
     const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * kMfmaTile;
-    element_mfma_tile<N, T, false, false>(Pb->m, k0, 0, vin, (const T*)Pb->flux, epi, S);
+    element_mfma_tile<N, T, false>(Pb->m, k0, 0, vin, (const T*)Pb->flux, epi, S);
     __syncthreads();
   }
 }
@@ -493,47 +379,40 @@ hipError_t launch_batch_element_mfma(int N, bool fp64, int grid, const BatchProb
 #undef ARDG_BEM
 }
 
-template <int N, typename P, bool BERN>
+template <int N, typename P>
 hipError_t elem_mfma_t(const DevMesh& m, int nfields, const void* vin, const void* flux,
                        const Epilogue& epi, hipStream_t st) {
   using T = typename Mma<P>::T;
   dim3 grid((unsigned)((m.K + kMfmaTile - 1) / kMfmaTile * nfields));
   if (m.conv)
-    hipLaunchKernelGGL((element_mfma_kernel<N, P, true, BERN>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, true>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi, nfields);
   else
-    hipLaunchKernelGGL((element_mfma_kernel<N, P, false, BERN>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, false>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi, nfields);
   return hipGetLastError();
 }
 
-template <typename P, bool BERN>
+template <typename P>
 hipError_t elem_mfma_dispatch(const DevMesh& m, int nf, const void* vin, const void* flux,
                               const Epilogue& epi, hipStream_t st) {
   switch (m.N) {
-    case 1: return elem_mfma_t<1, P, BERN>(m, nf, vin, flux, epi, st);
-    case 2: return elem_mfma_t<2, P, BERN>(m, nf, vin, flux, epi, st);
-    case 3: return elem_mfma_t<3, P, BERN>(m, nf, vin, flux, epi, st);
-    case 4: return elem_mfma_t<4, P, BERN>(m, nf, vin, flux, epi, st);
-    case 5: return elem_mfma_t<5, P, BERN>(m, nf, vin, flux, epi, st);
-    case 6: return elem_mfma_t<6, P, BERN>(m, nf, vin, flux, epi, st);
+    case 1: return elem_mfma_t<1, P>(m, nf, vin, flux, epi, st);
+    case 2: return elem_mfma_t<2, P>(m, nf, vin, flux, epi, st);
+    case 3: return elem_mfma_t<3, P>(m, nf, vin, flux, epi, st);
+    case 4: return elem_mfma_t<4, P>(m, nf, vin, flux, epi, st);
+    case 5: return elem_mfma_t<5, P>(m, nf, vin, flux, epi, st);
+    case 6: return elem_mfma_t<6, P>(m, nf, vin, flux, epi, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_element_mfma(const DevMesh& m, int prec, bool bern, int nfields, const void* vin,
-                               const void* flux, const Epilogue& epi, hipStream_t st) {
+hipError_t launch_element_mfma(const DevMesh& m, int prec, int nfields, const void* vin, const void* flux,
+                               const Epilogue& epi, hipStream_t st) {
   switch (prec) {
-    case PREC_FP64:
-      return bern ? elem_mfma_dispatch<double, true>(m, nfields, vin, flux, epi, st)
-                  : elem_mfma_dispatch<double, false>(m, nfields, vin, flux, epi, st);
-    case PREC_FP32:
-      return bern ? elem_mfma_dispatch<float, true>(m, nfields, vin, flux, epi, st)
-                  : elem_mfma_dispatch<float, false>(m, nfields, vin, flux, epi, st);
-    case PREC_BF16X3:
-      // split-BF16 stages keep nodal stage vectors
-      if (bern) return hipErrorInvalidValue;
-      return elem_mfma_dispatch<Bf16x3, false>(m, nfields, vin, flux, epi, st);
+    case PREC_FP64: return elem_mfma_dispatch<double>(m, nfields, vin, flux, epi, st);
+    case PREC_FP32: return elem_mfma_dispatch<float>(m, nfields, vin, flux, epi, st);
+    case PREC_BF16X3: return elem_mfma_dispatch<Bf16x3>(m, nfields, vin, flux, epi, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 2e-4
+TOLBF = 5e-2
 
 
 def _setup(name):
@@ -66,7 +67,8 @@ def test_fullsize_rhs_sampled(name):
     ur = W.random_nodal(u0.shape, seed=9)
     for data, label in ((u0, "smooth"), (ur, "random")):
         ud = to_dev(data)
-        for prec, dt, tol in ((ardg.FP64, torch.float64, TOL64), (ardg.FP32, torch.float32, TOL32)):
+        for prec, dt, tol in ((ardg.FP64, torch.float64, TOL64), (ardg.FP32, torch.float32, TOL32),
+                              (ardg.BF16X3, torch.float32, TOLBF)):
             x = ud.to(dt)
             out = torch.empty_like(x)
             lm.rhs_eval(x, out, precision=prec, nfields=nf)

@@ -146,21 +146,18 @@ def test_empty_and_tiny_meshes():
             assert np.abs(to_np(rhs) - ro).max() <= TOL64 * np.abs(ro).max()
 
 
-@pytest.mark.parametrize("form", ["nodal", "bernstein"])
+@pytest.mark.parametrize("N", [2, 3])
 @pytest.mark.parametrize("scheme", ["rk4", "lserk"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_time_stepping_heat_8x8(scheme, prec, form, monkeypatch):
-    """The plain heat problem: 8x8x2 unjittered, N=3, D=1,
-    u0 = sin(pi x) sin(pi y), 100 steps; state parity with the oracle and the
-    error against the exact solution.  form: the stage vectors hold nodal
-    values or Bernstein coefficients (BF16X3 always steps nodal vectors)."""
+def test_time_stepping_heat_8x8(scheme, prec, N):
+    """The plain heat problem: 8x8x2 unjittered, D=1, u0 = sin(pi x) sin(pi y),
+    100 steps (N = 2 is the plain-method workload as configured); state parity
+    with the oracle and the error against the exact solution."""
     import torch
     from oracle.rhs import lserk_step, mass_norm, rk4_step
     from paper_1912_06221_amd import ardg
-    print(f"heat 8x8 {scheme} {prec} {form}", flush=True)
-    monkeypatch.setenv("ARDG_STAGE_FORM", form)
+    print(f"heat 8x8 N={N} {scheme} {prec}", flush=True)
     mesh = W.split_square_mesh(8, 0.0)
-    N = 3
     ops, lm = library_mesh(mesh, N, "const", 1.0, None, 1)
     pr = oracle_problem(mesh, N, "const", 1.0, None, 1)
     xy = pr.nodal_xy()
@@ -268,13 +265,12 @@ def _blocks_D(mesh):
 @pytest.mark.parametrize("case", VARIANT_CASES,
                          ids=lambda c: f"m{c[0]}-N{c[1]}-{c[2]}-{'conv' if c[3] else 'diff'}")
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
-    """The kernel variants -- default (edge kernel chosen by grid size,
-    matrix-core element kernel, nodal stage vectors), the same with
-    Bernstein-form stage vectors, edge tiles split by side (conversion on the
-    vector unit or on the matrix cores), one thread per edge with Bernstein
-    input, one thread per edge / per element, all matrix-core -- compute the
-    same flux and RHS (to rounding), each matching the oracle."""
+def test_matrix_core_and_vector_kernels_agree(case, prec):
+    """The edge kernel implementations (ardg_mesh_set_kernels) -- chosen by
+    grid size, edge tiles split by side (conversion on the vector unit or on
+    the matrix cores), one thread per edge, one wave per tile on the matrix
+    cores -- compute the same flux and RHS (to rounding), each matching the
+    oracle."""
     import torch
     from paper_1912_06221_amd import ardg
     m, N, dk, vel = case
@@ -287,18 +283,11 @@ def test_matrix_core_and_vector_kernels_agree(case, prec, monkeypatch):
     p = ardg.FP64 if prec == "fp64" else ardg.FP32
     tol = TOL64 if prec == "fp64" else TOL32
     outs = {}
-    variants = {"default": (None, None, None), "bernstein-stages": (None, None, "bernstein"),
-                "split": ("split", None, None), "split-mfma": ("split-mfma", None, None),
-                "lane-bernstein": ("lane", None, "bernstein"),
-                "lane": ("lane", "valu", None), "mfma": ("mfma", "mfma", None)}
-    for variant, (edge_k, elem_k, form) in variants.items():
-        for var, val in (("ARDG_EDGE_KERNEL", edge_k), ("ARDG_ELEMENT_KERNEL", elem_k),
-                         ("ARDG_STAGE_FORM", form)):
-            if val is None:
-                monkeypatch.delenv(var, raising=False)
-            else:
-                monkeypatch.setenv(var, val)
+    variants = {"default": ardg.EDGE_AUTO, "split": ardg.EDGE_SPLIT, "split-mfma": ardg.EDGE_SPLIT_MFMA,
+                "lane": ardg.EDGE_LANE, "mfma": ardg.EDGE_MFMA}
+    for variant, kern in variants.items():
         ops, lm = library_mesh(mesh, N, D_mode, D, vel, 1)
+        lm.set_kernels(kern)
         u = W.random_nodal((1, mesh.K, ops.Np), seed=7 * N + m)
         ud = to_dev(u, dt)
         flux = torch.empty((1, lm.E, ops.Nfp), dtype=dt, device=ud.device)
