@@ -183,6 +183,19 @@ ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* p
 ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
                           void* rhs_dev, double t, void* hip_stream);
 
+/* ardg_rhs_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, but the edge fluxes go to a library-owned
+ * 64 MiB device array (one per GPU, held until the process ends) instead of
+ * a buffer allocated on first use, and the call makes no allocation.  The
+ * fluxes need nfields * (E_int + E_bdy) * Nfp * (8 in FP64, 4 otherwise)
+ * bytes; larger requests fail with E_INVALID_ARG.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (different
+ * streams or threads) race; calls on one stream are ordered.  Errors as
+ * ardg_rhs_eval. */
+ardg_status ardg_rhs_eval_noalloc(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
+                                  void* rhs_dev, double t, void* hip_stream);
+
 /* Edge fluxes only (the interior and boundary loop of Algorithm aRDG with the
  * diagonal flux; Algorithm 1 for element-wise D): flux_dev [F][E][Nfp] in the
  * precision's type, D included, each edge's values multiplied by its surface

@@ -56,6 +56,7 @@ SIGNATURES = {
     "ardg_mesh_set_velocity": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "ardg_mesh_set_kernels": (c_int32, [c_void_p, c_int32]),
     "ardg_rhs_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
+    "ardg_rhs_eval_noalloc": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
     "ardg_edge_flux_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "ardg_rk_workspace_bytes": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_int64)]),
     "ardg_rk_step": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
@@ -198,6 +199,13 @@ class Mesh:
     def rhs_eval(self, u, out, precision: int = FP64, nfields: int = 1, stream=None):
         _check(lib().ardg_rhs_eval(self.handle, precision, nfields, _ptr(u), _ptr(out), 0.0,
                                    _stream(stream)))
+        return out
+
+    def rhs_eval_noalloc(self, u, out, precision: int = FP64, nfields: int = 1, stream=None):
+        """rhs_eval with the fluxes in the library's device scratch array (no
+        allocation)."""
+        _check(lib().ardg_rhs_eval_noalloc(self.handle, precision, nfields, _ptr(u), _ptr(out), 0.0,
+                                           _stream(stream)))
         return out
 
     def edge_flux_eval(self, u, flux, precision: int = FP64, nfields: int = 1, stream=None):

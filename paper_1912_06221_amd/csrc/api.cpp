@@ -19,6 +19,7 @@
 #include "../../include/ardg.h"
 #include "device.hpp"
 #include "meshsetup.hpp"
+#include "noalloc.hpp"
 #include "refops.hpp"
 
 using namespace ardg;
@@ -534,6 +535,31 @@ ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, co
   if (s != ARDG_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   void* flux = mesh->flux_scratch;
+  HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux, st), "edge flux launch");
+  Epilogue epi;
+  epi.kind = EPI_RHS;
+  epi.rhs_out = rhs_dev;
+  HIP_TRY(launch_element(mesh->dm, precision, nfields, u_dev, flux, epi, st), "element launch");
+  return ARDG_OK;
+}
+
+ardg_status ardg_rhs_eval_noalloc(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
+                                  void* rhs_dev, double t, void* hip_stream) {
+  (void)t;
+  ardg_status s = check_compute(mesh, precision, nfields);
+  if (s != ARDG_OK) return s;
+  if (!u_dev || !rhs_dev) return fail(ARDG_E_INVALID_ARG, "rhs_eval_noalloc: null buffer");
+  const size_t ts = precision == ARDG_FP64 ? 8 : 4;
+  const size_t fb = (size_t)nfields * (mesh->hm.E_int + mesh->hm.E_bdy) * mesh->ro.Nfp * ts;
+  if (fb > kNoallocScratchBytes)
+    return fail(ARDG_E_INVALID_ARG, "rhs_eval_noalloc: the edge fluxes need " + std::to_string(fb) +
+                                        " bytes, more than the " + std::to_string(kNoallocScratchBytes) +
+                                        "-byte scratch array");
+  DeviceGuard g(mesh->device);
+  if (!g.ok) return fail(ARDG_E_HIP, "rhs_eval_noalloc: hipSetDevice failed");
+  void* flux = nullptr;
+  HIP_TRY(noalloc_scratch(mesh->device, &flux), "rhs_eval_noalloc: scratch address");
+  hipStream_t st = (hipStream_t)hip_stream;
   HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux, st), "edge flux launch");
   Epilogue epi;
   epi.kind = EPI_RHS;
