@@ -277,7 +277,8 @@ def mode_errors(case, states, u0):
     moved from the initial data."""
     u64 = states["fp64"]
     inc = float(np.linalg.norm(u64 - u0))
-    out = {"fp64_evolution_rel_l2": inc / float(np.linalg.norm(u0))}
+    out = {"fp64_evolution_rel_l2": inc / float(np.linalg.norm(u0)),
+           "fp64_norm_growth": float(np.linalg.norm(u64) / np.linalg.norm(u0))}
     for mode, u in states.items():
         if mode == "fp64":
             continue
@@ -312,6 +313,7 @@ def measure_case(case, args, dev, modes, error_steps):
         err = mode_errors(case, states, case.u0)
         err["steps"] = error_steps
         err["dt"] = dt
+        case.dt_stable = dt
         for m in modes:
             err.setdefault(m, {})
             err[m]["rhs_err_vs_oracle_sampled"] = case.rhs_vs_oracle(prec_of[m], dev)
@@ -319,6 +321,41 @@ def measure_case(case, args, dev, modes, error_steps):
         log(f"bench: {case.name} errors after {error_steps} steps: "
             + ", ".join(f"{m} {err[m].get('rel_l2_vs_fp64_increment', 0.0) or 0.0:.2e}" for m in modes))
     return res
+
+
+def alg2_compare(case, args, dev):
+    """Algorithm 2 (reconstructed coefficient times the reconstructed
+    gradient) beside Algorithm 1 on an element-wise-D workload: FP64 step
+    time, the smallest reconstructed coefficient on the diagonals relative to
+    the smallest element D, and the L2 difference of the two after the
+    workload's steps."""
+    from paper_1912_06221_amd import ardg
+    w = case.ops.export(ardg.OPS_ALG2_W).reshape(2, case.Nfp)
+    edges = case.lm.export(ardg.MESH_EDGES).reshape(-1, 4)
+    D = np.asarray(case.D)
+    Dt = D[edges[:, 0], None] * w[0][None, :] + D[edges[:, 2], None] * w[1][None, :]
+    steps = case.spec["steps"]
+    dt = getattr(case, "dt_stable", case.dt)
+    u1 = case.run_steps(ardg.FP64, steps, dev, dt)
+    case.lm.set_diffusion_element(D, alg=2)
+    try:
+        ms, te, tl = case.time_mode(ardg.FP64, args.steps, args.warmup, dev)
+        u2 = case.run_steps(ardg.FP64, steps, dev, dt)
+    finally:
+        case.lm.set_diffusion_element(D, alg=1)
+    out = {"fp64_ms_per_step": ms, "value": case.dof * 4 / (ms * 1e-3), "edge_us": te * 1e3,
+           "element_us": tl * 1e3, "min_Dtilde": float(Dt.min()),
+           "min_Dtilde_over_min_D": float(Dt.min() / D.min()), "steps": steps, "dt": dt}
+    if u1 is not None and u2 is not None:
+        n0 = float(np.linalg.norm(case.u0))
+        out["alg1_norm_growth"] = float(np.linalg.norm(u1)) / n0
+        out["alg2_norm_growth"] = float(np.linalg.norm(u2)) / n0
+        out["rel_l2_alg2_vs_alg1_state"] = float(np.linalg.norm(u2 - u1) / np.linalg.norm(u1))
+        inc = float(np.linalg.norm(u1 - case.u0))
+        out["rel_l2_alg2_vs_alg1_increment"] = float(np.linalg.norm(u2 - u1)) / inc if inc > 0 else None
+    log(f"bench: {case.name} Algorithm 2: {ms:.3f} ms/step, min D~ {out['min_Dtilde']:.3e}, "
+        f"alg2 vs alg1 increment {out.get('rel_l2_alg2_vs_alg1_increment')}")
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -570,6 +607,8 @@ def main():
         steps = c.spec["steps"] if (not args.no_errors and name.startswith("loguniform")) else 0
         r = measure_case(c, args, dev, modes, steps)
         r["config"] = c.config()
+        if c.alg1 and not args.no_errors:
+            r["algorithm2"] = alg2_compare(c, args, dev)
         for m in modes:
             if m != "fp64":
                 r[m]["speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r[m]["ms_per_step"]

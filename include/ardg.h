@@ -61,7 +61,7 @@ enum {
 
 enum { ARDG_FP64 = 0, ARDG_FP32 = 1, ARDG_BF16X3 = 2 };
 enum { ARDG_RK4 = 0, ARDG_LSERK54 = 1 };
-enum { ARDG_D_CONST = 0, ARDG_D_ELEMENT = 1 };
+enum { ARDG_D_CONST = 0, ARDG_D_ELEMENT = 1, ARDG_D_ELEMENT_ALG2 = 2 };
 enum { ARDG_VEL_NONE = 0, ARDG_VEL_AFFINE = 1 };
 /* Edge kernel implementations (ardg_mesh_set_kernels). */
 enum {
@@ -89,7 +89,10 @@ enum {
   ARDG_OPS_ALG1_GRAD = 11,   /* [4Nfp][2Np] Algorithm 1 blocks U1R, U1S, U2R, U2S on the same
                                 nodal sub-triangle data (flux = D1 (gR U1R + gS U1S)
                                 - D2 (gR U2R + gS U2S))                                    */
-  ARDG_OPS_N2B = 12          /* [Np][Np] nodal values -> Bernstein coefficients on I       */
+  ARDG_OPS_N2B = 12,         /* [Np][Np] nodal values -> Bernstein coefficients on I       */
+  ARDG_OPS_ALG2_W = 13       /* [2][Nfp] Algorithm 2: reconstruction at the diagonal nodes of
+                                a coefficient equal to 1 on side 1 / side 2 and 0 on the
+                                other (D~ = D1 w1 + D2 w2 for element-wise constant D)      */
 };
 
 /* ardg_mesh_export selectors. */
@@ -153,7 +156,13 @@ void ardg_mesh_destroy(ardg_mesh mesh);
  * NDG_diffusion_once_matrixForm_reference_general with Algorithm 1).
  * mode ARDG_D_CONST: D[nfields] host doubles, one constant per field.
  * mode ARDG_D_ELEMENT: D[K] host doubles (nfields must be 1); the flux is then
- * Algorithm 1's reconstruction of D grad u~.  All values must be finite > 0. */
+ * Algorithm 1's reconstruction of D grad u~.
+ * mode ARDG_D_ELEMENT_ALG2: D[K] as for ARDG_D_ELEMENT, with the flux of the
+ * alternative form (eq. NDG_diffusion_once_matrixForm_reference_general_
+ * alternative, Algorithm nonconstDiff2): the reconstructed coefficient
+ * D~ = RDG(D^1, D^2) at the diagonal nodes times n . grad u~; at boundary
+ * faces the mirror ghost carries the element's own D.
+ * All values must be finite > 0. */
 ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfields,
                                     const double* D);
 

@@ -18,13 +18,13 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libardg.so"
 OK = 0
 FP64, FP32, BF16X3 = 0, 1, 2
 RK4, LSERK54 = 0, 1
-D_CONST, D_ELEMENT = 0, 1
+D_CONST, D_ELEMENT, D_ELEMENT_ALG2 = 0, 1, 2
 VEL_NONE, VEL_AFFINE = 0, 1
 EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA = 0, 1, 2, 3, 4
 
 OPS_NODES, OPS_V, OPS_DR, OPS_DS, OPS_MASS, OPS_LIFT = 0, 1, 2, 3, 4, 5
 OPS_FACE_NODES, OPS_ROT_PERM, OPS_RECON_A, OPS_RECON_R = 6, 7, 8, 9
-OPS_RECON_GRAD, OPS_ALG1_GRAD, OPS_N2B = 10, 11, 12
+OPS_RECON_GRAD, OPS_ALG1_GRAD, OPS_N2B, OPS_ALG2_W = 10, 11, 12, 13
 MESH_EDGES, MESH_BFACES, MESH_EDGE_GEOM, MESH_BFACE_GEOM, MESH_ELEM_FACES = 0, 1, 2, 3, 4
 
 
@@ -181,9 +181,12 @@ class Mesh:
         D = np.ascontiguousarray(np.atleast_1d(D), dtype=np.float64)
         _check(lib().ardg_mesh_set_diffusion(self.handle, D_CONST, D.size, _dptr(D)))
 
-    def set_diffusion_element(self, D):
+    def set_diffusion_element(self, D, alg: int = 1):
+        """Element-wise D with the flux of Algorithm 1 (alg=1) or Algorithm 2
+        (alg=2)."""
         D = np.ascontiguousarray(D, dtype=np.float64)
-        _check(lib().ardg_mesh_set_diffusion(self.handle, D_ELEMENT, 1, _dptr(D)))
+        mode = {1: D_ELEMENT, 2: D_ELEMENT_ALG2}[alg]
+        _check(lib().ardg_mesh_set_diffusion(self.handle, mode, 1, _dptr(D)))
 
     def set_velocity(self, params=None):
         if params is None:

@@ -85,6 +85,10 @@ void pack_into(const RefOps& o, std::vector<double>& out) {
   // 1D Bernstein basis of degree N at the face's LGL nodes, tau = (x + 1)/2
   // measured from the face's first (counter-clockwise) vertex
   for (int j = 0; j < o.Nfp; ++j) {
+    out[L.w1 + j] = o.alg2_w1[j];
+    out[L.w2 + j] = o.alg2_w2[j];
+  }
+  for (int j = 0; j < o.Nfp; ++j) {
     const double tau = 0.5 * (o.lgl[j] + 1.0);
     for (int k = 0; k <= o.N; ++k) {
       double binom = 1.0;
@@ -236,6 +240,10 @@ ardg_status ardg_ops_export(ardg_ops ops, int32_t which, double* dst, int64_t ca
     case ARDG_OPS_RECON_GRAD: mat(o.recon_grad_nodal); break;
     case ARDG_OPS_ALG1_GRAD: mat(o.alg1_nodal); break;
     case ARDG_OPS_N2B: mat(o.N2B); break;
+    case ARDG_OPS_ALG2_W:
+      v = o.alg2_w1;
+      v.insert(v.end(), o.alg2_w2.begin(), o.alg2_w2.end());
+      break;
     default: return fail(ARDG_E_INVALID_ARG, "ops_export: unknown selector");
   }
   if (n_written) *n_written = (int64_t)v.size();
@@ -410,9 +418,9 @@ ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfield
     for (int f = 0; f < nfields; ++f)
       if (!(std::isfinite(D[f]) && D[f] > 0)) return fail(ARDG_E_INVALID_ARG, "set_diffusion: D must be finite > 0");
     for (int f = 0; f < kMaxFields; ++f) mesh->dm.Dfield[f] = D[std::min(f, nfields - 1)];
-    mesh->dm.alg1 = 0;
+    mesh->dm.dmode = DM_CONST;
     mesh->nfields_D = nfields;
-  } else if (mode == ARDG_D_ELEMENT) {
+  } else if (mode == ARDG_D_ELEMENT || mode == ARDG_D_ELEMENT_ALG2) {
     if (nfields != 1) return fail(ARDG_E_INVALID_ARG, "set_diffusion: element-wise D needs nfields == 1");
     const int64_t K = mesh->hm.K;
     for (int64_t k = 0; k < K; ++k)
@@ -424,7 +432,7 @@ ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfield
       if (s != ARDG_OK) return s;
       mesh->dm.Delem = mesh->Delem_dev;
     }
-    mesh->dm.alg1 = 1;
+    mesh->dm.dmode = mode == ARDG_D_ELEMENT ? DM_ALG1 : DM_ALG2;
     mesh->nfields_D = 1;
   } else {
     return fail(ARDG_E_INVALID_ARG, "set_diffusion: unknown mode");
@@ -483,8 +491,8 @@ static ardg_status check_compute(ardg_mesh mesh, int32_t precision, int32_t nfie
   if (precision != ARDG_FP64 && precision != ARDG_FP32 && precision != ARDG_BF16X3)
     return fail(ARDG_E_UNSUPPORTED, "unknown precision");
   if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "nfields out of range");
-  if (mesh->dm.alg1 && nfields != 1) return fail(ARDG_E_INVALID_ARG, "element-wise D is for one field");
-  if (!mesh->dm.alg1 && nfields > mesh->nfields_D && mesh->nfields_D != 1)
+  if (mesh->dm.dmode != DM_CONST && nfields != 1) return fail(ARDG_E_INVALID_ARG, "element-wise D is for one field");
+  if (mesh->dm.dmode == DM_CONST && nfields > mesh->nfields_D && mesh->nfields_D != 1)
     return fail(ARDG_E_INVALID_ARG, "more fields than diffusion coefficients");
   return ARDG_OK;
 }
@@ -1154,7 +1162,7 @@ ardg_status ardg_batch_create(const ardg_mesh* meshes, int32_t n, const char* tu
     if (!m) return fail(ARDG_E_INVALID_ARG, "batch_create: null mesh");
     if (m->device < 0 || m->device != dev)
       return fail(ARDG_E_INVALID_ARG, "batch_create: meshes must live on one device");
-    if (m->dm.alg1 || m->dm.conv || m->nfields_D != 1)
+    if (m->dm.dmode != DM_CONST || m->dm.conv || m->nfields_D != 1)
       return fail(ARDG_E_UNSUPPORTED, "batch_create: meshes need one field, constant D and no velocity");
   }
   try {

@@ -15,11 +15,12 @@ constexpr int kMaxFields = 16;
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 
 // Offsets of the packed constant operators (same layout in FP64 and FP32).
-// bf2n: 1D Bernstein coefficients of a face -> values at its LGL nodes.
+// bf2n: 1D Bernstein coefficients of a face -> values at its LGL nodes;
+// w1, w2: Algorithm 2's diagonal weights of the two sides' coefficients.
 struct OpLayout {
   int Np, Nfp;
   int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, drsh, lift, tau, nr, ns;
-  int bf2n, total;
+  int bf2n, w1, w2, total;
   __host__ __device__ constexpr OpLayout(int N)
       : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
         n2b(0),
@@ -43,7 +44,9 @@ struct OpLayout {
         nr(tau + Nfp),
         ns(nr + Np),
         bf2n(ns + Np),
-        total(bf2n + Nfp * Nfp) {}
+        w1(bf2n + Nfp * Nfp),
+        w2(w1 + Nfp),
+        total(w2 + Nfp) {}
 };
 
 // Edge kernel implementations (values as ARDG_EDGE_* in the C ABI).
@@ -52,6 +55,12 @@ struct OpLayout {
 // and EDGE_LANE otherwise; split-BF16 products run on EDGE_SPLIT_MFMA up to
 // N = 3 and on EDGE_MFMA above.
 enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, EDGE_SPLIT_MFMA = 4 };
+
+// Diffusion coefficient forms (values as ARDG_D_* in the C ABI): one
+// constant per field, or element-wise with the flux of Algorithm 1
+// (reconstruction of D grad u~) or Algorithm 2 (reconstructed D times
+// grad u~).
+enum DiffusionMode { DM_CONST = 0, DM_ALG1 = 1, DM_ALG2 = 2 };
 
 struct DevMesh {
   int N = 0;
@@ -70,7 +79,7 @@ struct DevMesh {
   const double2* vn = nullptr;    // [E] n1.v at A and at B (affine velocity)
   const double* ops64 = nullptr;
   const float* ops32 = nullptr;
-  int alg1 = 0;                   // element-wise D (Algorithm 1)
+  int dmode = DM_CONST;           // DiffusionMode
   int edge_kernel = EDGE_AUTO;    // EdgeKernel
   int conv = 0;                   // convective term on
   double Dfield[kMaxFields] = {};

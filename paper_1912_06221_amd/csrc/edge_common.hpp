@@ -219,11 +219,21 @@ __device__ inline void matvec_sel(cptr<T> A0, const T* x, T* y) {
     matvec<ROWS, COLS, T>(A0, x, y);
 }
 
+// Algorithm 2's reconstructed coefficient at diagonal node j of an edge
+// with element coefficients D1, D2: D1 w1_j + D2 w2_j.
+template <int N, typename T>
+__device__ inline T alg2_coef(cptr<T> op, int j, T D1, T D2) {
+  constexpr OpLayout L(N);
+  return D1 * op[L.w1 + j] + D2 * op[L.w2 + j];
+}
+
 // Diffusive flux of boundary face e (index past the interior edges): the
 // element's sub-triangle on its mirror-ghost rhombus and the boundary
-// reconstruction operator.  F receives sJ * flux, trace the element's values
-// on the face, vn the stored n.v (convection).
-template <int N, typename T, bool ALG1>
+// reconstruction operator (Algorithm 1: its boundary blocks; Algorithm 2:
+// the constant-coefficient operator times the coefficient reconstructed
+// from the element's D on both halves).  F receives sJ * flux, trace the
+// element's values on the face, vn the stored n.v (convection).
+template <int N, typename T, int DM>
 __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ uf, T* F, T* trace, double2& vn) {
   constexpr OpLayout L(N);
@@ -236,21 +246,24 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
   T v[Np];
 #pragma unroll
   for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
-  const T D = ALG1 ? (T)m.Delem[k] : (T)m.Dfield[field];
+  const T D = DM != DM_CONST ? (T)m.Delem[k] : (T)m.Dfield[field];
   T t[Np], c[Np];
   rotate_to_face<N, T>(v, fa, t, trace);
   matvec<Np, Np, T>(op + L.n2b, t, c);
   decasteljau<N, T>(c, mu);
   const T gR = (T)g.x, gS = (T)g.y;
   T gb[2 * Nfp];
-  matvec<2 * Nfp, Np, T>(op + (ALG1 ? L.ubr : L.kbr), c, gb);
+  matvec<2 * Nfp, Np, T>(op + (DM == DM_ALG1 ? L.ubr : L.kbr), c, gb);
 #pragma unroll
-  for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gb[j] + gS * gb[Nfp + j]);
+  for (int j = 0; j < Nfp; ++j) {
+    const T Dj = DM == DM_ALG2 ? alg2_coef<N, T>(op, j, D, D) : D;
+    F[j] = Dj * (gR * gb[j] + gS * gb[Nfp + j]);
+  }
 }
 
 // Boundary face e with its upwind convective flux (u+ = 0 outside), written
 // to the flux array.
-template <int N, typename T, bool ALG1>
+template <int N, typename T, int DM>
 __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -259,7 +272,7 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   const T* uf = u + (int64_t)field * m.K * Np;
   T F[Nfp], tr[Nfp];
   double2 vn = make_double2(0.0, 0.0);
-  boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr, vn);
+  boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr, vn);
   if (m.conv) {
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
@@ -274,7 +287,7 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
 }
 
 // One lane per edge.
-template <int N, typename T, bool ALG1>
+template <int N, typename T, int DM>
 __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                  const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -293,7 +306,7 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
     const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
     const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
     double D1d = 0.0, D2d = 0.0;
-    if (ALG1) {
+    if (DM != DM_CONST) {
       D1d = m.Delem[k1];
       D2d = m.Delem[k2];
     }
@@ -326,7 +339,7 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
     decasteljau<N, T>(c[1], mu2);
     const T* cc = &c[0][0];
     const T gR = (T)g.x, gS = (T)g.y;
-    if (ALG1) {
+    if (DM == DM_ALG1) {
       const T D1 = (T)D1d, D2 = (T)D2d;
       if (D1d == D2d) {
         // equal coefficients: Algorithm 1 reduces exactly to D (U1 - U2) c
@@ -346,10 +359,13 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       T gg[2 * Nfp];
       matvec_sel<kBoth, 2 * Nfp, 2 * Np, T>(op + L.kr, cc, gg);
 #pragma unroll
-      for (int j = 0; j < Nfp; ++j) F[j] = D * (gR * gg[j] + gS * gg[Nfp + j]);
+      for (int j = 0; j < Nfp; ++j) {
+        const T Dj = DM == DM_ALG2 ? alg2_coef<N, T>(op, j, (T)D1d, (T)D2d) : D;
+        F[j] = Dj * (gR * gg[j] + gS * gg[Nfp + j]);
+      }
     }
   } else {
-    boundary_flux<N, T, ALG1>(m, op, e, field, uf, F, tr1, vn);
+    boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr1, vn);
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
   }

@@ -44,7 +44,7 @@
 
 namespace ardg {
 
-template <int N, typename T, bool ALG1>
+template <int N, typename T, int DM>
 __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __restrict__ u,
                                                         T* __restrict__ flux, int nf) {
   int64_t tile;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
   tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
   const int64_t e = tile * blockDim.x + threadIdx.x;
   if (e >= m.E_int + m.E_bdy) return;
-  edge_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
+  edge_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
 }
 
 // Interior edges split by side: a block of two waves takes a tile of 64
@@ -76,14 +76,14 @@ struct SplitIn {
   static constexpr int Np = (N + 1) * (N + 2) / 2;
   T v[Np];               // the side's element values
   double2 mu, g, vn;     // apex weights of this side, (gamma_R, gamma_S) sJ, n.v sJ
-  double D1, D2;         // element D of both sides (Algorithm 1)
+  double D1, D2;         // element D of both sides (Algorithms 1 and 2)
   int f;                 // this side's face
   bool valid;
   int64_t e;
 };
 
 // Wave s of the block (side s + 1) issues the loads of the tile at e0.
-template <int N, typename T, bool ALG1, bool CONV>
+template <int N, typename T, int DM, bool CONV>
 __device__ inline void edge_split_gather(const DevMesh& m, int64_t e0, int field, const T* __restrict__ u,
                                          SplitIn<N, T>& in) {
   constexpr int Np = SplitIn<N, T>::Np;
@@ -106,7 +106,7 @@ __device__ inline void edge_split_gather(const DevMesh& m, int64_t e0, int field
   for (int n = 0; n < Np; ++n) in.v[n] = uf[(int64_t)k * Np + n];
   in.D1 = 0.0;
   in.D2 = 0.0;
-  if (ALG1) {
+  if (DM != DM_CONST) {
     in.D1 = m.Delem[k1];
     in.D2 = m.Delem[k2];
   }
@@ -118,7 +118,7 @@ __device__ inline void edge_split_gather(const DevMesh& m, int64_t e0, int field
 // reconstruction operator's columns of that side, contracted with the edge's
 // gamma and D one flux node at a time, and the upwind term where this side is
 // upstream -- and the two shares meet in LDS (part, Nfp x 64).
-template <int N, typename T, bool ALG1, bool CONV>
+template <int N, typename T, int DM, bool CONV>
 __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restrict__ flux, const SplitIn<N, T>& in,
                                          T (*part)[kSplitTile]) {
   constexpr OpLayout L(N);
@@ -134,20 +134,26 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
   decasteljau<N, T>(c, in.mu);
   // Algorithm 1 reduces to D (U1 - U2) when every edge of the tile has
   // D1 == D2; both waves see the same tile and take the same branch
-  const bool quad = ALG1 && __ballot(in.valid && in.D1 != in.D2) != 0;
+  const bool quad = DM == DM_ALG1 && __ballot(in.valid && in.D1 != in.D2) != 0;
   const T gR = (T)in.g.x, gS = (T)in.g.y;
   T F[Nfp];
-  if (quad) {
+  if (DM == DM_ALG2) {
+    // Algorithm 2: the constant-coefficient gradient operator, weighted per
+    // diagonal node by the reconstructed coefficient
+    const T D1 = (T)in.D1, D2 = (T)in.D2;
+    auto emit = [&](int j, const T* a) { F[j] = alg2_coef<N, T>(op, j, D1, D2) * (gR * a[0] + gS * a[1]); };
+    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + L.kr + s * Np, c, emit);
+  } else if (quad) {
     const T D1 = (T)in.D1, D2 = (T)in.D2;
     const T a1 = D1 * gR, b1 = D1 * gS, a2 = -D2 * gR, b2 = -D2 * gS;
     matvec_groups<4, Nfp, Nfp, Np, K2, T>(op + L.u1r + s * Np, c, [&](int j, const T* a) {
       F[j] = a1 * a[0] + b1 * a[1] + a2 * a[2] + b2 * a[3];
     });
   } else {
-    const T D = ALG1 ? (T)in.D1 : (T)m.Dfield[field];
+    const T D = DM == DM_ALG1 ? (T)in.D1 : (T)m.Dfield[field];
     const T a1 = D * gR, b1 = D * gS;
     auto emit = [&](int j, const T* a) { F[j] = a1 * a[0] + b1 * a[1]; };
-    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (ALG1 ? L.udr : L.kr) + s * Np, c, emit);
+    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (DM == DM_ALG1 ? L.udr : L.kr) + s * Np, c, emit);
   }
   if (CONV) {
     // upwind: node j of side 1 meets node N - j of side 2
@@ -175,7 +181,7 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
 // operator, one lane per face): their serial chain is the longest of the
 // launch, so they start first and run beside the interior tiles.  The other
 // blocks take one tile of 64 interior edges each.
-template <int N, typename T, bool ALG1, bool CONV>
+template <int N, typename T, int DM, bool CONV>
 __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
                                                                     T* __restrict__ flux, int nb_bdy, int nf) {
   __shared__ SplitShared<N, T> S;
@@ -184,7 +190,7 @@ __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, c
   if (b < nbt) {
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * (2 * kSplitTile) + threadIdx.x;
-    if (e < m.E_int + m.E_bdy) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
+    if (e < m.E_int + m.E_bdy) boundary_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   // nb_bdy is a multiple of 8, so b - nbt keeps b's XCD
@@ -192,8 +198,8 @@ __global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, c
   int field;
   tile_and_field(b - nbt, (int64_t)gridDim.x - nbt, nf, tile, field);
   SplitIn<N, T> in;
-  edge_split_gather<N, T, ALG1, CONV>(m, tile * kSplitTile, field, u, in);
-  edge_split_finish<N, T, ALG1, CONV>(m, field, flux, in, S.part);
+  edge_split_gather<N, T, DM, CONV>(m, tile * kSplitTile, field, u, in);
+  edge_split_finish<N, T, DM, CONV>(m, field, flux, in, S.part);
 }
 
 // Batched form: persistent blocks over items of many meshes (constant D, no
@@ -211,11 +217,11 @@ __global__ __launch_bounds__(2 * kSplitTile) void batch_edge_split_kernel(const 
     const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
     if (t >= 0) {
       SplitIn<N, T> in;
-      edge_split_gather<N, T, false, false>(P->m, (int64_t)t * kSplitTile, 0, vin, in);
-      edge_split_finish<N, T, false, false>(P->m, 0, (T*)P->flux, in, S.part);
+      edge_split_gather<N, T, DM_CONST, false>(P->m, (int64_t)t * kSplitTile, 0, vin, in);
+      edge_split_finish<N, T, DM_CONST, false>(P->m, 0, (T*)P->flux, in, S.part);
     } else {
       const int64_t e = P->m.E_int + (int64_t)(-1 - t) * (2 * kSplitTile) + threadIdx.x;
-      if (e < P->m.E_int + P->m.E_bdy) boundary_body<N, T, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+      if (e < P->m.E_int + P->m.E_bdy) boundary_body<N, T, DM_CONST>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
     }
     __syncthreads();
   }
@@ -247,7 +253,7 @@ __device__ inline void load_elem_in(const DevMesh& m, int64_t k, int field,
   in.p1 = m.vert[3 * k];
   in.p2 = m.vert[3 * k + 1];
   in.p3 = m.vert[3 * k + 2];
-  in.D = m.alg1 ? m.Delem[k] : m.Dfield[field];
+  in.D = m.dmode != DM_CONST ? m.Delem[k] : m.Dfield[field];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const int code = m.elem_face[f * m.K + k];
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(TILE) void batch_edge_kernel(const BatchProb* __res
     const int64_t e = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * TILE + threadIdx.x;
     if (e < P->m.E_int + P->m.E_bdy) {
       const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
-      edge_body<N, T, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+      edge_body<N, T, DM_CONST>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
     }
   }
 }
@@ -455,21 +461,28 @@ hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flu
 #define ARDG_SPLIT_LAUNCH(A, C)                                                                  \
   hipLaunchKernelGGL((edge_split_kernel<N, T, A, C>), grid, dim3(2 * kSplitTile), 0, st, m,       \
                      (const T*)u, (T*)flux, (int)nbb, nfields)
-    if (m.alg1) {
-      if (m.conv) ARDG_SPLIT_LAUNCH(true, true);
-      else ARDG_SPLIT_LAUNCH(true, false);
-    } else {
-      if (m.conv) ARDG_SPLIT_LAUNCH(false, true);
-      else ARDG_SPLIT_LAUNCH(false, false);
+    switch (m.dmode * 2 + (m.conv ? 1 : 0)) {
+      case 0: ARDG_SPLIT_LAUNCH(DM_CONST, false); break;
+      case 1: ARDG_SPLIT_LAUNCH(DM_CONST, true); break;
+      case 2: ARDG_SPLIT_LAUNCH(DM_ALG1, false); break;
+      case 3: ARDG_SPLIT_LAUNCH(DM_ALG1, true); break;
+      case 4: ARDG_SPLIT_LAUNCH(DM_ALG2, false); break;
+      case 5: ARDG_SPLIT_LAUNCH(DM_ALG2, true); break;
+      default: return hipErrorInvalidValue;
     }
 #undef ARDG_SPLIT_LAUNCH
     return hipGetLastError();
   }
   dim3 grid((unsigned)((E + 255) / 256 * nfields));
-  if (m.alg1)
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, true>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux, nfields);
-  else
-    hipLaunchKernelGGL((edge_flux_kernel<N, T, false>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux, nfields);
+#define ARDG_LANE_LAUNCH(A) \
+  hipLaunchKernelGGL((edge_flux_kernel<N, T, A>), grid, dim3(256), 0, st, m, (const T*)u, (T*)flux, nfields)
+  switch (m.dmode) {
+    case DM_CONST: ARDG_LANE_LAUNCH(DM_CONST); break;
+    case DM_ALG1: ARDG_LANE_LAUNCH(DM_ALG1); break;
+    case DM_ALG2: ARDG_LANE_LAUNCH(DM_ALG2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef ARDG_LANE_LAUNCH
   return hipGetLastError();
 }
 

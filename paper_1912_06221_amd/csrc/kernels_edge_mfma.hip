@@ -34,12 +34,13 @@ namespace ardg {
 constexpr int kEdgeTile = 64;   // interior edges per block (one wave)
 
 // Operator forms of step 4.
-//   PAIR_K : constant D, rows (d/dR, d/dS) of the reconstruction gradient
+//   PAIR_K : constant D (or Algorithm 2's per-node coefficient), rows
+//            (d/dR, d/dS) of the reconstruction gradient
 //   PAIR_UD: Algorithm 1 with D1 == D2 on every edge of the wave: U1 - U2
 //   QUAD   : Algorithm 1, rows (U1R, U1S, U2R, U2S)
 enum EdgeForm { PAIR_K = 0, PAIR_UD = 1, QUAD = 2 };
 
-template <int N, typename P, int FORM, bool CONV>
+template <int N, typename P, int FORM, int DM, bool CONV>
 __device__ inline void edge_tile_mfma(const DevMesh& m, const typename Mma<P>::T* __restrict__ opg,
                                       int field, const typename Mma<P>::T* __restrict__ uf,
                                       typename Mma<P>::T* __restrict__ out, int nval, int k1, int fa,
@@ -189,11 +190,11 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const typename Mma<P>::T
           fl[el * Nfp + jj] = F;
         }
       } else {
-        const T D = FORM == PAIR_K ? Dc : d1;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int jj = 8 * mt + 2 * grp + h;
           if (ok && jj < Nfp) {
+            const T D = DM == DM_ALG2 ? d1 * opg[L.w1 + jj] + d2 * opg[L.w2 + jj] : (FORM == PAIR_K ? Dc : d1);
             T F = D * (gR * g[sb][mt][2 * h] + gS * g[sb][mt][2 * h + 1]);
             if (CONV) F -= fl[el * Nfp + jj];
             fl[el * Nfp + jj] = F;
@@ -210,7 +211,7 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const typename Mma<P>::T
   }
 }
 
-template <int N, typename P, bool ALG1, bool CONV>
+template <int N, typename P, int DM, bool CONV>
 __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
                                                               const typename Mma<P>::T* __restrict__ u,
                                                               typename Mma<P>::T* __restrict__ flux,
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
     // the interior tiles
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * kEdgeTile + l;
-    if (e < E) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   int64_t tile;
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
   const int k1 = ef.x & 0x3fffffff, fa = (int)((unsigned)ef.x >> 30);
   const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
   const double2 mu1 = m.mu1[e], mu2 = m.mu2[e], gam = m.gam[e];
-  const double D1 = ALG1 ? m.Delem[k1] : 0.0, D2 = ALG1 ? m.Delem[k2] : 0.0;
+  const double D1 = DM != DM_CONST ? m.Delem[k1] : 0.0, D2 = DM != DM_CONST ? m.Delem[k2] : 0.0;
   const T* uf = u + (int64_t)field * m.K * Np;
   const T* opg = (const T*)(const void*)opbase<T>(m);
   if (CONV && valid) {
@@ -271,15 +272,15 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
   }
   __syncthreads();
   T* out = flux + ((int64_t)field * E + e0) * Nfp;
-  if (!ALG1) {
-    edge_tile_mfma<N, P, PAIR_K, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
-                                       D1, D2, cb, fl, rot);
+  if (DM != DM_ALG1) {
+    edge_tile_mfma<N, P, PAIR_K, DM, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+                                           D1, D2, cb, fl, rot);
   } else if (__ballot(valid && D1 != D2) == 0) {
-    edge_tile_mfma<N, P, PAIR_UD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
-                                        D1, D2, cb, fl, rot);
+    edge_tile_mfma<N, P, PAIR_UD, DM, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+                                            D1, D2, cb, fl, rot);
   } else {
-    edge_tile_mfma<N, P, QUAD, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
-                                     D1, D2, cb, fl, rot);
+    edge_tile_mfma<N, P, QUAD, DM, CONV>(m, opg, field, uf, out, nval, k1, fa, k2, fb, mu1, mu2, gam,
+                                         D1, D2, cb, fl, rot);
   }
 }
 
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
 // side's columns of the reconstruction operator (vector unit, scalar operands,
 // as in the vector-unit split kernel).  The conversion runs on the matrix pipe
 // beside the other waves' vector work.
-template <int N, typename P, bool ALG1, bool CONV>
+template <int N, typename P, int DM, bool CONV>
 __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
                                                                    const typename Mma<P>::T* __restrict__ u,
                                                                    typename Mma<P>::T* __restrict__ flux,
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
     // boundary faces first (mirror-ghost operator, one lane per face)
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * (2 * kEdgeTile) + threadIdx.x;
-    if (e < E) boundary_body<N, T, ALG1>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   int64_t tile;
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
   const int k2 = ef.y & 0x3fffffff, fb = (int)((unsigned)ef.y >> 30);
   const int k = s ? k2 : k1, f = s ? fb : fa;
   double D1d = 0.0, D2d = 0.0;
-  if (ALG1) {
+  if (DM != DM_CONST) {
     D1d = m.Delem[k1];
     D2d = m.Delem[k2];
   }
@@ -415,20 +416,24 @@ __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
     face_bernstein_to_nodal<N, T>(op, tr);
   }
   decasteljau<N, T>(c, mu);
-  const bool quad = ALG1 && __ballot(valid && D1d != D2d) != 0;
+  const bool quad = DM == DM_ALG1 && __ballot(valid && D1d != D2d) != 0;
   const T gR = (T)g.x, gS = (T)g.y;
   T F[Nfp];
-  if (quad) {
+  if (DM == DM_ALG2) {
+    const T D1 = (T)D1d, D2 = (T)D2d;
+    auto emit = [&](int j, const T* a) { F[j] = alg2_coef<N, T>(op, j, D1, D2) * (gR * a[0] + gS * a[1]); };
+    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + L.kr + s * Np, c, emit);
+  } else if (quad) {
     const T D1 = (T)D1d, D2 = (T)D2d;
     const T a1 = D1 * gR, b1 = D1 * gS, a2 = -D2 * gR, b2 = -D2 * gS;
     matvec_groups<4, Nfp, Nfp, Np, K2, T>(op + L.u1r + s * Np, c, [&](int j, const T* a) {
       F[j] = a1 * a[0] + b1 * a[1] + a2 * a[2] + b2 * a[3];
     });
   } else {
-    const T D = ALG1 ? (T)D1d : (T)m.Dfield[field];
+    const T D = DM == DM_ALG1 ? (T)D1d : (T)m.Dfield[field];
     const T a1 = D * gR, b1 = D * gS;
     auto emit = [&](int j, const T* a) { F[j] = a1 * a[0] + b1 * a[1]; };
-    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (ALG1 ? L.udr : L.kr) + s * Np, c, emit);
+    matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (DM == DM_ALG1 ? L.udr : L.kr) + s * Np, c, emit);
   }
   if (CONV) {
     // upwind: node j of side 1 meets node N - j of side 2
@@ -469,12 +474,14 @@ hipError_t edge_smfma_t(const DevMesh& m, int nfields, const void* u, void* flux
   const int nbd = (int)nbb;
 #define ARDG_SMFMA(A, C) \
   hipLaunchKernelGGL((edge_smfma_kernel<N, P, A, C>), grid, dim3(2 * kEdgeTile), 0, st, m, uu, ff, nbd, nfields)
-  if (m.alg1) {
-    if (m.conv) ARDG_SMFMA(true, true);
-    else ARDG_SMFMA(true, false);
-  } else {
-    if (m.conv) ARDG_SMFMA(false, true);
-    else ARDG_SMFMA(false, false);
+  switch (m.dmode * 2 + (m.conv ? 1 : 0)) {
+    case 0: ARDG_SMFMA(DM_CONST, false); break;
+    case 1: ARDG_SMFMA(DM_CONST, true); break;
+    case 2: ARDG_SMFMA(DM_ALG1, false); break;
+    case 3: ARDG_SMFMA(DM_ALG1, true); break;
+    case 4: ARDG_SMFMA(DM_ALG2, false); break;
+    case 5: ARDG_SMFMA(DM_ALG2, true); break;
+    default: return hipErrorInvalidValue;
   }
 #undef ARDG_SMFMA
   return hipGetLastError();
@@ -513,17 +520,18 @@ hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux,
   const T* uu = (const T*)u;
   T* ff = (T*)flux;
   const int nbd = (int)nbb;
-  if (m.alg1) {
-    if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
-    else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, true, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
-  } else {
-    if (m.conv)
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, true>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
-    else
-      hipLaunchKernelGGL((edge_mfma_kernel<N, P, false, false>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields);
+#define ARDG_EMFMA(A, C) \
+  hipLaunchKernelGGL((edge_mfma_kernel<N, P, A, C>), grid, dim3(kEdgeTile), 0, st, m, uu, ff, nbd, nfields)
+  switch (m.dmode * 2 + (m.conv ? 1 : 0)) {
+    case 0: ARDG_EMFMA(DM_CONST, false); break;
+    case 1: ARDG_EMFMA(DM_CONST, true); break;
+    case 2: ARDG_EMFMA(DM_ALG1, false); break;
+    case 3: ARDG_EMFMA(DM_ALG1, true); break;
+    case 4: ARDG_EMFMA(DM_ALG2, false); break;
+    case 5: ARDG_EMFMA(DM_ALG2, true); break;
+    default: return hipErrorInvalidValue;
   }
+#undef ARDG_EMFMA
   return hipGetLastError();
 }
 

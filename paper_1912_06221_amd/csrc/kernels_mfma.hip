@@ -84,7 +84,7 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
   const bool valid = k0 + el < m.K;
   const int64_t k = valid ? k0 + el : k0;
   const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
-  const double Dd = m.alg1 ? m.Delem[k] : m.Dfield[field];
+  const double Dd = m.dmode != DM_CONST ? m.Delem[k] : m.Dfield[field];
   int code[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) code[f] = m.elem_face[f * m.K + k];

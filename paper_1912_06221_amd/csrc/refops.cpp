@@ -329,6 +329,17 @@ RefOps build_refops(int N, bool* rank_ok) {
   o.alg1_nodal = vcat(vcat(alg1(G1, o.Dr, Phi1, RV), alg1(G1, o.Ds, Phi1, RV)),
                       vcat(alg1(G2, o.Dr, Phi2, RV), alg1(G2, o.Ds, Phi2, RV)));
 
+  // Algorithm 2: a constant coefficient is the same constant on the
+  // sub-triangle (all nodal values equal), so its reconstruction at the
+  // diagonal is G1 1 (side 1) and G2 1 (side 2)
+  o.alg2_w1.assign(Nfp, 0.0);
+  o.alg2_w2.assign(Nfp, 0.0);
+  for (int j = 0; j < Nfp; ++j)
+    for (int p = 0; p < Np; ++p) {
+      o.alg2_w1[j] += G1(j, p);
+      o.alg2_w2[j] += G2(j, p);
+    }
+
   // Boundary faces: the ghost's sub-triangle data is minus side 1's data with
   // (r, s) swapped, i.e. Bernstein multi-index (a1, a2, a3) -> (a1, a3, a2).
   Mat Sw(Np, Np);

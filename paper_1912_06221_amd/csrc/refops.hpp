@@ -29,6 +29,10 @@ struct RefOps {
   Mat U1R, U1S, U2R, U2S;            // Algorithm 1 blocks [Nfp][2Np]
   Mat KBR, KBS;                      // boundary (mirror ghost) versions [Nfp][Np]
   Mat UBR, UBS;                      // Algorithm 1 boundary versions [Nfp][Np]
+  // Algorithm 2: the reconstruction of a coefficient that is 1 on one
+  // sub-triangle and 0 on the other, at the diagonal nodes, so that an
+  // element-wise constant coefficient reconstructs to D1 w1 + D2 w2 there.
+  std::vector<double> alg2_w1, alg2_w2;   // [Nfp]
   // The same maps on nodal sub-triangle data (for export / checking).
   Mat recon_grad_nodal;              // [2Nfp][2Np]
   Mat alg1_nodal;                    // [4Nfp][2Np]

@@ -18,7 +18,7 @@ TOL32 = 2e-4
 TOLBF = 5e-2
 
 
-def _setup(name):
+def _setup(name, alg=1):
     from oracle.rhs import Problem
     from paper_1912_06221_amd import ardg
     spec = W.WORKLOADS[name]
@@ -35,13 +35,13 @@ def _setup(name):
     ops = ardg.Ops(N)
     lm = ardg.Mesh(ops, mesh.vxy, mesh.etov, device=0)
     if mode == "element":
-        lm.set_diffusion_element(D)
+        lm.set_diffusion_element(D, alg=alg)
     else:
         lm.set_diffusion_const(D)
     if vel is not None:
         lm.set_velocity(vel)
     pr = Problem(mesh.vxy, mesh.etov, N, D, D_mode=mode, velocity=vel, nfields=nf,
-                 build_edges=False)
+                 build_edges=False, alg=alg)
     xy = pr.nodal_xy()
     u0 = np.stack([W.fourier_modes(xy[..., 0], xy[..., 1], seed=W.seed_for(cfg, "IC") + 10 * f)
                    for f in range(nf)])
@@ -105,3 +105,28 @@ def test_fullsize_rk4_step_sampled():
         err = np.abs(inc_got - inc_ref).max() / np.abs(inc_ref).max()
         print(f"  prec={prec} increment rel err {err:.2e}", flush=True)
         assert err <= tol
+
+
+@pytest.mark.parametrize("name", ["contrast_256x256_N4", "loguniformD_512x512_N6"])
+def test_fullsize_alg2_rhs_sampled(name):
+    """Algorithm 2 (reconstructed coefficient times the reconstructed
+    gradient) at the full sizes of the two element-wise-D workloads, FP64 and
+    FP32, on sampled elements."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    print(f"full-size rhs, Algorithm 2, {name}", flush=True)
+    spec, mesh, ops, lm, pr, u0 = _setup(name, alg=2)
+    els = _sample(mesh.K, 16, seed=3)
+    ur = W.random_nodal(u0.shape, seed=9)
+    for data, label in ((u0, "smooth"), (ur, "random")):
+        ud = to_dev(data)
+        for prec, dt, tol in ((ardg.FP64, torch.float64, TOL64), (ardg.FP32, torch.float32, TOL32)):
+            x = ud.to(dt)
+            out = torch.empty_like(x)
+            lm.rhs_eval(x, out, precision=prec)
+            got = to_np(out)
+            ref = pr.rhs_elements(data[0], els)
+            scale = np.abs(pr.rhs_elements(ur[0] * np.abs(data[0]).max(), els)).max()
+            err = np.abs(got[0, els] - ref).max() / scale
+            print(f"  {label} prec={prec} err/scale={err:.2e}", flush=True)
+            assert err <= tol

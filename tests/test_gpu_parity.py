@@ -66,6 +66,10 @@ CASES = [
     (12, 0.2, 3, "const", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0), 3),
     (10, 0.2, 2, "const", (0.6, -0.4, 0.2, -1.0, 1.0, 0.1), 2),
     (10, 0.2, 4, "const", (0.3, -0.2, 0.0, -1.0, 1.0, 0.0), 2),
+    (12, 0.2, 2, "element2", None, 1),
+    (11, 0.2, 3, "element2", None, 1),
+    (8, 0.2, 6, "element2", None, 1),
+    (10, 0.2, 4, "element2", (0.3, -0.2, 0.0, -1.0, 1.0, 0.0), 1),
 ]
 
 
@@ -252,6 +256,9 @@ VARIANT_CASES = [
     (12, 4, "const", None),
     (10, 3, "const", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)),
     (10, 4, "blocks", (0.3, -0.2, 0.0, -1.0, 1.0, 0.0)),
+    (10, 2, "blocks2", None),
+    (9, 5, "blocks2", None),
+    (10, 3, "blocks2", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)),
 ]
 
 
@@ -276,8 +283,8 @@ def test_matrix_core_and_vector_kernels_agree(case, prec):
     m, N, dk, vel = case
     print(f"variants m{m} N{N} {dk} {prec}", flush=True)
     mesh = W.split_square_mesh(m, 0.2, seed=100 + N)
-    D_mode = "element" if dk == "blocks" else "const"
-    D = _blocks_D(mesh) if dk == "blocks" else [0.9]
+    D_mode = {"blocks": "element", "blocks2": "element2"}.get(dk, "const")
+    D = _blocks_D(mesh) if dk.startswith("blocks") else [0.9]
     pr = oracle_problem(mesh, N, D_mode, D, vel, 1)
     dt = torch.float64 if prec == "fp64" else torch.float32
     p = ardg.FP64 if prec == "fp64" else ardg.FP32

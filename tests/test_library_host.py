@@ -202,3 +202,24 @@ def test_batch_refuses_host_only_meshes(L):
     assert ei.value.status == -1
     with pytest.raises(ardg.ArdgError):
         ardg.Batch([])
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
+def test_alg2_weights_match_oracle(L, N):
+    """Algorithm 2's diagonal weights (reconstruction of a coefficient that is
+    1 on one side and 0 on the other) from the library's host setup against
+    the oracle's literal reconstruction on a jittered mesh's edges."""
+    from paper_1912_06221_amd import ardg as A
+    from oracle import ardg as OA
+    from oracle.mesh import Geometry
+    from oracle.reference_element import RefOps
+    ops = A.Ops(N)
+    w = ops.export(A.OPS_ALG2_W).reshape(2, N + 1)
+    mesh = W.split_square_mesh(3, 0.2, seed=N)
+    g = Geometry(mesh.vxy, mesh.etov)
+    ro = RefOps(N)
+    one, zero = np.ones(ro.Np), np.zeros(ro.Np)
+    for (k1, f1, k2, f2) in g.interior[:6]:
+        eg = OA.interior_edge_geometry(g, k1, f1, k2, f2)
+        assert np.abs(OA.coefficient_on_diagonal(ro, eg, f1, f2, one, zero) - w[0]).max() < 1e-12
+        assert np.abs(OA.coefficient_on_diagonal(ro, eg, f1, f2, zero, one) - w[1]).max() < 1e-12
