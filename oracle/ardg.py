@@ -38,6 +38,13 @@ Readings of places the paper leaves open:
   factors; the second RDG takes the nodal products D_k grad(u~_k) already on
   the sub-triangles (so no second V_p) and the flux is n1 . (result on the
   diagonal).  At a boundary face the ghost carries the element's own D.
+* Prescribed exterior data at a boundary face (inhomogeneous Dirichlet data,
+  needed for the paper's Gaussian tests, whose solution is not zero on the
+  boundary; the paper does not say how it imposes it): the ghost
+  sub-triangle Omega'_2 = (P2, B, A) of the mirror rhombus carries the
+  prescribed exterior state g itself, sampled at its nodes, so that
+  u~ = RDG(u1, g).  With Algorithms 1 and 2 the ghost carries the element's
+  own D.  The default (no data given) stays the zero-Dirichlet mirror ghost.
 * Algorithm 2 (the alternative form): D~ = RDG(D^1, D^2) is the same
   least-squares reconstruction applied to the coefficient's nodal data of the
   two elements (projected onto the sub-triangles like u), Grad(u~) is the
@@ -463,3 +470,48 @@ def boundary_edge_operator_alg2(ops: RefOps, geom, k1, f1, eg: EdgeGeometry, D1:
     W = boundary_edge_operator(ops, geom, k1, f1, eg)
     Dt = boundary_coefficient_on_diagonal(ops, eg, f1, D1 * np.ones(ops.Np))
     return Dt[:, None] * W
+
+
+# ----------------------------------------------------------------------------
+# Boundary faces with prescribed exterior data on the ghost sub-triangle
+# ----------------------------------------------------------------------------
+
+def ghost_nodes(N: int, eg: EdgeGeometry) -> np.ndarray:
+    """[Np, 2] physical points of the nodes of Omega'_2 = (P2, B, A), in the
+    node order of the reference triangle mapped with those vertices."""
+    rs = nodes(N)
+    r, s = rs[:, 0], rs[:, 1]
+    return (-(r + s)[:, None] / 2.0 * eg.P2[None, :] + (r + 1)[:, None] / 2.0 * eg.B[None, :]
+            + (s + 1)[:, None] / 2.0 * eg.A[None, :])
+
+
+def prescribed_boundary_operators(ops: RefOps, eg: EdgeGeometry, f1: int):
+    """(W1, WG), [Nfp, Np] each: the flux n1 . grad u~ of a boundary face with
+    u~ = RDG(u1, g), W1 acting on the element's nodal data and WG on the
+    exterior state at ghost_nodes (already on Omega'_2: no projection)."""
+    N, Np = ops.N, ops.Np
+    R = recon_pinv(N)
+    c1 = R[:, :Np] @ total_projection(ops, eg.pi1, f1)
+    cg = R[:, Np:] @ ops.Vinv
+    g1x, g1y = _gradient_on_diagonal(N, c1, eg)
+    ggx, ggy = _gradient_on_diagonal(N, cg, eg)
+    return eg.n1[0] * g1x + eg.n1[1] * g1y, eg.n1[0] * ggx + eg.n1[1] * ggy
+
+
+def prescribed_boundary_operators_alg1(ops: RefOps, eg: EdgeGeometry, f1: int, D1: float):
+    """Algorithm 1 at a boundary face with prescribed exterior data; the ghost
+    carries the element's D."""
+    Np = ops.Np
+    P1 = total_projection(ops, eg.pi1, f1)
+    Z = np.zeros((Np, Np))
+    W1 = _alg1_from_subtriangle_modal(ops, eg, P1, Z, D1, D1)
+    WG = _alg1_from_subtriangle_modal(ops, eg, Z, ops.Vinv, D1, D1)
+    return W1, WG
+
+
+def prescribed_boundary_operators_alg2(ops: RefOps, eg: EdgeGeometry, f1: int, D1: float):
+    """Algorithm 2 at a boundary face with prescribed exterior data: the
+    coefficient reconstructed from the element's D on both halves."""
+    W1, WG = prescribed_boundary_operators(ops, eg, f1)
+    Dt = boundary_coefficient_on_diagonal(ops, eg, f1, D1 * np.ones(ops.Np))
+    return Dt[:, None] * W1, Dt[:, None] * WG

@@ -17,8 +17,14 @@ TEST INFRASTRUCTURE ONLY.
 * Convection (the v.grad part of eq. convection_diffusion): nodal collocation
   of v u, weak form, upwind numerical flux f* = max(n.v,0) u- + min(n.v,0) u+,
   with u+ = 0 outside the domain.  The velocity is affine, v(x) = v0 + W x.
+* Boundary faces: zero Dirichlet data through the mirror ghost, or, when a
+  ghost state g(x, y, t, field) is given, the prescribed exterior state on
+  the ghost sub-triangle (the flux then has a part linear in g; the upwind
+  flux takes u+ = g at the face nodes).
 * Time stepping: classic four-stage RK4 and the five-stage fourth-order
-  low-storage RK of Carpenter and Kennedy (the paper's integrator).
+  low-storage RK of Carpenter and Kennedy (the paper's integrator), with the
+  stage times c_s where the right-hand side depends on time (through the
+  boundary data).
 * Norms: cell-normalised L2 and L_inf (eqs. L2_norm_cellUnit,
   Linf_norm_cellUnit) by collapsed Gauss quadrature.
 """
@@ -36,11 +42,13 @@ class Problem:
 
     D_mode: "const" (D is a float, or a list with one value per field) or
     "element" (D is an array [K]; flux by Algorithm 1, or Algorithm 2 when
-    alg=2).
+    alg=2).  ghost: None (zero Dirichlet, mirror ghost) or a callable
+    g(x, y, t, field) giving the prescribed exterior state.
     """
 
     def __init__(self, vxy, etov, N: int, D, D_mode: str = "const",
-                 velocity=None, nfields: int = 1, build_edges: bool = True, alg: int = 1):
+                 velocity=None, nfields: int = 1, build_edges: bool = True, alg: int = 1,
+                 ghost=None):
         self.geom = Geometry(vxy, etov)
         self.ops = RefOps(N)
         self.N = N
@@ -61,6 +69,7 @@ class Problem:
         else:
             raise ValueError(D_mode)
         self.velocity = velocity   # None or (v0x, v0y, W11, W12, W21, W22)
+        self.ghost = ghost
         if build_edges:
             self._build_edges()
 
@@ -82,16 +91,23 @@ class Problem:
             E2.append(W2)
         self.W1 = np.array(E1).reshape(-1, ops.Nfp, ops.Np)
         self.W2 = np.array(E2).reshape(-1, ops.Nfp, ops.Np)
-        B = []
+        B, G, GX = [], [], []
         self.bdy_geom = []
         for (k1, f1) in self.bdy_edges:
             eg = ardg.boundary_edge_geometry(g, k1, f1)
             self.bdy_geom.append(eg)
-            if self.D_mode == "element":
+            if self.ghost is not None:
+                W1, WG = self._prescribed_operators(k1, f1, eg)
+                B.append(W1)
+                G.append(WG)
+                GX.append(ardg.ghost_nodes(ops.N, eg))
+            elif self.D_mode == "element":
                 B.append(self._element_boundary_operator(k1, f1, eg))
             else:
                 B.append(ardg.boundary_edge_operator(ops, g, k1, f1, eg))
         self.WB = np.array(B).reshape(-1, ops.Nfp, ops.Np)
+        self.WG = np.array(G).reshape(-1, ops.Nfp, ops.Np)
+        self.GX = np.array(GX).reshape(-1, ops.Np, 2)
 
     def _element_edge_operator(self, eg, f1, f2, k1, k2):
         alg = ardg.edge_operator_alg2 if self.alg == 2 else ardg.edge_operator_alg1
@@ -101,8 +117,18 @@ class Problem:
         alg = ardg.boundary_edge_operator_alg2 if self.alg == 2 else ardg.boundary_edge_operator_alg1
         return alg(self.ops, self.geom, k1, f1, eg, self.Delem[k1])
 
+    def _prescribed_operators(self, k1, f1, eg):
+        if self.D_mode != "element":
+            return ardg.prescribed_boundary_operators(self.ops, eg, f1)
+        alg = ardg.prescribed_boundary_operators_alg2 if self.alg == 2 else ardg.prescribed_boundary_operators_alg1
+        return alg(self.ops, eg, f1, self.Delem[k1])
+
+    def ghost_values(self, X, t, field):
+        """The prescribed exterior state at physical points X [..., 2]."""
+        return np.asarray(self.ghost(X[..., 0], X[..., 1], t, field), dtype=np.float64)
+
     # -- fluxes -----------------------------------------------------------------
-    def diffusive_flux(self, u: np.ndarray, field: int = 0):
+    def diffusive_flux(self, u: np.ndarray, field: int = 0, t: float = 0.0):
         """Fluxes F in element-1 (CCW) order: [E_int, Nfp] and [E_bdy, Nfp]."""
         k1 = np.array([e[0] for e in self.int_edges], dtype=np.int64)
         k2 = np.array([e[2] for e in self.int_edges], dtype=np.int64)
@@ -111,6 +137,8 @@ class Problem:
         if len(k2):
             Fi = Fi + np.einsum("eij,ej->ei", self.W2, u[k2])
         Fb = np.einsum("eij,ej->ei", self.WB, u[kb]) if len(kb) else np.zeros((0, self.ops.Nfp))
+        if self.ghost is not None and len(kb):
+            Fb = Fb + np.einsum("eij,ej->ei", self.WG, self.ghost_values(self.GX, t, field))
         if self.D_mode == "const":
             Fi = Fi * self.Dfield[field]
             Fb = Fb * self.Dfield[field]
@@ -138,8 +166,9 @@ class Problem:
         v0x, v0y, a, b, c, d = self.velocity
         return v0x + a * xy[..., 0] + b * xy[..., 1], v0y + c * xy[..., 0] + d * xy[..., 1]
 
-    def upwind_face_flux(self, u):
-        """[K, 3, Nfp] upwind flux f* per element face (CCW order)."""
+    def upwind_face_flux(self, u, t: float = 0.0, field: int = 0):
+        """[K, 3, Nfp] upwind flux f* per element face (CCW order); outside
+        the domain u+ is 0, or the prescribed exterior state."""
         ops, g = self.ops, self.geom
         xyn = g.physical(ops.rs)
         vx, vy = self.velocity_at(xyn)
@@ -151,7 +180,8 @@ class Problem:
                 um = u[k, idx]
                 k2 = g.EToE[k, f]
                 if k2 < 0:
-                    up = np.zeros_like(um)
+                    up = (np.zeros_like(um) if self.ghost is None
+                          else self.ghost_values(xyn[k, idx], t, field))
                 else:
                     f2 = g.EToF[k, f]
                     up = u[k2, ops.fmask[f2]][::-1]
@@ -159,14 +189,14 @@ class Problem:
         return out
 
     # -- right-hand side ------------------------------------------------------
-    def rhs(self, u: np.ndarray) -> np.ndarray:
-        """du/dt for state u [F, K, Np] (or [K, Np] for one field)."""
+    def rhs(self, u: np.ndarray, t: float = 0.0) -> np.ndarray:
+        """du/dt at time t for state u [F, K, Np] (or [K, Np] for one field)."""
         single = (u.ndim == 2)
         U = u[None] if single else u
-        out = np.stack([self._rhs_field(U[f], f) for f in range(U.shape[0])])
+        out = np.stack([self._rhs_field(U[f], f, t) for f in range(U.shape[0])])
         return out[0] if single else out
 
-    def _rhs_field(self, u, field):
+    def _rhs_field(self, u, field, t=0.0):
         ops, g = self.ops, self.geom
         rx, ry, sx, sy = (a[:, None] for a in (g.rx, g.ry, g.sx, g.sy))
         ur = u @ ops.Dr.T
@@ -177,7 +207,7 @@ class Problem:
         vol = (rx * (qx @ ops.Drw.T) + sx * (qx @ ops.Dsw.T)
                + ry * (qy @ ops.Drw.T) + sy * (qy @ ops.Dsw.T))
         rhs = -Dk * vol
-        Fi, Fb = self.diffusive_flux(u, field)
+        Fi, Fb = self.diffusive_flux(u, field, t)
         Ff = self.face_fluxes(Fi, Fb)
         surf = np.zeros_like(u)
         for f in range(3):
@@ -185,10 +215,10 @@ class Problem:
             surf += scale * (Ff[:, f, :] @ ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp].T)
         rhs = rhs + surf
         if self.velocity is not None:
-            rhs = rhs + self._convection_weak(u)
+            rhs = rhs + self._convection_weak(u, t, field)
         return rhs
 
-    def _convection_weak(self, u):
+    def _convection_weak(self, u, t=0.0, field=0):
         """-div(v u) in weak form: Dxw (vx u) + Dyw (vy u) - sum_f LIFT_f f*."""
         ops, g = self.ops, self.geom
         xyn = g.physical(ops.rs)
@@ -197,7 +227,7 @@ class Problem:
         rx, ry, sx, sy = (a[:, None] for a in (g.rx, g.ry, g.sx, g.sy))
         vol = (rx * (fx @ ops.Drw.T) + sx * (fx @ ops.Dsw.T)
                + ry * (fy @ ops.Drw.T) + sy * (fy @ ops.Dsw.T))
-        fs = self.upwind_face_flux(u)
+        fs = self.upwind_face_flux(u, t, field)
         surf = np.zeros_like(u)
         for f in range(3):
             scale = (g.sJ[:, f] / g.J)[:, None]
@@ -205,13 +235,17 @@ class Problem:
         return vol - surf
 
     # -- RHS of a few elements only (sampled checks on large meshes) ---------
-    def _face_flux_one(self, u, k, f, field):
+    def _face_flux_one(self, u, k, f, field, t=0.0):
         """Flux seen by face f of element k (CCW order), computed for that one
         edge with the same steps as the full assembly."""
         g, ops = self.geom, self.ops
         k2 = int(g.EToE[k, f])
         if k2 < 0:
             eg = ardg.boundary_edge_geometry(g, k, f)
+            if self.ghost is not None:
+                W1, WG = self._prescribed_operators(k, f, eg)
+                F = W1 @ u[k] + WG @ self.ghost_values(ardg.ghost_nodes(ops.N, eg), t, field)
+                return F if self.D_mode == "element" else self.Dfield[field] * F
             if self.D_mode == "element":
                 F = self._element_boundary_operator(k, f, eg) @ u[k]
             else:
@@ -228,9 +262,10 @@ class Problem:
             F = self.Dfield[field] * (W1 @ u[k1] + W2 @ u[kb])
         return F if k == k1 else -F[::-1]
 
-    def rhs_elements(self, u, elements, field: int = 0):
-        """du/dt on the listed elements only, [len(elements), Np]; u [K, Np]
-        needs valid values on the listed elements and their face neighbours."""
+    def rhs_elements(self, u, elements, field: int = 0, t: float = 0.0):
+        """du/dt at time t on the listed elements only, [len(elements), Np];
+        u [K, Np] needs valid values on the listed elements and their face
+        neighbours."""
         ops, g = self.ops, self.geom
         out = np.zeros((len(elements), ops.Np))
         xyn = g.physical(ops.rs) if self.velocity is not None else None
@@ -242,7 +277,7 @@ class Problem:
             Dk = self.Delem[k] if self.D_mode == "element" else self.Dfield[field]
             r = -Dk * (rx * (ops.Drw @ qx) + sx * (ops.Dsw @ qx) + ry * (ops.Drw @ qy) + sy * (ops.Dsw @ qy))
             for f in range(3):
-                F = self._face_flux_one(u, k, f, field)
+                F = self._face_flux_one(u, k, f, field, t)
                 Lf = ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp]
                 r = r + g.sJ[k, f] / g.J[k] * (Lf @ F)
             if self.velocity is not None:
@@ -253,7 +288,12 @@ class Problem:
                     idx = ops.fmask[f]
                     vn = g.nx[k, f] * vx[idx] + g.ny[k, f] * vy[idx]
                     k2 = g.EToE[k, f]
-                    up = np.zeros(ops.Nfp) if k2 < 0 else u[k2, ops.fmask[g.EToF[k, f]]][::-1]
+                    if k2 >= 0:
+                        up = u[k2, ops.fmask[g.EToF[k, f]]][::-1]
+                    elif self.ghost is not None:
+                        up = self.ghost_values(xyn[k, idx], t, field)
+                    else:
+                        up = np.zeros(ops.Nfp)
                     fs = np.maximum(vn, 0.0) * uk[idx] + np.minimum(vn, 0.0) * up
                     Lf = ops.LIFT[:, f * ops.Nfp:(f + 1) * ops.Nfp]
                     r = r - g.sJ[k, f] / g.J[k] * (Lf @ fs)
@@ -306,11 +346,19 @@ class Problem:
 # Time integration
 # ----------------------------------------------------------------------------
 
-def rk4_step(rhs, u, dt):
-    k1 = rhs(u)
-    k2 = rhs(u + 0.5 * dt * k1)
-    k3 = rhs(u + 0.5 * dt * k2)
-    k4 = rhs(u + dt * k3)
+def rk4_step(rhs, u, dt, t=None):
+    """One classic RK4 step; with t given, rhs(u, t) is evaluated at the
+    stage times t, t + dt/2, t + dt/2, t + dt."""
+    if t is None:
+        k1 = rhs(u)
+        k2 = rhs(u + 0.5 * dt * k1)
+        k3 = rhs(u + 0.5 * dt * k2)
+        k4 = rhs(u + dt * k3)
+    else:
+        k1 = rhs(u, t)
+        k2 = rhs(u + 0.5 * dt * k1, t + 0.5 * dt)
+        k3 = rhs(u + 0.5 * dt * k2, t + 0.5 * dt)
+        k4 = rhs(u + dt * k3, t + dt)
     return u + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
@@ -327,10 +375,28 @@ LSERK_B = np.array([1432997174477.0 / 9575080441755.0,
                     2277821191437.0 / 14882151754819.0])
 
 
-def lserk_step(rhs, u, dt):
+def lserk_stage_times():
+    """Stage times c_s of the 2N-storage scheme: the stage values of
+    du/dt = 1 (u = t, integrated exactly), c_0 = 0, c_s = sum of B_j r_j with
+    r_j = A_j r_{j-1} + 1."""
+    c, r, out = 0.0, 0.0, []
+    for s in range(5):
+        out.append(c)
+        r = LSERK_A[s] * r + 1.0
+        c = c + LSERK_B[s] * r
+    return np.array(out)
+
+
+LSERK_C = lserk_stage_times()
+
+
+def lserk_step(rhs, u, dt, t=None):
+    """One step of the five-stage low-storage RK; with t given, rhs(u, t) is
+    evaluated at the stage times t + c_s dt."""
     res = np.zeros_like(u)
     for s in range(5):
-        res = LSERK_A[s] * res + dt * rhs(u)
+        r = rhs(u) if t is None else rhs(u, t + LSERK_C[s] * dt)
+        res = LSERK_A[s] * res + dt * r
         u = u + LSERK_B[s] * res
     return u
 

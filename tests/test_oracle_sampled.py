@@ -134,9 +134,9 @@ def test_spectrum_detects_planted_downwind_flux(monkeypatch):
     pr_rot = Problem(mesh.vxy, mesh.etov, 2, 0.0, velocity=ROT_SHIFT)
     orig = Problem.upwind_face_flux
 
-    def downwind(self, u):
+    def downwind(self, u, t=0.0, field=0):
         ops, g = self.ops, self.geom
-        up = orig(self, u)
+        up = orig(self, u, t, field)
         # f* = min(n.v,0) u- + max(n.v,0) u+: recover u+ from the upwind form
         xyn = g.physical(ops.rs)
         vx, vy = self.velocity_at(xyn)

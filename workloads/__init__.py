@@ -21,6 +21,21 @@ below are synthetic stand-ins with the same structure):
   a_kl = g_kl/(k^2+l^2), g ~ N(0,1); vanishes on the boundary of the square.
 * ``manufactured``: exp(-2 pi^2 D t) sin(pi x) sin(pi y), an exact solution of
   the heat equation with zero Dirichlet data on the unit square.
+* ``paper_grid(kind, n)``: the three grid families of the paper's results
+  (its figure is missing; this is the reading the text supports).  Grid a:
+  the square [0,10] x [-5,5] cut into n x n cells of two triangles (2 n^2
+  elements, every interior pair a parallelogram).  Grids b and c: a
+  quadrilateral (corners BL, BR, TR, TL) cut into the four triangles
+  (BL, BR, C), (BR, TR, C), (TR, TL, C), (TL, BL, C) around a centre point C,
+  each refined uniformly into n^2 congruent triangles (4 n^2 elements); pairs
+  across the four corner-to-centre lines ("the diagonals") are not
+  parallelograms.  Grid b: the square itself with C = (5, 0) (two triangles
+  across a diagonal form one larger triangle).  Grid c: the bottom-left and
+  top-right corners moved to (1.5, -3.5) and (11.5, 6.5) and C = (6.5, 1.5),
+  which leaves all four blocks, hence all elements, the same area.
+* ``gaussian``: the paper's travelling Gaussian pulse of mass M released at
+  time -D0/D, M / (4 pi (D t + D0)) exp(-|x - a t - x0|^2 / (4 (D t + D0))),
+  an exact solution of u_t + a . grad u = D lap u (a = 0: pure diffusion).
 """
 from __future__ import annotations
 
@@ -32,7 +47,7 @@ import numpy as np
 __all__ = [
     "Mesh", "split_square_mesh", "centroids", "circle_contrast_D",
     "loguniform_per_element", "fourier_modes", "manufactured",
-    "random_nodal", "seed_for", "WORKLOADS", "batch_problems",
+    "random_nodal", "seed_for", "WORKLOADS", "batch_problems", "paper_grid", "gaussian",
 ]
 
 
@@ -157,3 +172,57 @@ def batch_problems(n: int = 512, seed: int = seed_for(3, "batch"),
         out.append(dict(m=m, N=N, D=D, mesh_seed=seed * 1000 + 2 * i,
                         ic_seed=seed * 1000 + 2 * i + 1))
     return out
+
+
+def _refined_triangle(V0, V1, V2, n):
+    """Points and CCW triangles of the uniform n x n refinement of (V0,V1,V2)."""
+    idx = {}
+    pts = []
+    for j in range(n + 1):
+        for i in range(n + 1 - j):
+            idx[(i, j)] = len(pts)
+            pts.append(V0 + (i / n) * (V1 - V0) + (j / n) * (V2 - V0))
+    tris = []
+    for j in range(n):
+        for i in range(n - j):
+            tris.append((idx[(i, j)], idx[(i + 1, j)], idx[(i, j + 1)]))
+            if i + j <= n - 2:
+                tris.append((idx[(i + 1, j)], idx[(i + 1, j + 1)], idx[(i, j + 1)]))
+    return np.array(pts), np.array(tris, dtype=np.int64)
+
+
+def paper_grid(kind: str, n: int) -> Mesh:
+    """Grid family a, b or c at refinement n (see the module docstring)."""
+    if kind == "a":
+        m = split_square_mesh(n, 0.0)
+        vxy = m.vxy * np.array([10.0, 10.0]) + np.array([0.0, -5.0])
+        return Mesh(vxy=vxy, etov=m.etov)
+    if kind == "b":
+        BL, BR, TR, TL, C = (0.0, -5.0), (10.0, -5.0), (10.0, 5.0), (0.0, 5.0), (5.0, 0.0)
+    elif kind == "c":
+        BL, BR, TR, TL, C = (1.5, -3.5), (10.0, -5.0), (11.5, 6.5), (0.0, 5.0), (6.5, 1.5)
+    else:
+        raise ValueError(kind)
+    BL, BR, TR, TL, C = (np.array(p) for p in (BL, BR, TR, TL, C))
+    allp, allt, off = [], [], 0
+    for (A, B) in ((BL, BR), (BR, TR), (TR, TL), (TL, BL)):
+        p, t = _refined_triangle(A, B, C, n)
+        allp.append(p)
+        allt.append(t + off)
+        off += len(p)
+    P = np.vstack(allp)
+    T = np.vstack(allt)
+    # merge the points the blocks share (their common edges)
+    key = np.round(P, 9)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    inv = inv.ravel()
+    return Mesh(vxy=P[first], etov=inv[T].astype(np.int32))
+
+
+def gaussian(x, y, t, D=1.0, D0=2.0, x0=(5.0, 0.0), a=(0.0, 0.0), M=1.0):
+    """The Gaussian pulse of mass M released at time -D0/D at x0, advected with
+    constant velocity a: M / (4 pi (D t + D0)) exp(-|x - a t - x0|^2 / (4 (D t + D0)))."""
+    s = D * t + D0
+    dx = x - a[0] * t - x0[0]
+    dy = y - a[1] * t - x0[1]
+    return M / (4.0 * math.pi * s) * np.exp(-(dx * dx + dy * dy) / (4.0 * s))
