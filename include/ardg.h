@@ -26,8 +26,10 @@
  *    given in side 1's counter-clockwise face order (A -> B) with side 1's
  *    outward normal; side 2 sees the negated values in reverse order.
  *  - Boundary faces: zero Dirichlet data through a mirror ghost element (the
- *    element reflected across the face carrying -u at mirrored points); the
- *    paper specifies no boundary treatment.
+ *    element reflected across the face carrying -u at mirrored points), or,
+ *    after ardg_mesh_set_boundary_data, a prescribed exterior state on the
+ *    ghost's half of the reconstruction parallelogram; the paper specifies no
+ *    boundary treatment.
  *  - Device pointers are caller-owned device memory on the mesh's device.
  *    Host pointers are only read during the call (the library copies them).
  *  - Every call returns an ardg_status; 0 is success, negative values are
@@ -102,7 +104,11 @@ enum {
   ARDG_MESH_EDGE_GEOM = 2,   /* double [E_int][8]: P1x, P1y, mu1_A, mu1_B, mu2_B, mu2_A,
                                 gamma_R, gamma_S                                            */
   ARDG_MESH_BFACE_GEOM = 3,  /* double [E_bdy][6]: P1x, P1y, mu_A, mu_B, gamma_R, gamma_S  */
-  ARDG_MESH_ELEM_FACES = 4   /* int32 [K][3]: (edge index << 1) | side (0: side 1)         */
+  ARDG_MESH_ELEM_FACES = 4,  /* int32 [K][3]: (edge index << 1) | side (0: side 1)         */
+  ARDG_MESH_BFACE_GHOST_NODES = 5  /* double [E_bdy][Np][2]: physical points of the nodes of each
+                                boundary face's ghost sub-triangle (P2, B, A) (the reference
+                                nodes mapped with those vertices): where the exterior state
+                                of ardg_mesh_set_boundary_data is sampled                    */
 };
 
 typedef struct ardg_ops_s* ardg_ops;
@@ -177,6 +183,21 @@ ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfield
  * captured step graphs.  Errors: E_INVALID_ARG. */
 ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel);
 
+/* Prescribed exterior state at the boundary faces (inhomogeneous, time-
+ * dependent Dirichlet data), replacing the zero-Dirichlet mirror ghost: the
+ * ghost sub-triangle (P2, B, A) of each boundary face carries the state g at
+ * its nodes (ARDG_MESH_BFACE_GHOST_NODES), so the reconstruction is
+ * u~ = RDG(u1, g); the upwind convective flux takes u+ = g on the face.
+ * coeffs: host [nfields][E_bdy][Np][nt] doubles, the Chebyshev coefficients
+ * of g at each ghost node in tau = (2t - t_a - t_b) / (t_b - t_a) on
+ * [t_a, t_b] (copied).  Every evaluation (ardg_rhs_eval at its t, each stage
+ * of ardg_rk_step at its stage time) must lie in [t_a, t_b]; calls outside it
+ * fail with E_INVALID_ARG.  nt = 0 clears the data (back to zero Dirichlet).
+ * With element-wise D the ghost carries the element's coefficient.  Meshes
+ * with boundary data cannot join a batch.  Errors: E_INVALID_ARG, E_OOM. */
+ardg_status ardg_mesh_set_boundary_data(ardg_mesh mesh, int32_t nfields, int32_t nt, double t_a, double t_b,
+                                        const double* coeffs);
+
 /* Velocity of the convective term of eq. convection_diffusion, for every
  * field: ARDG_VEL_NONE, or ARDG_VEL_AFFINE with v(x,y) = (p0 + p2 x + p3 y,
  * p1 + p4 x + p5 y), params[6] on the host (v = (-y, x) is {0,0,0,-1,1,0}).
@@ -187,8 +208,9 @@ ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* p
  * precision ARDG_FP64: u_dev, rhs_dev are double [F][K][Np];
  * ARDG_FP32: float [F][K][Np] (operators and arithmetic in FP32, operators
  * built in FP64).  Enqueued on hip_stream (hipStream_t, NULL = default);
- * uses a flux buffer owned by the mesh.  t is accepted for API symmetry (no
- * term depends on time).  Errors: E_INVALID_ARG, E_UNSUPPORTED, E_HIP. */
+ * uses a flux buffer owned by the mesh.  t: the time of the prescribed
+ * boundary data (the only term that depends on time).  Errors:
+ * E_INVALID_ARG, E_UNSUPPORTED, E_HIP. */
 ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
                           void* rhs_dev, double t, void* hip_stream);
 
@@ -206,15 +228,16 @@ ardg_status ardg_rhs_eval_noalloc(ardg_mesh mesh, int32_t precision, int32_t nfi
                                   void* rhs_dev, double t, void* hip_stream);
 
 /* Edge fluxes only (the interior and boundary loop of Algorithm aRDG with the
- * diagonal flux; Algorithm 1 for element-wise D): flux_dev [F][E][Nfp] in the
+ * diagonal flux; Algorithms 1 and 2 for element-wise D): flux_dev [F][E][Nfp] in the
  * precision's type, D included, each edge's values multiplied by its surface
  * factor sJ = |edge| / 2 (the factor the surface integral of the weak form
  * applies, so that the element kernel needs no edge lengths).  Interior edges
  * first in ardg_mesh_export(EDGES) order, then boundary faces; values at the
  * edge's LGL nodes in element 1's counter-clockwise order, the sign of element
- * 1's outward normal.  A parity hook for the edge kernel. */
+ * 1's outward normal; t is the time of the prescribed boundary data.  A
+ * parity hook for the edge kernel. */
 ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfields,
-                                const void* u_dev, void* flux_dev, void* hip_stream);
+                                const void* u_dev, void* flux_dev, double t, void* hip_stream);
 
 /* Bytes of device workspace ardg_rk_step needs for (scheme, precision, nfields). */
 ardg_status ardg_rk_workspace_bytes(ardg_mesh mesh, int32_t scheme, int32_t precision,
@@ -227,8 +250,10 @@ ardg_status ardg_rk_workspace_bytes(ardg_mesh mesh, int32_t scheme, int32_t prec
  * of ardg_rk_workspace_bytes bytes, 256-byte aligned.  The step loop is
  * captured once per (scheme, precision, nfields, buffers, step count, dt)
  * into HIP graphs of at most 256 steps, replayed as often as nsteps needs
- * (plus one graph for the remainder).  Errors: E_INVALID_ARG, E_UNSUPPORTED,
- * E_HIP. */
+ * (plus one graph for the remainder).  t0: the time at the start, for the
+ * prescribed boundary data (evaluated at each stage's time: RK4 0, dt/2,
+ * dt/2, dt; the low-storage scheme's stage times).  Errors: E_INVALID_ARG,
+ * E_UNSUPPORTED, E_HIP. */
 ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields,
                          double* u_dev, void* work_dev, double t0, double dt, int32_t nsteps,
                          void* hip_stream);

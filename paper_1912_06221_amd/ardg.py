@@ -26,6 +26,7 @@ OPS_NODES, OPS_V, OPS_DR, OPS_DS, OPS_MASS, OPS_LIFT = 0, 1, 2, 3, 4, 5
 OPS_FACE_NODES, OPS_ROT_PERM, OPS_RECON_A, OPS_RECON_R = 6, 7, 8, 9
 OPS_RECON_GRAD, OPS_ALG1_GRAD, OPS_N2B, OPS_ALG2_W = 10, 11, 12, 13
 MESH_EDGES, MESH_BFACES, MESH_EDGE_GEOM, MESH_BFACE_GEOM, MESH_ELEM_FACES = 0, 1, 2, 3, 4
+MESH_BFACE_GHOST_NODES = 5
 
 
 class ArdgError(RuntimeError):
@@ -55,9 +56,10 @@ SIGNATURES = {
     "ardg_mesh_set_diffusion": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
     "ardg_mesh_set_velocity": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "ardg_mesh_set_kernels": (c_int32, [c_void_p, c_int32]),
+    "ardg_mesh_set_boundary_data": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_double, POINTER(c_double)]),
     "ardg_rhs_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
     "ardg_rhs_eval_noalloc": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
-    "ardg_edge_flux_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "ardg_edge_flux_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
     "ardg_rk_workspace_bytes": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_int64)]),
     "ardg_rk_step": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_double,
                                c_double, c_int32, c_void_p]),
@@ -198,21 +200,32 @@ class Mesh:
     def set_kernels(self, edge_kernel: int = EDGE_AUTO):
         _check(lib().ardg_mesh_set_kernels(self.handle, edge_kernel))
 
+    def set_boundary_data(self, coeffs, t_a: float, t_b: float):
+        """Prescribed exterior state: coeffs [F][E_bdy][Np][nt] Chebyshev
+        coefficients in time on [t_a, t_b] (None clears)."""
+        if coeffs is None:
+            _check(lib().ardg_mesh_set_boundary_data(self.handle, 1, 0, 0.0, 1.0, None))
+            return
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        if c.ndim != 4 or c.shape[1] != self.E_bdy or c.shape[2] != self.Np:
+            raise ValueError("coeffs must be [F][E_bdy][Np][nt]")
+        _check(lib().ardg_mesh_set_boundary_data(self.handle, c.shape[0], c.shape[3], t_a, t_b, _dptr(c)))
+
     # ---- device calls (torch tensors on this mesh's device) ---------------
-    def rhs_eval(self, u, out, precision: int = FP64, nfields: int = 1, stream=None):
-        _check(lib().ardg_rhs_eval(self.handle, precision, nfields, _ptr(u), _ptr(out), 0.0,
+    def rhs_eval(self, u, out, precision: int = FP64, nfields: int = 1, stream=None, t: float = 0.0):
+        _check(lib().ardg_rhs_eval(self.handle, precision, nfields, _ptr(u), _ptr(out), t,
                                    _stream(stream)))
         return out
 
-    def rhs_eval_noalloc(self, u, out, precision: int = FP64, nfields: int = 1, stream=None):
+    def rhs_eval_noalloc(self, u, out, precision: int = FP64, nfields: int = 1, stream=None, t: float = 0.0):
         """rhs_eval with the fluxes in the library's device scratch array (no
         allocation)."""
-        _check(lib().ardg_rhs_eval_noalloc(self.handle, precision, nfields, _ptr(u), _ptr(out), 0.0,
+        _check(lib().ardg_rhs_eval_noalloc(self.handle, precision, nfields, _ptr(u), _ptr(out), t,
                                            _stream(stream)))
         return out
 
-    def edge_flux_eval(self, u, flux, precision: int = FP64, nfields: int = 1, stream=None):
-        _check(lib().ardg_edge_flux_eval(self.handle, precision, nfields, _ptr(u), _ptr(flux),
+    def edge_flux_eval(self, u, flux, precision: int = FP64, nfields: int = 1, stream=None, t: float = 0.0):
+        _check(lib().ardg_edge_flux_eval(self.handle, precision, nfields, _ptr(u), _ptr(flux), t,
                                          _stream(stream)))
         return flux
 

@@ -144,6 +144,14 @@ struct ardg_mesh_s {
   int nfields_D = 1;
   void* flux_scratch = nullptr;
   size_t flux_scratch_bytes = 0;
+  // prescribed exterior data: Chebyshev coefficients in time [F][E_bdy][Np][nt]
+  // on [ghost_ta, ghost_tb], the state at the current stage time, and the
+  // start time of the current step (device scalar advanced by the step graphs)
+  double* ghost_coef = nullptr;
+  double* ghost_val = nullptr;
+  double* tdev = nullptr;
+  int ghost_nt = 0, ghost_nf = 0;
+  double ghost_ta = 0.0, ghost_tb = 0.0;
   hipStream_t cap_stream = nullptr;
   std::map<GraphKey, hipGraphExec_t> graphs;
   uint64_t version = 0;
@@ -157,6 +165,9 @@ struct ardg_mesh_s {
       if (Delem_dev) (void)hipFree(Delem_dev);
       if (vn_dev) (void)hipFree(vn_dev);
       if (flux_scratch) (void)hipFree(flux_scratch);
+      if (ghost_coef) (void)hipFree(ghost_coef);
+      if (ghost_val) (void)hipFree(ghost_val);
+      if (tdev) (void)hipFree(tdev);
     }
   }
   void drop_graphs() {
@@ -394,6 +405,25 @@ ardg_status ardg_mesh_export(ardg_mesh mesh, int32_t which, void* dst, int64_t c
         dv.insert(dv.end(), row, row + 8);
       }
       break;
+    case ARDG_MESH_BFACE_GHOST_NODES: {
+      is_int = false;
+      const int rotv[3][3] = {{2, 0, 1}, {0, 1, 2}, {1, 2, 0}};
+      const RefOps& o = mesh->ro;
+      for (int64_t b = 0; b < h.E_bdy; ++b) {
+        const int64_t k = h.bk[b];
+        const int f = h.bf[b];
+        const int ia = h.etov[3 * k + rotv[f][1]], ib = h.etov[3 * k + rotv[f][2]];
+        const double ax = h.vxy[2 * ia], ay = h.vxy[2 * ia + 1], bx = h.vxy[2 * ib], by = h.vxy[2 * ib + 1];
+        // the ghost sub-triangle (P2, B, A) with P2 = A + B - P1
+        const double p2x = ax + bx - h.bP1[2 * b], p2y = ay + by - h.bP1[2 * b + 1];
+        for (int n = 0; n < o.Np; ++n) {
+          const double l1 = -0.5 * (o.r[n] + o.s[n]), l2 = 0.5 * (o.r[n] + 1.0), l3 = 0.5 * (o.s[n] + 1.0);
+          dv.push_back(l1 * p2x + l2 * bx + l3 * ax);
+          dv.push_back(l1 * p2y + l2 * by + l3 * ay);
+        }
+      }
+      break;
+    }
     case ARDG_MESH_BFACE_GEOM:
       is_int = false;
       for (int64_t b = 0; b < h.E_bdy; ++b) {
@@ -485,6 +515,65 @@ ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* p
   return ARDG_OK;
 }
 
+ardg_status ardg_mesh_set_boundary_data(ardg_mesh mesh, int32_t nfields, int32_t nt, double t_a, double t_b,
+                                        const double* coeffs) {
+  if (!mesh) return fail(ARDG_E_INVALID_ARG, "set_boundary_data: null handle");
+  if (nt == 0) {
+    mesh->dm.ghost = nullptr;
+    mesh->ghost_nt = mesh->ghost_nf = 0;
+    mesh->drop_graphs();
+    return ARDG_OK;
+  }
+  if (nt < 1 || nt > 64) return fail(ARDG_E_INVALID_ARG, "set_boundary_data: nt must be in 1..64 (0 clears)");
+  if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "set_boundary_data: nfields");
+  if (!coeffs) return fail(ARDG_E_INVALID_ARG, "set_boundary_data: null coefficients");
+  if (!(std::isfinite(t_a) && std::isfinite(t_b) && t_b > t_a))
+    return fail(ARDG_E_INVALID_ARG, "set_boundary_data: need finite t_a < t_b");
+  const size_t nv = (size_t)nfields * mesh->hm.E_bdy * mesh->ro.Np;
+  for (size_t i = 0; i < nv * nt; ++i)
+    if (!std::isfinite(coeffs[i])) return fail(ARDG_E_INVALID_ARG, "set_boundary_data: non-finite coefficient");
+  mesh->drop_graphs();
+  if (mesh->device >= 0) {
+    DeviceGuard g(mesh->device);
+    if (mesh->ghost_coef) (void)hipFree(mesh->ghost_coef);
+    if (mesh->ghost_val) (void)hipFree(mesh->ghost_val);
+    mesh->ghost_coef = mesh->ghost_val = nullptr;
+    mesh->dm.ghost = nullptr;
+    ardg_status s = upload(coeffs, nv * nt, &mesh->ghost_coef);
+    if (s != ARDG_OK) return s;
+    if (nv) {
+      hipError_t e = hipMalloc((void**)&mesh->ghost_val, nv * sizeof(double));
+      if (e != hipSuccess) return fail(ARDG_E_OOM, "set_boundary_data: allocation failed");
+    }
+    if (!mesh->tdev) {
+      hipError_t e = hipMalloc((void**)&mesh->tdev, sizeof(double));
+      if (e != hipSuccess) return fail(ARDG_E_OOM, "set_boundary_data: allocation failed");
+    }
+    // E_bdy == 0: a non-null marker still routes the launches through the
+    // (empty) evaluation; no boundary face reads it
+    mesh->dm.ghost = mesh->ghost_val ? mesh->ghost_val : mesh->tdev;
+  }
+  mesh->ghost_nt = nt;
+  mesh->ghost_nf = nfields;
+  mesh->ghost_ta = t_a;
+  mesh->ghost_tb = t_b;
+  return ARDG_OK;
+}
+
+// Exterior state at time toff (+ the device step time when tbase is used).
+static hipError_t ghost_eval(ardg_mesh mesh, int nfields, bool use_tbase, double toff, hipStream_t st) {
+  if (!mesh->dm.ghost) return hipSuccess;
+  const int64_t n = (int64_t)nfields * mesh->hm.E_bdy * mesh->ro.Np;
+  return launch_ghost_eval(mesh->ghost_coef, mesh->ghost_val, n, mesh->ghost_nt, mesh->ghost_ta, mesh->ghost_tb,
+                           use_tbase ? mesh->tdev : nullptr, toff, st);
+}
+
+static bool time_in_range(ardg_mesh mesh, double t0, double t1) {
+  if (!mesh->dm.ghost) return true;
+  const double tol = 1e-9 * std::max(1.0, std::fabs(mesh->ghost_tb - mesh->ghost_ta));
+  return t0 >= mesh->ghost_ta - tol && t1 <= mesh->ghost_tb + tol;
+}
+
 static ardg_status check_compute(ardg_mesh mesh, int32_t precision, int32_t nfields) {
   if (!mesh) return fail(ARDG_E_INVALID_ARG, "null mesh");
   if (mesh->device < 0) return fail(ARDG_E_INVALID_ARG, "mesh was created host-only (device -1)");
@@ -494,6 +583,8 @@ static ardg_status check_compute(ardg_mesh mesh, int32_t precision, int32_t nfie
   if (mesh->dm.dmode != DM_CONST && nfields != 1) return fail(ARDG_E_INVALID_ARG, "element-wise D is for one field");
   if (mesh->dm.dmode == DM_CONST && nfields > mesh->nfields_D && mesh->nfields_D != 1)
     return fail(ARDG_E_INVALID_ARG, "more fields than diffusion coefficients");
+  if (mesh->dm.ghost && nfields > mesh->ghost_nf)
+    return fail(ARDG_E_INVALID_ARG, "more fields than the boundary data was given for");
   return ARDG_OK;
 }
 
@@ -520,22 +611,24 @@ ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel) {
 }
 
 ardg_status ardg_edge_flux_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
-                                void* flux_dev, void* hip_stream) {
+                                void* flux_dev, double t, void* hip_stream) {
   ardg_status s = check_compute(mesh, precision, nfields);
   if (s != ARDG_OK) return s;
   if (!u_dev || !flux_dev) return fail(ARDG_E_INVALID_ARG, "edge_flux_eval: null buffer");
+  if (!time_in_range(mesh, t, t)) return fail(ARDG_E_INVALID_ARG, "edge_flux_eval: t outside the boundary data's interval");
   DeviceGuard g(mesh->device);
   hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(ghost_eval(mesh, nfields, false, t, st), "boundary data launch");
   HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux_dev, st), "edge flux launch");
   return ARDG_OK;
 }
 
 ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
                           void* rhs_dev, double t, void* hip_stream) {
-  (void)t;
   ardg_status s = check_compute(mesh, precision, nfields);
   if (s != ARDG_OK) return s;
   if (!u_dev || !rhs_dev) return fail(ARDG_E_INVALID_ARG, "rhs_eval: null buffer");
+  if (!time_in_range(mesh, t, t)) return fail(ARDG_E_INVALID_ARG, "rhs_eval: t outside the boundary data's interval");
   DeviceGuard g(mesh->device);
   const size_t ts = precision == ARDG_FP64 ? 8 : 4;
   const size_t fb = align256((size_t)nfields * (mesh->hm.E_int + mesh->hm.E_bdy) * mesh->ro.Nfp * ts);
@@ -543,6 +636,7 @@ ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, co
   if (s != ARDG_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   void* flux = mesh->flux_scratch;
+  HIP_TRY(ghost_eval(mesh, nfields, false, t, st), "boundary data launch");
   HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux, st), "edge flux launch");
   Epilogue epi;
   epi.kind = EPI_RHS;
@@ -553,10 +647,11 @@ ardg_status ardg_rhs_eval(ardg_mesh mesh, int32_t precision, int32_t nfields, co
 
 ardg_status ardg_rhs_eval_noalloc(ardg_mesh mesh, int32_t precision, int32_t nfields, const void* u_dev,
                                   void* rhs_dev, double t, void* hip_stream) {
-  (void)t;
   ardg_status s = check_compute(mesh, precision, nfields);
   if (s != ARDG_OK) return s;
   if (!u_dev || !rhs_dev) return fail(ARDG_E_INVALID_ARG, "rhs_eval_noalloc: null buffer");
+  if (!time_in_range(mesh, t, t))
+    return fail(ARDG_E_INVALID_ARG, "rhs_eval_noalloc: t outside the boundary data's interval");
   const size_t ts = precision == ARDG_FP64 ? 8 : 4;
   const size_t fb = (size_t)nfields * (mesh->hm.E_int + mesh->hm.E_bdy) * mesh->ro.Nfp * ts;
   if (fb > kNoallocScratchBytes)
@@ -568,6 +663,7 @@ ardg_status ardg_rhs_eval_noalloc(ardg_mesh mesh, int32_t precision, int32_t nfi
   void* flux = nullptr;
   HIP_TRY(noalloc_scratch(mesh->device, &flux), "rhs_eval_noalloc: scratch address");
   hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(ghost_eval(mesh, nfields, false, t, st), "boundary data launch");
   HIP_TRY(launch_edge_flux(mesh->dm, precision, nfields, u_dev, flux, st), "edge flux launch");
   Epilogue epi;
   epi.kind = EPI_RHS;
@@ -636,6 +732,19 @@ static StageIO stage_io(int scheme, bool f64, int s, double* u, void* v) {
   return io;
 }
 
+// Stage time offsets c_s (in units of dt): classic RK4 0, 1/2, 1/2, 1; the
+// low-storage scheme's from its coefficients (the stage values of
+// du/dt = 1, integrated exactly: r_s = A_s r_{s-1} + 1, c_{s+1} = c_s + B_s r_s).
+static double stage_time(int scheme, int s) {
+  if (scheme == ARDG_RK4) return s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5);
+  double c = 0.0, r = 0.0;
+  for (int j = 0; j < s; ++j) {
+    r = kLsA[j] * r + 1.0;
+    c += kLsB[j] * r;
+  }
+  return c;
+}
+
 static void stage_epilogue(int scheme, int s, Epilogue& epi) {
   epi.stage = s;
   if (scheme == ARDG_RK4) {
@@ -668,11 +777,17 @@ static hipError_t enqueue_steps(ardg_mesh mesh, int scheme, int precision, int n
   for (int step = 0; step < nsteps; ++step) {
     for (int s = 0; s < nst; ++s) {
       const StageIO io = stage_io(scheme, f64, s, u, w.v);
+      e = ghost_eval(mesh, nfields, true, stage_time(scheme, s) * dt, st);
+      if (e != hipSuccess) return e;
       e = launch_edge_flux(mesh->dm, precision, nfields, io.vin, w.flux, st);
       if (e != hipSuccess) return e;
       stage_epilogue(scheme, s, epi);
       epi.vnext = io.vnext;
       e = launch_element(mesh->dm, precision, nfields, io.vin, w.flux, epi, st);
+      if (e != hipSuccess) return e;
+    }
+    if (mesh->dm.ghost) {
+      e = launch_advance_time(mesh->tdev, dt, st);
       if (e != hipSuccess) return e;
     }
   }
@@ -734,7 +849,6 @@ static ardg_status step_graphs(ardg_mesh mesh, int scheme, int precision, int nf
 
 ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int32_t nfields, double* u_dev,
                          void* work_dev, double t0, double dt, int32_t nsteps, void* hip_stream) {
-  (void)t0;
   ardg_status s = check_compute(mesh, precision, nfields);
   if (s != ARDG_OK) return s;
   if (scheme != ARDG_RK4 && scheme != ARDG_LSERK54) return fail(ARDG_E_INVALID_ARG, "unknown scheme");
@@ -742,10 +856,13 @@ ardg_status ardg_rk_step(ardg_mesh mesh, int32_t scheme, int32_t precision, int3
   if (((uintptr_t)work_dev & 255) != 0) return fail(ARDG_E_INVALID_ARG, "rk_step: work_dev not 256-byte aligned");
   if (nsteps < 0 || !std::isfinite(dt)) return fail(ARDG_E_INVALID_ARG, "rk_step: bad nsteps or dt");
   if (nsteps == 0) return ARDG_OK;
+  if (!time_in_range(mesh, std::min(t0, t0 + nsteps * dt), std::max(t0, t0 + nsteps * dt)))
+    return fail(ARDG_E_INVALID_ARG, "rk_step: the steps leave the boundary data's time interval");
   DeviceGuard g(mesh->device);
   hipGraphExec_t ex_full = nullptr, ex_rem = nullptr;
   s = step_graphs(mesh, scheme, precision, nfields, u_dev, work_dev, dt, nsteps, &ex_full, &ex_rem);
   if (s != ARDG_OK) return s;
+  if (mesh->dm.ghost) HIP_TRY(launch_set_time(mesh->tdev, t0, (hipStream_t)hip_stream), "time launch");
   const int chunk = std::min<int>(nsteps, kGraphSteps);
   for (int i = 0; i < nsteps / chunk; ++i)
     HIP_TRY(hipGraphLaunch(ex_full, (hipStream_t)hip_stream), "hipGraphLaunch");
@@ -785,7 +902,8 @@ static hipError_t capture_stages(ardg_mesh mesh, int scheme, int precision, int 
     const StageIO io = stage_io(scheme, f64, sidx, u_dev, w.v);
     stage_epilogue(scheme, sidx, epi);
     epi.vnext = io.vnext;
-    if (with_edge) ec = launch_edge_flux(mesh->dm, precision, nfields, io.vin, w.flux, cs);
+    if (with_edge) ec = ghost_eval(mesh, nfields, false, 0.0 + stage_time(scheme, sidx) * dt, cs);
+    if (with_edge && ec == hipSuccess) ec = launch_edge_flux(mesh->dm, precision, nfields, io.vin, w.flux, cs);
     if (ec == hipSuccess) ec = launch_element(mesh->dm, precision, nfields, io.vin, w.flux, epi, cs);
   }
   hipGraph_t graph = nullptr;
@@ -1162,8 +1280,9 @@ ardg_status ardg_batch_create(const ardg_mesh* meshes, int32_t n, const char* tu
     if (!m) return fail(ARDG_E_INVALID_ARG, "batch_create: null mesh");
     if (m->device < 0 || m->device != dev)
       return fail(ARDG_E_INVALID_ARG, "batch_create: meshes must live on one device");
-    if (m->dm.dmode != DM_CONST || m->dm.conv || m->nfields_D != 1)
-      return fail(ARDG_E_UNSUPPORTED, "batch_create: meshes need one field, constant D and no velocity");
+    if (m->dm.dmode != DM_CONST || m->dm.conv || m->nfields_D != 1 || m->dm.ghost)
+      return fail(ARDG_E_UNSUPPORTED,
+                  "batch_create: meshes need one field, constant D, no velocity and zero Dirichlet data");
   }
   try {
     auto b = std::make_unique<ardg_batch_s>();

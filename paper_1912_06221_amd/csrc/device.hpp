@@ -77,6 +77,10 @@ struct DevMesh {
   const int* elem_face = nullptr; // [3][K] (edge << 1) | side
   const double* Delem = nullptr;  // [K] when D is element-wise
   const double2* vn = nullptr;    // [E] n1.v at A and at B (affine velocity)
+  // prescribed exterior state at the nodes of each boundary face's ghost
+  // sub-triangle (P2, B, A), [F][E_bdy][Np] at the current stage time, or
+  // null (zero Dirichlet data through the mirror ghost)
+  const double* ghost = nullptr;
   const double* ops64 = nullptr;
   const float* ops32 = nullptr;
   int dmode = DM_CONST;           // DiffusionMode
@@ -144,6 +148,15 @@ hipError_t launch_batch_element_mfma(int N, bool fp64, int grid, const BatchProb
 // Element kernel on the matrix cores (same contract as launch_element).
 hipError_t launch_element_mfma(const DevMesh& m, int prec, int nfields, const void* vin, const void* flux,
                                const Epilogue& epi, hipStream_t st);
+// Exterior state at the ghost nodes from its Chebyshev expansion in time on
+// [ta, tb] (coeffs [n][nt], out [n]): at t = *tbase + toff when tbase is
+// given (the stage time inside captured step graphs), else at t = toff.
+hipError_t launch_ghost_eval(const double* coeffs, double* out, int64_t n, int nt, double ta, double tb,
+                             const double* tbase, double toff, hipStream_t st);
+// *t = value (one thread).
+hipError_t launch_set_time(double* t, double value, hipStream_t st);
+// *t += dt (one thread): the end of a step.
+hipError_t launch_advance_time(double* t, double dt, hipStream_t st);
 // Copy an FP64 state into an FP32 copy (stage input of the FP32 mode).
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // Count non-finite values of an FP64 array into *count_dev (int).

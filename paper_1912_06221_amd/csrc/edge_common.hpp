@@ -231,11 +231,15 @@ __device__ inline T alg2_coef(cptr<T> op, int j, T D1, T D2) {
 // element's sub-triangle on its mirror-ghost rhombus and the boundary
 // reconstruction operator (Algorithm 1: its boundary blocks; Algorithm 2:
 // the constant-coefficient operator times the coefficient reconstructed
-// from the element's D on both halves).  F receives sJ * flux, trace the
-// element's values on the face, vn the stored n.v (convection).
+// from the element's D on both halves).  With prescribed exterior data the
+// ghost sub-triangle carries that state instead of the mirror image: the
+// reconstruction operator's side-2 columns act on its Bernstein
+// coefficients, and gtrace receives its values on the face (side-1 order)
+// for the upwind flux.  F receives sJ * flux, trace the element's values on
+// the face, vn the stored n.v (convection).
 template <int N, typename T, int DM>
 __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, int field,
-                                     const T* __restrict__ uf, T* F, T* trace, double2& vn) {
+                                     const T* __restrict__ uf, T* F, T* trace, double2& vn, T* gtrace) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
   const int64_t b = e - m.E_int;
@@ -252,6 +256,34 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
   matvec<Np, Np, T>(op + L.n2b, t, c);
   decasteljau<N, T>(c, mu);
   const T gR = (T)g.x, gS = (T)g.y;
+  if (m.ghost) {
+    // exterior state on the ghost sub-triangle (P2, B, A): nodal -> Bernstein
+    T gv[Np], bg[Np];
+    const double* gs = m.ghost + ((int64_t)field * m.E_bdy + b) * Np;
+#pragma unroll
+    for (int n = 0; n < Np; ++n) gv[n] = (T)gs[n];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) gtrace[j] = gv[lat(N, j, N - j)];
+    matvec<Np, Np, T>(op + L.n2b, gv, bg);
+    constexpr int R = DM == DM_ALG1 ? 4 * Nfp : 2 * Nfp;
+    T g1[R], g2[R];
+    matvec_ld<R, Np, 2 * Np, T>(op + (DM == DM_ALG1 ? L.u1r : L.kr), c, g1);
+    matvec_ld<R, Np, 2 * Np, T>(op + (DM == DM_ALG1 ? L.u1r : L.kr) + Np, bg, g2);
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      if (DM == DM_ALG1) {
+        // the ghost carries the element's D: D1 = D2 = D
+        F[j] = D * (gR * (g1[j] + g2[j]) + gS * (g1[Nfp + j] + g2[Nfp + j]) -
+                    gR * (g1[2 * Nfp + j] + g2[2 * Nfp + j]) - gS * (g1[3 * Nfp + j] + g2[3 * Nfp + j]));
+      } else {
+        const T Dj = DM == DM_ALG2 ? alg2_coef<N, T>(op, j, D, D) : D;
+        F[j] = Dj * (gR * (g1[j] + g2[j]) + gS * (g1[Nfp + j] + g2[Nfp + j]));
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j <= N; ++j) gtrace[j] = T(0);   // u+ = 0 outside the domain
   T gb[2 * Nfp];
   matvec<2 * Nfp, Np, T>(op + (DM == DM_ALG1 ? L.ubr : L.kbr), c, gb);
 #pragma unroll
@@ -261,8 +293,8 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
   }
 }
 
-// Boundary face e with its upwind convective flux (u+ = 0 outside), written
-// to the flux array.
+// Boundary face e with its upwind convective flux (u+ outside: 0, or the
+// prescribed exterior state), written to the flux array.
 template <int N, typename T, int DM>
 __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ u, T* __restrict__ flux) {
@@ -270,15 +302,15 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   constexpr int Np = L.Np, Nfp = L.Nfp;
   const int64_t E = m.E_int + m.E_bdy;
   const T* uf = u + (int64_t)field * m.K * Np;
-  T F[Nfp], tr[Nfp];
+  T F[Nfp], tr[Nfp], gtr[Nfp];
   double2 vn = make_double2(0.0, 0.0);
-  boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr, vn);
+  boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr, vn, gtr);
   if (m.conv) {
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
       const T tau = op[L.tau + j];
       const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
-      if (vnj > (T)0) F[j] -= vnj * tr[j];
+      F[j] -= vnj * ((vnj > (T)0) ? tr[j] : gtr[j]);
     }
   }
   T* out = flux + ((int64_t)field * E + e) * Nfp;
@@ -365,9 +397,11 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       }
     }
   } else {
-    boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr1, vn);
+    T gtr[Nfp];
+    boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr1, vn, gtr);
+    // side 2's trace in its own order: u+ outside (0, or the exterior state)
 #pragma unroll
-    for (int j = 0; j < Nfp; ++j) tr2[j] = 0;   // u+ = 0 outside the domain
+    for (int j = 0; j < Nfp; ++j) tr2[j] = gtr[N - j];
   }
   if (m.conv) {
     // upwind flux f* = max(n.v,0) u- + min(n.v,0) u+, subtracted from the

@@ -425,6 +425,27 @@ __global__ void batch_to_f32_kernel(const BatchProb* __restrict__ probs, const i
   }
 }
 
+// Chebyshev series of the prescribed exterior state in tau = (2t - ta - tb) /
+// (tb - ta), one value per thread (Clenshaw's recurrence).
+__global__ void ghost_eval_kernel(const double* __restrict__ coeffs, double* __restrict__ out, int64_t n,
+                                  int nt, double ta, double tb, const double* __restrict__ tbase, double toff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double t = (tbase ? tbase[0] : 0.0) + toff;
+  const double tau = (2.0 * t - ta - tb) / (tb - ta);
+  const double* c = coeffs + i * nt;
+  double b1 = 0.0, b2 = 0.0;
+  for (int k = nt - 1; k >= 1; --k) {
+    const double b0 = c[k] + 2.0 * tau * b1 - b2;
+    b2 = b1;
+    b1 = b0;
+  }
+  out[i] = c[0] + tau * b1 - b2;
+}
+
+__global__ void set_time_kernel(double* t, double value) { t[0] = value; }
+__global__ void advance_time_kernel(double* t, double dt) { t[0] += dt; }
+
 __global__ void to_f32_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = (float)s[i];
@@ -603,6 +624,24 @@ hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int ni
                                int Np, int grid, hipStream_t st) {
   if (nitems == 0) return hipSuccess;
   hipLaunchKernelGGL(batch_to_f32_kernel, dim3(grid), dim3(256), 0, st, probs, items, nitems, tile, Np);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_eval(const double* coeffs, double* out, int64_t n, int nt, double ta, double tb,
+                             const double* tbase, double toff, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(ghost_eval_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, coeffs, out, n, nt,
+                     ta, tb, tbase, toff);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_time(double* t, double value, hipStream_t st) {
+  hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(1), 0, st, t, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_time(double* t, double dt, hipStream_t st) {
+  hipLaunchKernelGGL(advance_time_kernel, dim3(1), dim3(1), 0, st, t, dt);
   return hipGetLastError();
 }
 

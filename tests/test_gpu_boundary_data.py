@@ -1,0 +1,129 @@
+"""Parity of the library's prescribed exterior data at boundary faces with
+the oracle: edge fluxes and right-hand sides at a given time, and RK4 /
+low-storage stepping whose stages evaluate the data at their own times.
+
+The exterior state is a polynomial of low degree in t, so the library's
+Chebyshev representation reproduces it exactly and the comparison is to the
+FP64 parity bar (1e-12)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from boundary_data import chebyshev_coefficients
+from gpu_common import library_mesh, make_case, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+PRECS = {"fp64": (0, 1e-12), "fp32": (1, 2e-4), "bf16x3": (2, 5e-2)}
+
+
+def _g(x, y, t, f):
+    return np.sin(1.3 * x + 0.4 + f) * np.cos(0.7 * y) * (1.0 + 0.5 * t - 0.3 * t * t)
+
+
+def _setup(m, N, D_mode, vel, nf, seed, t_a=0.0, t_b=1.0, Dc=0.4):
+    from paper_1912_06221_amd import ardg
+    mesh, D = make_case(m, 0.2, N, D_mode, velocity=vel, nfields=nf, seed=seed)
+    if D_mode == "const":
+        D = [Dc * (1 + f) for f in range(nf)]
+    ops, lm = library_mesh(mesh, N, D_mode, D, vel, nf)
+    X = lm.export(ardg.MESH_BFACE_GHOST_NODES).reshape(lm.E_bdy, ops.Np, 2)
+    lm.set_boundary_data(chebyshev_coefficients(_g, X, t_a, t_b, 4, nf), t_a, t_b)
+    from oracle.rhs import Problem
+    pr = Problem(mesh.vxy, mesh.etov, N, D, D_mode="element" if D_mode.startswith("element") else "const",
+                 velocity=vel, nfields=nf, alg=2 if D_mode == "element2" else 1, ghost=_g)
+    return mesh, ops, lm, pr
+
+
+CASES = [
+    # m, N, D_mode, velocity, nfields
+    (8, 1, "const", None, 1),
+    (8, 2, "const", None, 2),
+    (7, 3, "const", (0.7, -0.4, 0.0, 0.0, 0.0, 0.0), 1),
+    (6, 4, "element", None, 1),
+    (6, 3, "element2", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0), 1),
+    (5, 6, "const", None, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"m{c[0]}-N{c[1]}-{c[2]}-{'conv' if c[3] else 'diff'}-F{c[4]}")
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_boundary_data_flux_and_rhs(case, prec):
+    import torch
+    from paper_1912_06221_amd import ardg
+    m, N, D_mode, vel, nf = case
+    print(f"boundary data {case} {prec}", flush=True)
+    mesh, ops, lm, pr = _setup(m, N, D_mode, vel, nf, seed=7 * m + N)
+    u = W.random_nodal((nf, mesh.K, ops.Np), seed=m + N)
+    t = 0.37
+    p, tol = PRECS[prec]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ud = to_dev(u, dt)
+    rhs = torch.empty_like(ud)
+    lm.rhs_eval(ud, rhs, precision=p, nfields=nf, t=t)
+    ro = pr.rhs(u, t)
+    err = np.abs(to_np(rhs) - ro).max() / np.abs(ro).max()
+    print(f"  rhs rel err {err:.2e}", flush=True)
+    assert err <= tol
+    # the same through every edge kernel implementation (FP64)
+    if prec == "fp64":
+        for kern in (ardg.EDGE_SPLIT, ardg.EDGE_LANE, ardg.EDGE_MFMA, ardg.EDGE_SPLIT_MFMA):
+            lm.set_kernels(kern)
+            lm.rhs_eval(ud, rhs, precision=p, nfields=nf, t=t)
+            e2 = np.abs(to_np(rhs) - ro).max() / np.abs(ro).max()
+            print(f"  kernel {kern}: rhs rel err {e2:.2e}", flush=True)
+            assert e2 <= tol
+        lm.set_kernels(ardg.EDGE_AUTO)
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "lserk"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_boundary_data_time_stepping(scheme, prec):
+    """Stepping from t0 = 0.1 in graphs (a second call continues in time):
+    each stage sees the data at its own time."""
+    from oracle.rhs import lserk_step, mass_norm, rk4_step
+    from paper_1912_06221_amd import ardg
+    print(f"boundary data stepping {scheme} {prec}", flush=True)
+    N = 3
+    # D and dt inside the explicit stability limit (rho ~ 6e2 here)
+    mesh, ops, lm, pr = _setup(6, N, "const", (0.5, 0.2, 0.0, 0.0, 0.0, 0.0), 1, seed=5, Dc=4e-3)
+    xy = pr.nodal_xy()
+    u0 = np.sin(xy[..., 0] * 2.1) * np.cos(xy[..., 1] * 1.3)
+    sch = ardg.RK4 if scheme == "rk4" else ardg.LSERK54
+    step = rk4_step if scheme == "rk4" else lserk_step
+    p = ardg.FP64 if prec == "fp64" else ardg.FP32
+    tol = 1e-12 if prec == "fp64" else 2e-4
+    dt, n, t0 = 1e-3, 30, 0.1
+    ud = to_dev(u0[None])
+    work = ardg.alloc_workspace(lm.workspace_bytes(sch, p, 1), ud.device)
+    lm.rk_step(ud, work, dt, n, scheme=sch, precision=p, t0=t0)
+    lm.rk_step(ud, work, dt, n, scheme=sch, precision=p, t0=t0 + n * dt)
+    uo, t = u0.copy(), t0
+    for _ in range(2 * n):
+        uo = step(pr.rhs, uo, dt, t)
+        t += dt
+    rel = mass_norm(pr, to_np(ud)[0] - uo) / mass_norm(pr, uo - u0)
+    print(f"  state error relative to the change {rel:.2e}", flush=True)
+    assert rel <= tol * 10
+
+
+def test_boundary_data_errors_and_clearing():
+    import torch
+    from paper_1912_06221_amd import ardg
+    print("boundary data errors", flush=True)
+    mesh, ops, lm, pr = _setup(5, 2, "const", None, 1, seed=3, t_a=0.0, t_b=0.5)
+    u = to_dev(W.random_nodal((1, mesh.K, ops.Np), seed=1))
+    out = torch.empty_like(u)
+    with pytest.raises(ardg.ArdgError):
+        lm.rhs_eval(u, out, t=0.8)
+    work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, ardg.FP64, 1), u.device)
+    with pytest.raises(ardg.ArdgError):
+        lm.rk_step(u, work, 0.01, 100, t0=0.0)
+    # cleared: back to zero Dirichlet data through the mirror ghost
+    lm.set_boundary_data(None, 0.0, 1.0)
+    from oracle.rhs import Problem
+    p0 = Problem(mesh.vxy, mesh.etov, 2, 0.4)
+    un = to_np(u)
+    lm.rhs_eval(u, out)
+    ro = p0.rhs(un[0])
+    assert np.abs(to_np(out)[0] - ro).max() <= 1e-12 * np.abs(ro).max()

@@ -223,3 +223,20 @@ def test_alg2_weights_match_oracle(L, N):
         eg = OA.interior_edge_geometry(g, k1, f1, k2, f2)
         assert np.abs(OA.coefficient_on_diagonal(ro, eg, f1, f2, one, zero) - w[0]).max() < 1e-12
         assert np.abs(OA.coefficient_on_diagonal(ro, eg, f1, f2, zero, one) - w[1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 3, 5])
+def test_ghost_nodes_match_oracle(L, N):
+    """The physical points where the exterior state is sampled (the nodes of
+    each boundary face's ghost sub-triangle) from the library's host setup
+    against the oracle's."""
+    from paper_1912_06221_amd import ardg as A
+    mesh = W.split_square_mesh(4, 0.2, seed=N + 40)
+    ops = A.Ops(N)
+    lm = A.Mesh(ops, mesh.vxy, mesh.etov, device=-1)
+    X = lm.export(A.MESH_BFACE_GHOST_NODES).reshape(lm.E_bdy, ops.Np, 2)
+    g = Geometry(mesh.vxy, mesh.etov)
+    bf = lm.export(A.MESH_BFACES).reshape(-1, 2)
+    for b, (k, f) in enumerate(bf):
+        eg = oa.boundary_edge_geometry(g, int(k), int(f))
+        assert np.abs(X[b] - oa.ghost_nodes(N, eg)).max() < 1e-12
