@@ -45,6 +45,19 @@ Readings of places the paper leaves open:
   prescribed exterior state g itself, sampled at its nodes, so that
   u~ = RDG(u1, g).  With Algorithms 1 and 2 the ghost carries the element's
   own D.  The default (no data given) stays the zero-Dirichlet mirror ghost.
+* Algorithm 1 with a nodal coefficient (eq.
+  NDG_diffusion_once_matrixForm_reference_general with D a function of space,
+  anisotropic, or of the solution): D is a symmetric tensor field
+  [[Dxx, Dxy], [Dxy, Dyy]] given by its nodal values on each element;
+  "project D" evaluates each element's D polynomial at the nodes of its
+  sub-triangle (the total projection of eq. totalProjection applied to D),
+  the product is the nodal tensor-vector product D_p^k grad(u~_k), and the
+  rest is as for element-wise D.  A solution-dependent coefficient D = u D0
+  (the D0 C of eq. advection_diffusion_nonlinear and of the shear equation
+  eq. diffusion_shear, whose cross term is the off-diagonal entry) takes the
+  nodal values of u itself.  A ghost carries the coefficient the same way as
+  its data: the element's nodal D at the mirrored points, or D0 times the
+  ghost's state.
 * Algorithm 2 (the alternative form): D~ = RDG(D^1, D^2) is the same
   least-squares reconstruction applied to the coefficient's nodal data of the
   two elements (projected onto the sub-triangles like u), Grad(u~) is the
@@ -515,3 +528,43 @@ def prescribed_boundary_operators_alg2(ops: RefOps, eg: EdgeGeometry, f1: int, D
     W1, WG = prescribed_boundary_operators(ops, eg, f1)
     Dt = boundary_coefficient_on_diagonal(ops, eg, f1, D1 * np.ones(ops.Np))
     return Dt[:, None] * W1, Dt[:, None] * WG
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 with a nodal tensor coefficient
+# ----------------------------------------------------------------------------
+
+def nodal_on_subtriangle(ops: RefOps, pi, f: int, values) -> np.ndarray:
+    """An element's nodal field [..., Np] evaluated at the nodes of its
+    sub-triangle (the total projection followed by the sub-triangle's
+    Vandermonde): V V^{-1} V_p V_rf^{-1} values."""
+    return np.asarray(values) @ (ops.V @ total_projection(ops, pi, f)).T
+
+
+def alg1_tensor_flux(ops: RefOps, eg: EdgeGeometry, m1, m2, Dp1, Dp2) -> np.ndarray:
+    """Algorithm 1 with nodal tensor coefficients: m_k modal data on Omega'_k
+    [Np], Dp_k [3, Np] = (Dxx, Dxy, Dyy) at Omega'_k's nodes.  Returns the
+    flux n1 . (D grad u~)~ at the diagonal nodes [Nfp]."""
+    N, Np = ops.N, ops.Np
+    R = recon_pinv(N)
+    c = R[:, :Np] @ m1 + R[:, Np:] @ m2                  # u~ = RDG(u1, u2)
+    rs = nodes(N)
+    u1n = phi(rs[:, 0], rs[:, 1], N) @ c                 # Separation
+    u2n = phi(-rs[:, 0], -rs[:, 1], N) @ c
+    g1x = eg.Rx * (ops.Dr @ u1n) + eg.Sx * (ops.Ds @ u1n)   # Grad, own frames
+    g1y = eg.Ry * (ops.Dr @ u1n) + eg.Sy * (ops.Ds @ u1n)
+    g2x = eg.Rx2 * (ops.Dr @ u2n) + eg.Sx2 * (ops.Ds @ u2n)
+    g2y = eg.Ry2 * (ops.Dr @ u2n) + eg.Sy2 * (ops.Ds @ u2n)
+    q1x, q1y = Dp1[0] * g1x + Dp1[1] * g1y, Dp1[1] * g1x + Dp1[2] * g1y
+    q2x, q2y = Dp2[0] * g2x + Dp2[1] * g2y, Dp2[1] * g2x + Dp2[2] * g2y
+    cx = R[:, :Np] @ (ops.Vinv @ q1x) + R[:, Np:] @ (ops.Vinv @ q2x)   # second RDG
+    cy = R[:, :Np] @ (ops.Vinv @ q1y) + R[:, Np:] @ (ops.Vinv @ q2y)
+    E0, _, _ = diagonal_eval(N)
+    return eg.n1[0] * (E0 @ cx) + eg.n1[1] * (E0 @ cy)
+
+
+def mirrored_on_ghost(ops: RefOps, geom, k1, eg: EdgeGeometry, values) -> np.ndarray:
+    """An element's nodal field evaluated at the mirror images of the nodes of
+    the ghost sub-triangle (P2, B, A): the even reflection of a coefficient
+    (the ghost's data is minus this for the solution)."""
+    return -(np.asarray(values) @ _boundary_ghost_data_operator(ops, geom, k1, eg).T)

@@ -40,10 +40,13 @@ from .reference_element import RefOps, vandermonde
 class Problem:
     """A mesh, an order N, diffusion coefficients and an optional velocity.
 
-    D_mode: "const" (D is a float, or a list with one value per field) or
+    D_mode: "const" (D is a float, or a list with one value per field),
     "element" (D is an array [K]; flux by Algorithm 1, or Algorithm 2 when
-    alg=2).  ghost: None (zero Dirichlet, mirror ghost) or a callable
-    g(x, y, t, field) giving the prescribed exterior state.
+    alg=2), "nodal" (D is an array [K, Np, 3] of the symmetric tensor
+    (Dxx, Dxy, Dyy) at each element's nodes; Algorithm 1 with nodal products)
+    or "solution" (D is (D0xx, D0xy, D0yy) and the coefficient is u D0).
+    ghost: None (zero Dirichlet, mirror ghost) or a callable g(x, y, t,
+    field) giving the prescribed exterior state.
     """
 
     def __init__(self, vxy, etov, N: int, D, D_mode: str = "const",
@@ -66,6 +69,14 @@ class Problem:
             if nfields != 1:
                 raise ValueError("element-wise D is for one field")
             self.Delem = np.asarray(D, dtype=np.float64)
+        elif D_mode == "nodal":
+            if nfields != 1:
+                raise ValueError("nodal D is for one field")
+            self.Dnodal = np.asarray(D, dtype=np.float64)
+        elif D_mode == "solution":
+            if nfields != 1:
+                raise ValueError("solution-dependent D is for one field")
+            self.D0 = np.asarray(D, dtype=np.float64).reshape(3)
         else:
             raise ValueError(D_mode)
         self.velocity = velocity   # None or (v0x, v0y, W11, W12, W21, W22)
@@ -80,9 +91,12 @@ class Problem:
         self.bdy_edges = g.boundary
         E1, E2 = [], []
         self.edge_geom = []
+        tensor = self.D_mode in ("nodal", "solution")
         for (k1, f1, k2, f2) in self.int_edges:
             eg = ardg.interior_edge_geometry(g, k1, f1, k2, f2)
             self.edge_geom.append(eg)
+            if tensor:
+                continue       # the flux is formed from the data on each call
             if self.D_mode == "element":
                 W1, W2 = self._element_edge_operator(eg, f1, f2, k1, k2)
             else:
@@ -96,6 +110,9 @@ class Problem:
         for (k1, f1) in self.bdy_edges:
             eg = ardg.boundary_edge_geometry(g, k1, f1)
             self.bdy_geom.append(eg)
+            if tensor:
+                GX.append(ardg.ghost_nodes(ops.N, eg))
+                continue
             if self.ghost is not None:
                 W1, WG = self._prescribed_operators(k1, f1, eg)
                 B.append(W1)
@@ -127,9 +144,43 @@ class Problem:
         """The prescribed exterior state at physical points X [..., 2]."""
         return np.asarray(self.ghost(X[..., 0], X[..., 1], t, field), dtype=np.float64)
 
+    # -- nodal tensor coefficient (Algorithm 1 with nodal products) ----------
+    def element_tensor(self, u, k):
+        """[3, Np] (Dxx, Dxy, Dyy) at element k's nodes."""
+        if self.D_mode == "nodal":
+            return self.Dnodal[k].T
+        return self.D0[:, None] * u[k][None, :]
+
+    def _tensor_edge_flux(self, u, k1, f1, k2, f2, eg, t, field):
+        """Flux of one interior edge (k2 >= 0) or boundary face (k2 < 0) with
+        the nodal tensor coefficient."""
+        ops = self.ops
+        m1 = ardg.total_projection(ops, eg.pi1, f1) @ u[k1]
+        Dp1 = ardg.nodal_on_subtriangle(ops, eg.pi1, f1, self.element_tensor(u, k1))
+        if k2 >= 0:
+            m2 = ardg.total_projection(ops, eg.pi2, f2) @ u[k2]
+            Dp2 = ardg.nodal_on_subtriangle(ops, eg.pi2, f2, self.element_tensor(u, k2))
+        else:
+            if self.ghost is not None:
+                u2n = self.ghost_values(ardg.ghost_nodes(ops.N, eg), t, field)
+            else:
+                u2n = -ardg.mirrored_on_ghost(ops, self.geom, k1, eg, u[k1])
+            m2 = ops.Vinv @ u2n
+            if self.D_mode == "nodal":
+                Dp2 = ardg.mirrored_on_ghost(ops, self.geom, k1, eg, self.Dnodal[k1].T)
+            else:
+                Dp2 = self.D0[:, None] * u2n[None, :]
+        return ardg.alg1_tensor_flux(ops, eg, m1, m2, Dp1, Dp2)
+
     # -- fluxes -----------------------------------------------------------------
     def diffusive_flux(self, u: np.ndarray, field: int = 0, t: float = 0.0):
         """Fluxes F in element-1 (CCW) order: [E_int, Nfp] and [E_bdy, Nfp]."""
+        if self.D_mode in ("nodal", "solution"):
+            Fi = np.array([self._tensor_edge_flux(u, k1, f1, k2, f2, self.edge_geom[e], t, field)
+                           for e, (k1, f1, k2, f2) in enumerate(self.int_edges)]).reshape(-1, self.ops.Nfp)
+            Fb = np.array([self._tensor_edge_flux(u, k1, f1, -1, -1, self.bdy_geom[e], t, field)
+                           for e, (k1, f1) in enumerate(self.bdy_edges)]).reshape(-1, self.ops.Nfp)
+            return Fi, Fb
         k1 = np.array([e[0] for e in self.int_edges], dtype=np.int64)
         k2 = np.array([e[2] for e in self.int_edges], dtype=np.int64)
         kb = np.array([e[0] for e in self.bdy_edges], dtype=np.int64)
@@ -203,7 +254,14 @@ class Problem:
         us = u @ ops.Ds.T
         qx = rx * ur + sx * us
         qy = ry * ur + sy * us
-        Dk = self.Delem[:, None] if self.D_mode == "element" else self.Dfield[field]
+        if self.D_mode in ("nodal", "solution"):
+            # q = D grad u as the nodal tensor-vector product
+            Dt = (self.Dnodal.transpose(2, 0, 1) if self.D_mode == "nodal"
+                  else self.D0[:, None, None] * u[None])
+            qx, qy = Dt[0] * qx + Dt[1] * qy, Dt[1] * qx + Dt[2] * qy
+            Dk = 1.0
+        else:
+            Dk = self.Delem[:, None] if self.D_mode == "element" else self.Dfield[field]
         vol = (rx * (qx @ ops.Drw.T) + sx * (qx @ ops.Dsw.T)
                + ry * (qy @ ops.Drw.T) + sy * (qy @ ops.Dsw.T))
         rhs = -Dk * vol
@@ -240,6 +298,13 @@ class Problem:
         edge with the same steps as the full assembly."""
         g, ops = self.geom, self.ops
         k2 = int(g.EToE[k, f])
+        if self.D_mode in ("nodal", "solution"):
+            if k2 < 0:
+                return self._tensor_edge_flux(u, k, f, -1, -1, ardg.boundary_edge_geometry(g, k, f), t, field)
+            f2 = int(g.EToF[k, f])
+            k1, fa, kb, fb = (k, f, k2, f2) if k < k2 else (k2, f2, k, f)
+            F = self._tensor_edge_flux(u, k1, fa, kb, fb, ardg.interior_edge_geometry(g, k1, fa, kb, fb), t, field)
+            return F if k == k1 else -F[::-1]
         if k2 < 0:
             eg = ardg.boundary_edge_geometry(g, k, f)
             if self.ghost is not None:
@@ -274,7 +339,12 @@ class Problem:
             uk = u[k]
             qx = rx * (ops.Dr @ uk) + sx * (ops.Ds @ uk)
             qy = ry * (ops.Dr @ uk) + sy * (ops.Ds @ uk)
-            Dk = self.Delem[k] if self.D_mode == "element" else self.Dfield[field]
+            if self.D_mode in ("nodal", "solution"):
+                Dt = self.element_tensor(u, k)
+                qx, qy = Dt[0] * qx + Dt[1] * qy, Dt[1] * qx + Dt[2] * qy
+                Dk = 1.0
+            else:
+                Dk = self.Delem[k] if self.D_mode == "element" else self.Dfield[field]
             r = -Dk * (rx * (ops.Drw @ qx) + sx * (ops.Dsw @ qx) + ry * (ops.Drw @ qy) + sy * (ops.Dsw @ qy))
             for f in range(3):
                 F = self._face_flux_one(u, k, f, field, t)

@@ -219,3 +219,43 @@ def physical_edge_flux_alg1(N, eg, rs_nodes, xy1, u1, xy2, u2, D1, D2):
     cy = ls.fit(comp(0, 1), comp(1, 1))
     Xd = ls.diagonal()
     return eg.n1[0] * ls.value(cx, Xd) + eg.n1[1] * ls.value(cy, Xd)
+
+
+def physical_edge_flux_alg1_tensor(N, eg, rs_nodes, xy1, u1, D1, xy2, u2, D2, D0=None):
+    """Algorithm 1 with a nodal tensor coefficient, in physical coordinates.
+
+    D_k: callable X -> [len(X), 3] (Dxx, Dxy, Dyy) of side k's coefficient
+    (the element's coefficient polynomial, evaluated anywhere); with D0
+    given instead, the coefficient of each side is D0 times that side's state.
+    Side 2 given as xy2 = None: the mirror ghost carrying -u1, with the
+    coefficient at mirrored points (or D0 times the ghost's state).
+    """
+    p1 = PhysPoly(N, xy1, u1)
+    if xy2 is None:
+        A, B = eg.A, eg.B
+
+        def p2(X):
+            return -p1(_mirror(X, A, B))
+
+        def D2(X, D1=D1):
+            return D1(_mirror(X, A, B))
+    else:
+        p2 = PhysPoly(N, xy2, u2)
+    if D0 is not None:
+        D1 = lambda X: p1(X)[:, None] * np.asarray(D0)[None, :]
+        D2 = lambda X: p2(X)[:, None] * np.asarray(D0)[None, :]
+    ls = ParallelogramLS(N, eg)
+    c = ls.fit(p1, p2)
+    parts = []
+    for V, Dk in ((np.array([eg.P1, eg.A, eg.B]), D1), (np.array([eg.P2, eg.B, eg.A]), D2)):
+        Xn = _map_nodes(rs_nodes, V)
+        pk = PhysPoly(N, Xn, ls.value(c, Xn))         # separation
+        g = pk.grad(Xn)
+        Dn = Dk(Xn)                                    # coefficient at the sub-triangle's nodes
+        qx = Dn[:, 0] * g[:, 0] + Dn[:, 1] * g[:, 1]
+        qy = Dn[:, 1] * g[:, 0] + Dn[:, 2] * g[:, 1]
+        parts.append((PhysPoly(N, Xn, qx), PhysPoly(N, Xn, qy)))
+    cx = ls.fit(parts[0][0], parts[1][0])
+    cy = ls.fit(parts[0][1], parts[1][1])
+    Xd = ls.diagonal()
+    return eg.n1[0] * ls.value(cx, Xd) + eg.n1[1] * ls.value(cy, Xd)
