@@ -51,7 +51,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernel_common.hpp",
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_tensor.hip", "kernel_common.hpp",
                   "edge_common.hpp", "mfma.hpp", "device.hpp")
 
 

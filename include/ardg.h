@@ -63,7 +63,7 @@ enum {
 
 enum { ARDG_FP64 = 0, ARDG_FP32 = 1, ARDG_BF16X3 = 2 };
 enum { ARDG_RK4 = 0, ARDG_LSERK54 = 1 };
-enum { ARDG_D_CONST = 0, ARDG_D_ELEMENT = 1, ARDG_D_ELEMENT_ALG2 = 2 };
+enum { ARDG_D_CONST = 0, ARDG_D_ELEMENT = 1, ARDG_D_ELEMENT_ALG2 = 2, ARDG_D_NODAL = 3, ARDG_D_SOLUTION = 4 };
 enum { ARDG_VEL_NONE = 0, ARDG_VEL_AFFINE = 1 };
 /* Edge kernel implementations (ardg_mesh_set_kernels). */
 enum {
@@ -168,7 +168,21 @@ void ardg_mesh_destroy(ardg_mesh mesh);
  * alternative, Algorithm nonconstDiff2): the reconstructed coefficient
  * D~ = RDG(D^1, D^2) at the diagonal nodes times n . grad u~; at boundary
  * faces the mirror ghost carries the element's own D.
- * All values must be finite > 0. */
+ * mode ARDG_D_NODAL: a symmetric tensor coefficient, space-varying and
+ * anisotropic (eq. NDG_diffusion_once_matrixForm_reference_general; the
+ * shear equation's cross term is its off-diagonal): D[K][Np][3] host
+ * doubles, (Dxx, Dxy, Dyy) at every node; Algorithm 1 with nodal products
+ * (each element's D evaluated at its sub-triangle's nodes, D grad u~ formed
+ * node by node, reconstructed again); a mirror ghost carries D at mirrored
+ * points.
+ * mode ARDG_D_SOLUTION: D[3] = (D0xx, D0xy, D0yy), the coefficient u D0 of
+ * eqs. advection_diffusion_nonlinear and diffusion_shear (nonlinear: each
+ * stage uses its own state), Algorithm 1 as for ARDG_D_NODAL; a ghost
+ * carries D0 times its state.
+ * Tensor modes: nfields 1, FP64 and FP32 only (E_UNSUPPORTED for BF16X3),
+ * one edge kernel (ardg_mesh_set_kernels does not apply); every tensor must
+ * be symmetric positive definite.
+ * Scalar values must be finite > 0. */
 ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfields,
                                     const double* D);
 

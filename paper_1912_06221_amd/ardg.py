@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libardg.so"
 OK = 0
 FP64, FP32, BF16X3 = 0, 1, 2
 RK4, LSERK54 = 0, 1
-D_CONST, D_ELEMENT, D_ELEMENT_ALG2 = 0, 1, 2
+D_CONST, D_ELEMENT, D_ELEMENT_ALG2, D_NODAL, D_SOLUTION = 0, 1, 2, 3, 4
 VEL_NONE, VEL_AFFINE = 0, 1
 EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA = 0, 1, 2, 3, 4
 
@@ -189,6 +189,18 @@ class Mesh:
         D = np.ascontiguousarray(D, dtype=np.float64)
         mode = {1: D_ELEMENT, 2: D_ELEMENT_ALG2}[alg]
         _check(lib().ardg_mesh_set_diffusion(self.handle, mode, 1, _dptr(D)))
+
+    def set_diffusion_nodal(self, D):
+        """Tensor coefficient (Dxx, Dxy, Dyy) at every node: D [K][Np][3]."""
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        if D.shape != (self.K, self.Np, 3):
+            raise ValueError("D must be [K][Np][3]")
+        _check(lib().ardg_mesh_set_diffusion(self.handle, D_NODAL, 1, _dptr(D)))
+
+    def set_diffusion_solution(self, D0):
+        """Solution-dependent coefficient u D0, D0 = (D0xx, D0xy, D0yy)."""
+        D = np.ascontiguousarray(D0, dtype=np.float64).reshape(3)
+        _check(lib().ardg_mesh_set_diffusion(self.handle, D_SOLUTION, 1, _dptr(D)))
 
     def set_velocity(self, params=None):
         if params is None:

@@ -88,6 +88,13 @@ void pack_into(const RefOps& o, std::vector<double>& out) {
     out[L.w1 + j] = o.alg2_w1[j];
     out[L.w2 + j] = o.alg2_w2[j];
   }
+  put(L.tr1, o.TR1);
+  put(L.ts1, o.TS1);
+  put(L.tr2, o.TR2);
+  put(L.ts2, o.TS2);
+  put(L.g1, o.G1);
+  put(L.g2, o.G2);
+  put(L.b2n, o.Bv);
   for (int j = 0; j < o.Nfp; ++j) {
     const double tau = 0.5 * (o.lgl[j] + 1.0);
     for (int k = 0; k <= o.N; ++k) {
@@ -141,6 +148,9 @@ struct ardg_mesh_s {
   std::vector<void*> allocs;      // device allocations owned by the mesh
   double* Delem_dev = nullptr;
   double2* vn_dev = nullptr;
+  double* Dnodal_dev = nullptr;     // tensor coefficient [K][Np][3]
+  double4* gp_dev = nullptr;        // per face: parallelogram inverse metric
+  double2* sn_dev = nullptr;        // per face: sJ n1
   int nfields_D = 1;
   void* flux_scratch = nullptr;
   size_t flux_scratch_bytes = 0;
@@ -164,6 +174,9 @@ struct ardg_mesh_s {
       for (void* p : allocs) (void)hipFree(p);
       if (Delem_dev) (void)hipFree(Delem_dev);
       if (vn_dev) (void)hipFree(vn_dev);
+      if (Dnodal_dev) (void)hipFree(Dnodal_dev);
+      if (gp_dev) (void)hipFree(gp_dev);
+      if (sn_dev) (void)hipFree(sn_dev);
       if (flux_scratch) (void)hipFree(flux_scratch);
       if (ghost_coef) (void)hipFree(ghost_coef);
       if (ghost_val) (void)hipFree(ghost_val);
@@ -441,8 +454,65 @@ ardg_status ardg_mesh_export(ardg_mesh mesh, int32_t which, void* dst, int64_t c
   return ARDG_OK;
 }
 
+// Per face (interior edges, then boundary faces) the inverse metric of the
+// enclosed parallelogram in the frame (P1, A, B) and sJ n1 = (t_y, -t_x) / 2
+// for the edge vector t = B - A: the tensor-coefficient kernel forms
+// physical gradients with them.
+static ardg_status upload_face_metric(ardg_mesh mesh) {
+  if (mesh->gp_dev || mesh->device < 0) return ARDG_OK;
+  const HostMesh& h = mesh->hm;
+  const int rotv[3][3] = {{2, 0, 1}, {0, 1, 2}, {1, 2, 0}};
+  const int64_t E = h.E_int + h.E_bdy;
+  std::vector<double4> gp(E);
+  std::vector<double2> sn(E);
+  auto face = [&](int64_t e, int64_t k, int f, double p1x, double p1y) {
+    const int ia = h.etov[3 * k + rotv[f][1]], ib = h.etov[3 * k + rotv[f][2]];
+    const double ax = h.vxy[2 * ia], ay = h.vxy[2 * ia + 1], bx = h.vxy[2 * ib], by = h.vxy[2 * ib + 1];
+    const double xr = 0.5 * (ax - p1x), yr = 0.5 * (ay - p1y), xs = 0.5 * (bx - p1x), ys = 0.5 * (by - p1y);
+    const double J = xr * ys - xs * yr;
+    gp[e] = make_double4(ys / J, -xs / J, -yr / J, xr / J);
+    sn[e] = make_double2(0.5 * (by - ay), -0.5 * (bx - ax));
+  };
+  for (int64_t e = 0; e < h.E_int; ++e) face(e, h.e1[e], h.f1[e], h.P1[2 * e], h.P1[2 * e + 1]);
+  for (int64_t b = 0; b < h.E_bdy; ++b) face(h.E_int + b, h.bk[b], h.bf[b], h.bP1[2 * b], h.bP1[2 * b + 1]);
+  DeviceGuard g(mesh->device);
+  ardg_status s = upload(gp.data(), gp.size(), &mesh->gp_dev);
+  if (s != ARDG_OK) return s;
+  s = upload(sn.data(), sn.size(), &mesh->sn_dev);
+  if (s != ARDG_OK) return s;
+  mesh->dm.gp = mesh->gp_dev;
+  mesh->dm.sn = mesh->sn_dev;
+  return ARDG_OK;
+}
+
+static bool spd(double a, double b, double c) {
+  return std::isfinite(a) && std::isfinite(b) && std::isfinite(c) && a > 0 && c > 0 && a * c - b * b > 0;
+}
+
 ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfields, const double* D) {
   if (!mesh || !D) return fail(ARDG_E_INVALID_ARG, "set_diffusion: null argument");
+  if (mode == ARDG_D_NODAL || mode == ARDG_D_SOLUTION) {
+    if (nfields != 1) return fail(ARDG_E_INVALID_ARG, "set_diffusion: a tensor coefficient needs nfields == 1");
+    const int64_t n = mode == ARDG_D_NODAL ? mesh->hm.K * mesh->ro.Np : 1;
+    for (int64_t i = 0; i < n; ++i)
+      if (!spd(D[3 * i], D[3 * i + 1], D[3 * i + 2]))
+        return fail(ARDG_E_INVALID_ARG, "set_diffusion: every tensor (Dxx, Dxy, Dyy) must be symmetric positive definite");
+    ardg_status s = upload_face_metric(mesh);
+    if (s != ARDG_OK) return s;
+    if (mode == ARDG_D_NODAL && mesh->device >= 0) {
+      DeviceGuard g(mesh->device);
+      if (mesh->Dnodal_dev) { (void)hipFree(mesh->Dnodal_dev); mesh->Dnodal_dev = nullptr; }
+      s = upload(D, (size_t)(3 * n), &mesh->Dnodal_dev);
+      if (s != ARDG_OK) return s;
+      mesh->dm.Dnodal = mesh->Dnodal_dev;
+    }
+    if (mode == ARDG_D_SOLUTION)
+      for (int i = 0; i < 3; ++i) mesh->dm.D0[i] = D[i];
+    mesh->dm.dmode = mode == ARDG_D_NODAL ? DM_NODAL : DM_SOLUTION;
+    mesh->nfields_D = 1;
+    mesh->drop_graphs();
+    return ARDG_OK;
+  }
   if (mode == ARDG_D_CONST) {
     if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "set_diffusion: nfields");
     for (int f = 0; f < nfields; ++f)
@@ -581,6 +651,8 @@ static ardg_status check_compute(ardg_mesh mesh, int32_t precision, int32_t nfie
     return fail(ARDG_E_UNSUPPORTED, "unknown precision");
   if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "nfields out of range");
   if (mesh->dm.dmode != DM_CONST && nfields != 1) return fail(ARDG_E_INVALID_ARG, "element-wise D is for one field");
+  if ((mesh->dm.dmode == DM_NODAL || mesh->dm.dmode == DM_SOLUTION) && precision == ARDG_BF16X3)
+    return fail(ARDG_E_UNSUPPORTED, "a tensor coefficient has no split-BF16 form (FP64 and FP32 only)");
   if (mesh->dm.dmode == DM_CONST && nfields > mesh->nfields_D && mesh->nfields_D != 1)
     return fail(ARDG_E_INVALID_ARG, "more fields than diffusion coefficients");
   if (mesh->dm.ghost && nfields > mesh->ghost_nf)

@@ -16,11 +16,15 @@ enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 
 // Offsets of the packed constant operators (same layout in FP64 and FP32).
 // bf2n: 1D Bernstein coefficients of a face -> values at its LGL nodes;
-// w1, w2: Algorithm 2's diagonal weights of the two sides' coefficients.
+// w1, w2: Algorithm 2's diagonal weights of the two sides' coefficients;
+// tr1, ts1, tr2, ts2, g1, g2: Algorithm 1 with a nodal coefficient (reference
+// gradients of u~ at each sub-triangle's nodes from both sides' Bernstein
+// coefficients, nodal data on a sub-triangle -> diagonal values); b2n:
+// Bernstein coefficients -> nodal values.
 struct OpLayout {
   int Np, Nfp;
   int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, drsh, lift, tau, nr, ns;
-  int bf2n, w1, w2, total;
+  int bf2n, w1, w2, tr1, ts1, tr2, ts2, g1, g2, b2n, total;
   __host__ __device__ constexpr OpLayout(int N)
       : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
         n2b(0),
@@ -46,7 +50,14 @@ struct OpLayout {
         bf2n(ns + Np),
         w1(bf2n + Nfp * Nfp),
         w2(w1 + Nfp),
-        total(w2 + Nfp) {}
+        tr1(w2 + Nfp),
+        ts1(tr1 + Np * 2 * Np),
+        tr2(ts1 + Np * 2 * Np),
+        ts2(tr2 + Np * 2 * Np),
+        g1(ts2 + Np * 2 * Np),
+        g2(g1 + Nfp * Np),
+        b2n(g2 + Nfp * Np),
+        total(b2n + Np * Np) {}
 };
 
 // Edge kernel implementations (values as ARDG_EDGE_* in the C ABI).
@@ -60,7 +71,9 @@ enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, E
 // constant per field, or element-wise with the flux of Algorithm 1
 // (reconstruction of D grad u~) or Algorithm 2 (reconstructed D times
 // grad u~).
-enum DiffusionMode { DM_CONST = 0, DM_ALG1 = 1, DM_ALG2 = 2 };
+// DM_NODAL: a symmetric tensor (Dxx, Dxy, Dyy) at every node; DM_SOLUTION:
+// the tensor D0 times the solution.  Both with Algorithm 1's nodal products.
+enum DiffusionMode { DM_CONST = 0, DM_ALG1 = 1, DM_ALG2 = 2, DM_NODAL = 3, DM_SOLUTION = 4 };
 
 struct DevMesh {
   int N = 0;
@@ -81,6 +94,13 @@ struct DevMesh {
   // sub-triangle (P2, B, A), [F][E_bdy][Np] at the current stage time, or
   // null (zero Dirichlet data through the mirror ghost)
   const double* ghost = nullptr;
+  // tensor coefficient: nodal values [K][Np][3] (DM_NODAL) or D0 (DM_SOLUTION),
+  // and per face (interior edges, then boundary faces) the parallelogram's
+  // inverse metric (r_x, r_y, s_x, s_y) and sJ n1
+  const double* Dnodal = nullptr;
+  double D0[3] = {};
+  const double4* gp = nullptr;
+  const double2* sn = nullptr;
   const double* ops64 = nullptr;
   const float* ops32 = nullptr;
   int dmode = DM_CONST;           // DiffusionMode
@@ -135,6 +155,9 @@ hipError_t launch_batch_element(int N, bool fp64, int tile, int grid, const Batc
 hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int nitems, int tile,
                                int Np, int grid, hipStream_t st);
 
+// Edge kernel for a nodal tensor coefficient (DM_NODAL, DM_SOLUTION): one
+// lane per face, FP64 and FP32 (same contract as launch_edge_flux).
+hipError_t launch_edge_tensor(const DevMesh& m, int prec, int nfields, const void* u, void* flux, hipStream_t st);
 // Edge kernel with interior edges on the matrix cores (same contract as
 // launch_edge_flux).
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,

@@ -524,6 +524,8 @@ hipError_t edge_dispatch(const DevMesh& m, int nf, const void* u, void* flux, hi
 }
 
 hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux, hipStream_t st) {
+  // a nodal tensor coefficient has one kernel (whatever edge kernel is chosen)
+  if (m.dmode == DM_NODAL || m.dmode == DM_SOLUTION) return launch_edge_tensor(m, prec, nfields, u, flux, st);
   // split-BF16 products exist only on the matrix cores: side-split tiles up
   // to N = 3, one wave per tile above (measured faster)
   if (m.edge_kernel == EDGE_SPLIT_MFMA || (prec == PREC_BF16X3 && m.edge_kernel == EDGE_AUTO && m.N <= 3))

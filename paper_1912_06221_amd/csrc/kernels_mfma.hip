@@ -25,6 +25,8 @@
 // LDS-staged, coalesced passes as the thread-per-element kernel.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.hpp"
 #include "kernel_common.hpp"
 #include "mfma.hpp"
@@ -52,8 +54,10 @@ struct ElemShared {
 };
 
 // One 64-element tile starting at element k0 of field `field`; all 256
-// threads of the block take part (wave w: sub-tile w).
-template <int N, typename P, bool CONV>
+// threads of the block take part (wave w: sub-tile w).  TENS: the diffusion
+// coefficient is a nodal tensor (or the tensor D0 times the solution):
+// q = D grad u is formed node by node and the scalar D is 1.
+template <int N, typename P, bool CONV, bool TENS = false>
 __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field,
                                          const typename Mma<P>::T* __restrict__ vin,
                                          const typename Mma<P>::T* __restrict__ flux, const Epilogue& epi,
@@ -84,7 +88,7 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
   const bool valid = k0 + el < m.K;
   const int64_t k = valid ? k0 + el : k0;
   const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
-  const double Dd = m.dmode != DM_CONST ? m.Delem[k] : m.Dfield[field];
+  const double Dd = TENS ? 1.0 : (m.dmode != DM_CONST ? m.Delem[k] : m.Dfield[field]);
   int code[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) code[f] = m.elem_face[f * m.K + k];
@@ -219,8 +223,26 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int node = 16 * mt + M::row(grp, r);
-      const T qx = rx * ur[mt][r] + sx * us[mt][r];
-      const T qy = ry * ur[mt][r] + sy * us[mt][r];
+      T qx = rx * ur[mt][r] + sx * us[mt][r];
+      T qy = ry * ur[mt][r] + sy * us[mt][r];
+      if (TENS) {
+        const int nc = node < Np ? node : 0;
+        T dxx, dxy, dyy;
+        if (m.dmode == DM_SOLUTION) {
+          const T un = (valid && node < Np) ? sh[el * Np + nc] : T(0);
+          dxx = (T)m.D0[0] * un;
+          dxy = (T)m.D0[1] * un;
+          dyy = (T)m.D0[2] * un;
+        } else {
+          const double* dn = m.Dnodal + ((int64_t)k * Np + nc) * 3;
+          dxx = (T)dn[0];
+          dxy = (T)dn[1];
+          dyy = (T)dn[2];
+        }
+        const T tx = dxx * qx + dxy * qy, ty = dxy * qx + dyy * qy;
+        qx = tx;
+        qy = ty;
+      }
       qxa[mt][r] = qx;
       qya[mt][r] = qy;
       T wr = D * (rx * qx + ry * qy);
@@ -321,7 +343,7 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
   tile_end<N, T, kMfmaTile, kMfmaThreads>(epi, sh, io, kPre);
 }
 
-template <int N, typename P, bool CONV>
+template <int N, typename P, bool CONV, bool TENS>
 __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
                                                                     const typename Mma<P>::T* __restrict__ vin,
                                                                     const typename Mma<P>::T* __restrict__ flux,
@@ -330,7 +352,7 @@ __global__ __launch_bounds__(kMfmaThreads) void element_mfma_kernel(DevMesh m,
   int64_t tile;
   int field;
   tile_and_field(blockIdx.x, gridDim.x, nf, tile, field);
-  element_mfma_tile<N, P, CONV>(m, tile * kMfmaTile, field, vin, flux, epi, S);
+  element_mfma_tile<N, P, CONV, TENS>(m, tile * kMfmaTile, field, vin, flux, epi, S);
 }
 
 // Batched form: persistent blocks over (problem, 64-element tile) items of
@@ -384,11 +406,25 @@ hipError_t elem_mfma_t(const DevMesh& m, int nfields, const void* vin, const voi
                        const Epilogue& epi, hipStream_t st) {
   using T = typename Mma<P>::T;
   dim3 grid((unsigned)((m.K + kMfmaTile - 1) / kMfmaTile * nfields));
+  if (m.dmode == DM_NODAL || m.dmode == DM_SOLUTION) {
+    // tensor coefficients: FP64 and FP32 (no split-BF16 form)
+    if constexpr (std::is_same<P, Bf16x3>::value) {
+      return hipErrorInvalidValue;
+    } else {
+      if (m.conv)
+        hipLaunchKernelGGL((element_mfma_kernel<N, P, true, true>), grid, dim3(kMfmaThreads), 0, st, m,
+                           (const T*)vin, (const T*)flux, epi, nfields);
+      else
+        hipLaunchKernelGGL((element_mfma_kernel<N, P, false, true>), grid, dim3(kMfmaThreads), 0, st, m,
+                           (const T*)vin, (const T*)flux, epi, nfields);
+      return hipGetLastError();
+    }
+  }
   if (m.conv)
-    hipLaunchKernelGGL((element_mfma_kernel<N, P, true>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, true, false>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi, nfields);
   else
-    hipLaunchKernelGGL((element_mfma_kernel<N, P, false>), grid, dim3(kMfmaThreads), 0, st, m,
+    hipLaunchKernelGGL((element_mfma_kernel<N, P, false, false>), grid, dim3(kMfmaThreads), 0, st, m,
                        (const T*)vin, (const T*)flux, epi, nfields);
   return hipGetLastError();
 }

@@ -329,6 +329,16 @@ RefOps build_refops(int N, bool* rank_ok) {
   o.alg1_nodal = vcat(vcat(alg1(G1, o.Dr, Phi1, RV), alg1(G1, o.Ds, Phi1, RV)),
                       vcat(alg1(G2, o.Dr, Phi2, RV), alg1(G2, o.Ds, Phi2, RV)));
 
+  // Algorithm 1 with a nodal coefficient: separation + reference gradient on
+  // each sub-triangle, and each sub-triangle's part of the second
+  // reconstruction on the diagonal
+  o.TR1 = matmul(matmul(o.Dr, Phi1), RB);
+  o.TS1 = matmul(matmul(o.Ds, Phi1), RB);
+  o.TR2 = matmul(matmul(o.Dr, Phi2), RB);
+  o.TS2 = matmul(matmul(o.Ds, Phi2), RB);
+  o.G1 = G1;
+  o.G2 = G2;
+
   // Algorithm 2: a constant coefficient is the same constant on the
   // sub-triangle (all nodal values equal), so its reconstruction at the
   // diagonal is G1 1 (side 1) and G2 1 (side 2)

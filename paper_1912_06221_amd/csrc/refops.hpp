@@ -33,6 +33,12 @@ struct RefOps {
   // sub-triangle and 0 on the other, at the diagonal nodes, so that an
   // element-wise constant coefficient reconstructs to D1 w1 + D2 w2 there.
   std::vector<double> alg2_w1, alg2_w2;   // [Nfp]
+  // Algorithm 1 with a nodal coefficient: the reference gradient (d/dr,
+  // d/ds in each sub-triangle's own frame) of u~ at the nodes of sub-triangle
+  // k from the Bernstein coefficients of both sub-triangles [Np][2Np], and the
+  // map from nodal data on sub-triangle k to values at the diagonal nodes
+  // (the second reconstruction) [Nfp][Np].
+  Mat TR1, TS1, TR2, TS2, G1, G2;
   // The same maps on nodal sub-triangle data (for export / checking).
   Mat recon_grad_nodal;              // [2Nfp][2Np]
   Mat alg1_nodal;                    // [4Nfp][2Np]
