@@ -65,6 +65,8 @@ enum { ARDG_FP64 = 0, ARDG_FP32 = 1, ARDG_BF16X3 = 2 };
 enum { ARDG_RK4 = 0, ARDG_LSERK54 = 1 };
 enum { ARDG_D_CONST = 0, ARDG_D_ELEMENT = 1, ARDG_D_ELEMENT_ALG2 = 2, ARDG_D_NODAL = 3, ARDG_D_SOLUTION = 4 };
 enum { ARDG_VEL_NONE = 0, ARDG_VEL_AFFINE = 1 };
+/* The compressible Navier-Stokes system (ardg_mesh_set_navier_stokes). */
+enum { ARDG_NS_OFF = 0, ARDG_NS_SUTHERLAND = 1, ARDG_NS_CONSTANT_MU = 2 };
 /* Edge kernel implementations (ardg_mesh_set_kernels). */
 enum {
   ARDG_EDGE_AUTO = 0,        /* chosen per launch (default)                                 */
@@ -92,9 +94,11 @@ enum {
                                 nodal sub-triangle data (flux = D1 (gR U1R + gS U1S)
                                 - D2 (gR U2R + gS U2S))                                    */
   ARDG_OPS_N2B = 12,         /* [Np][Np] nodal values -> Bernstein coefficients on I       */
-  ARDG_OPS_ALG2_W = 13       /* [2][Nfp] Algorithm 2: reconstruction at the diagonal nodes of
+  ARDG_OPS_ALG2_W = 13,      /* [2][Nfp] Algorithm 2: reconstruction at the diagonal nodes of
                                 a coefficient equal to 1 on side 1 / side 2 and 0 on the
                                 other (D~ = D1 w1 + D2 w2 for element-wise constant D)      */
+  ARDG_OPS_RECON_VALUE = 14  /* [Nfp][2Np] nodal data on the two sub-triangles (each in its
+                                own frame) -> u~ at the diagonal nodes                      */
 };
 
 /* ardg_mesh_export selectors. */
@@ -212,6 +216,29 @@ ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel);
 ardg_status ardg_mesh_set_boundary_data(ardg_mesh mesh, int32_t nfields, int32_t nt, double t_a, double t_b,
                                         const double* coeffs);
 
+/* The compressible Navier-Stokes equations (subsection on the Navier-Stokes
+ * equations: eq. aRDG_Navier_Stokes with the stress of eq. NS_viscosity, the
+ * heat flux of eq. NS_heatflux, kappa = Cp mu / Pr) in place of the scalar
+ * equation.  The state has four fields, (rho, rho u, rho v, E), [4][K][Np];
+ * the gas is ideal: p = (gamma - 1)(E - rho |u|^2 / 2), T = p / (rho R),
+ * Cp = gamma R / (gamma - 1).  The inviscid flux at a face is Lax-Friedrichs
+ * (lambda = the larger |u . n| + c of the two traces); the viscous flux at a
+ * face is G . n of the aRDG reconstructions of u, v and T on the enclosed
+ * parallelogram (values and gradients at the diagonal nodes), with mu and
+ * kappa from the reconstructed T.  Every boundary face takes its exterior
+ * state from ardg_mesh_set_boundary_data (four fields, conserved variables):
+ * at the ghost sub-triangle's nodes for the reconstruction and at the face
+ * nodes as the outer Lax-Friedrichs state; computing without it fails with
+ * E_INVALID_ARG.  law: ARDG_NS_SUTHERLAND (mu = mu_ref (T/T_ref)^(3/2)
+ * (T_ref + S)/(T + S)), ARDG_NS_CONSTANT_MU (mu = mu_ref), or ARDG_NS_OFF
+ * (back to the scalar equation).  params: host doubles {gamma, R, Pr, mu_ref,
+ * T_ref, S} (gamma > 1, R, Pr, T_ref > 0, mu_ref, S >= 0).  While it is on,
+ * the diffusion coefficient and the velocity are not used, nfields must be
+ * 4, and the precision FP64 or FP32 (E_UNSUPPORTED otherwise); the state
+ * must keep rho > 0 and p > 0.  The mesh cannot join a batch.  Drops the
+ * mesh's captured step graphs.  Errors: E_INVALID_ARG, E_OOM. */
+ardg_status ardg_mesh_set_navier_stokes(ardg_mesh mesh, int32_t law, const double* params);
+
 /* Velocity of the convective term of eq. convection_diffusion, for every
  * field: ARDG_VEL_NONE, or ARDG_VEL_AFFINE with v(x,y) = (p0 + p2 x + p3 y,
  * p1 + p4 x + p5 y), params[6] on the host (v = (-y, x) is {0,0,0,-1,1,0}).
@@ -242,7 +269,9 @@ ardg_status ardg_rhs_eval_noalloc(ardg_mesh mesh, int32_t precision, int32_t nfi
                                   void* rhs_dev, double t, void* hip_stream);
 
 /* Edge fluxes only (the interior and boundary loop of Algorithm aRDG with the
- * diagonal flux; Algorithms 1 and 2 for element-wise D): flux_dev [F][E][Nfp] in the
+ * diagonal flux; Algorithms 1 and 2 for element-wise D; for the Navier-Stokes
+ * system the numerical flux (F + G)* . n1 of the four conserved fields,
+ * inviscid and viscous together): flux_dev [F][E][Nfp] in the
  * precision's type, D included, each edge's values multiplied by its surface
  * factor sJ = |edge| / 2 (the factor the surface integral of the weak form
  * applies, so that the element kernel needs no edge lengths).  Interior edges

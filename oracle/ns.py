@@ -94,18 +94,22 @@ class NavierStokes:
     """The semi-discrete compressible Navier-Stokes system on a triangle mesh.
 
     exterior: callable (x, y, t) -> Q [4, ...], the prescribed state outside
-    the domain (used at boundary faces).
+    the domain (used at boundary faces).  build_edges=False skips the
+    per-edge geometry of the whole mesh (rhs_elements builds what it needs
+    edge by edge), for sampled checks on large meshes.
     """
 
-    def __init__(self, vxy, etov, N: int, gas: Gas, exterior):
+    def __init__(self, vxy, etov, N: int, gas: Gas, exterior, build_edges: bool = True):
         self.geom = Geometry(vxy, etov)
         self.ops = RefOps(N)
         self.N = N
         self.gas = gas
         self.exterior = exterior
         g = self.geom
-        self.int_geom = [ardg.interior_edge_geometry(g, k1, f1, k2, f2) for (k1, f1, k2, f2) in g.interior]
-        self.bdy_geom = [ardg.boundary_edge_geometry(g, k1, f1) for (k1, f1) in g.boundary]
+        self.int_geom = self.bdy_geom = None
+        if build_edges:
+            self.int_geom = [ardg.interior_edge_geometry(g, k1, f1, k2, f2) for (k1, f1, k2, f2) in g.interior]
+            self.bdy_geom = [ardg.boundary_edge_geometry(g, k1, f1) for (k1, f1) in g.boundary]
 
     def nodal_xy(self):
         return self.geom.physical(self.ops.rs)
@@ -175,6 +179,8 @@ class NavierStokes:
         its own counter-clockwise order and outward normal: side 1 reads the
         edge's flux as is, side 2 negated and in reverse order."""
         g = self.geom
+        if self.int_geom is None:
+            raise RuntimeError("face_fluxes needs the edge geometry (build_edges=True)")
         P = self._primitive_fields(Q)
         out = np.zeros((g.K, 3, 4, self.ops.Nfp))
         for e, (k1, f1, k2, f2) in enumerate(g.interior):
@@ -185,10 +191,11 @@ class NavierStokes:
             out[k1, f1] = self._boundary_H(Q, P, k1, f1, self.bdy_geom[e], t)
         return out
 
-    def face_flux_one(self, Q, k, f, t):
-        """The flux seen by face f of element k alone (same steps, one edge)."""
+    def face_flux_one(self, Q, k, f, t, P=None):
+        """The flux seen by face f of element k alone (same steps, one edge);
+        P: the primitive fields of Q if already formed."""
         g = self.geom
-        P = self._primitive_fields(Q)
+        P = self._primitive_fields(Q) if P is None else P
         k2 = int(g.EToE[k, f])
         if k2 < 0:
             return self._boundary_H(Q, P, k, f, ardg.boundary_edge_geometry(g, k, f), t)
@@ -239,5 +246,6 @@ class NavierStokes:
         """dQ/dt on the listed elements only [4, len(elements), Np], each face
         flux computed for its edge alone (sampled checks on large meshes)."""
         els = np.asarray(elements, dtype=np.int64)
-        Hs = np.array([[self.face_flux_one(Q, int(k), f, t) for f in range(3)] for k in els])
+        P = self._primitive_fields(Q)
+        Hs = np.array([[self.face_flux_one(Q, int(k), f, t, P) for f in range(3)] for k in els])
         return self._volume(Q, els) - self._lift(Hs, els)

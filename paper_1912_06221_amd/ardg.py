@@ -20,11 +20,13 @@ FP64, FP32, BF16X3 = 0, 1, 2
 RK4, LSERK54 = 0, 1
 D_CONST, D_ELEMENT, D_ELEMENT_ALG2, D_NODAL, D_SOLUTION = 0, 1, 2, 3, 4
 VEL_NONE, VEL_AFFINE = 0, 1
+NS_OFF, NS_SUTHERLAND, NS_CONSTANT_MU = 0, 1, 2
 EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA = 0, 1, 2, 3, 4
 
 OPS_NODES, OPS_V, OPS_DR, OPS_DS, OPS_MASS, OPS_LIFT = 0, 1, 2, 3, 4, 5
 OPS_FACE_NODES, OPS_ROT_PERM, OPS_RECON_A, OPS_RECON_R = 6, 7, 8, 9
 OPS_RECON_GRAD, OPS_ALG1_GRAD, OPS_N2B, OPS_ALG2_W = 10, 11, 12, 13
+OPS_RECON_VALUE = 14
 MESH_EDGES, MESH_BFACES, MESH_EDGE_GEOM, MESH_BFACE_GEOM, MESH_ELEM_FACES = 0, 1, 2, 3, 4
 MESH_BFACE_GHOST_NODES = 5
 
@@ -56,6 +58,7 @@ SIGNATURES = {
     "ardg_mesh_set_diffusion": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
     "ardg_mesh_set_velocity": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "ardg_mesh_set_kernels": (c_int32, [c_void_p, c_int32]),
+    "ardg_mesh_set_navier_stokes": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "ardg_mesh_set_boundary_data": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_double, POINTER(c_double)]),
     "ardg_rhs_eval": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
     "ardg_rhs_eval_noalloc": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_double, c_void_p]),
@@ -211,6 +214,16 @@ class Mesh:
 
     def set_kernels(self, edge_kernel: int = EDGE_AUTO):
         _check(lib().ardg_mesh_set_kernels(self.handle, edge_kernel))
+
+    def set_navier_stokes(self, law: int = NS_SUTHERLAND, gamma: float = 1.4, R: float = 1.0,
+                          Pr: float = 0.7, mu_ref: float = 1e-2, T_ref: float = 1.0, S: float = 0.4):
+        """The compressible Navier-Stokes system on four fields (law NS_OFF
+        switches back to the scalar equation)."""
+        if law == NS_OFF:
+            _check(lib().ardg_mesh_set_navier_stokes(self.handle, NS_OFF, None))
+            return
+        p = np.array([gamma, R, Pr, mu_ref, T_ref, S], dtype=np.float64)
+        _check(lib().ardg_mesh_set_navier_stokes(self.handle, law, _dptr(p)))
 
     def set_boundary_data(self, coeffs, t_a: float, t_b: float):
         """Prescribed exterior state: coeffs [F][E_bdy][Np][nt] Chebyshev

@@ -95,6 +95,7 @@ void pack_into(const RefOps& o, std::vector<double>& out) {
   put(L.g1, o.G1);
   put(L.g2, o.G2);
   put(L.b2n, o.Bv);
+  put(L.kv, o.KV);
   for (int j = 0; j < o.Nfp; ++j) {
     const double tau = 0.5 * (o.lgl[j] + 1.0);
     for (int k = 0; k <= o.N; ++k) {
@@ -264,6 +265,7 @@ ardg_status ardg_ops_export(ardg_ops ops, int32_t which, double* dst, int64_t ca
     case ARDG_OPS_RECON_GRAD: mat(o.recon_grad_nodal); break;
     case ARDG_OPS_ALG1_GRAD: mat(o.alg1_nodal); break;
     case ARDG_OPS_N2B: mat(o.N2B); break;
+    case ARDG_OPS_RECON_VALUE: mat(o.recon_value_nodal); break;
     case ARDG_OPS_ALG2_W:
       v = o.alg2_w1;
       v.insert(v.end(), o.alg2_w2.begin(), o.alg2_w2.end());
@@ -630,6 +632,30 @@ ardg_status ardg_mesh_set_boundary_data(ardg_mesh mesh, int32_t nfields, int32_t
   return ARDG_OK;
 }
 
+ardg_status ardg_mesh_set_navier_stokes(ardg_mesh mesh, int32_t law, const double* params) {
+  if (!mesh) return fail(ARDG_E_INVALID_ARG, "set_navier_stokes: null handle");
+  if (law == ARDG_NS_OFF) {
+    mesh->dm.ns = NS_OFF;
+    mesh->drop_graphs();
+    return ARDG_OK;
+  }
+  if (law != ARDG_NS_SUTHERLAND && law != ARDG_NS_CONSTANT_MU)
+    return fail(ARDG_E_INVALID_ARG, "set_navier_stokes: unknown law");
+  if (!params) return fail(ARDG_E_INVALID_ARG, "set_navier_stokes: null params");
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(params[i])) return fail(ARDG_E_INVALID_ARG, "set_navier_stokes: non-finite parameter");
+  const double gamma = params[0], R = params[1], Pr = params[2], mu_ref = params[3], T_ref = params[4],
+               S = params[5];
+  if (!(gamma > 1.0 && R > 0.0 && Pr > 0.0 && mu_ref >= 0.0 && T_ref > 0.0 && S >= 0.0))
+    return fail(ARDG_E_INVALID_ARG, "set_navier_stokes: need gamma > 1, R, Pr, T_ref > 0 and mu_ref, S >= 0");
+  ardg_status s = upload_face_metric(mesh);
+  if (s != ARDG_OK) return s;
+  for (int i = 0; i < 6; ++i) mesh->dm.gas[i] = params[i];
+  mesh->dm.ns = law == ARDG_NS_SUTHERLAND ? NS_SUTHERLAND : NS_CONSTANT_MU;
+  mesh->drop_graphs();
+  return ARDG_OK;
+}
+
 // Exterior state at time toff (+ the device step time when tbase is used).
 static hipError_t ghost_eval(ardg_mesh mesh, int nfields, bool use_tbase, double toff, hipStream_t st) {
   if (!mesh->dm.ghost) return hipSuccess;
@@ -650,6 +676,15 @@ static ardg_status check_compute(ardg_mesh mesh, int32_t precision, int32_t nfie
   if (precision != ARDG_FP64 && precision != ARDG_FP32 && precision != ARDG_BF16X3)
     return fail(ARDG_E_UNSUPPORTED, "unknown precision");
   if (nfields < 1 || nfields > kMaxFields) return fail(ARDG_E_INVALID_ARG, "nfields out of range");
+  if (mesh->dm.ns != NS_OFF) {
+    if (nfields != 4) return fail(ARDG_E_INVALID_ARG, "the Navier-Stokes system has four fields");
+    if (precision == ARDG_BF16X3)
+      return fail(ARDG_E_UNSUPPORTED, "the Navier-Stokes system has no split-BF16 form (FP64 and FP32 only)");
+    if (!mesh->dm.ghost || mesh->ghost_nf < 4)
+      return fail(ARDG_E_INVALID_ARG, "the Navier-Stokes system needs the exterior state of all four fields "
+                                      "(ardg_mesh_set_boundary_data)");
+    return ARDG_OK;
+  }
   if (mesh->dm.dmode != DM_CONST && nfields != 1) return fail(ARDG_E_INVALID_ARG, "element-wise D is for one field");
   if ((mesh->dm.dmode == DM_NODAL || mesh->dm.dmode == DM_SOLUTION) && precision == ARDG_BF16X3)
     return fail(ARDG_E_UNSUPPORTED, "a tensor coefficient has no split-BF16 form (FP64 and FP32 only)");
@@ -1352,7 +1387,7 @@ ardg_status ardg_batch_create(const ardg_mesh* meshes, int32_t n, const char* tu
     if (!m) return fail(ARDG_E_INVALID_ARG, "batch_create: null mesh");
     if (m->device < 0 || m->device != dev)
       return fail(ARDG_E_INVALID_ARG, "batch_create: meshes must live on one device");
-    if (m->dm.dmode != DM_CONST || m->dm.conv || m->nfields_D != 1 || m->dm.ghost)
+    if (m->dm.dmode != DM_CONST || m->dm.conv || m->nfields_D != 1 || m->dm.ghost || m->dm.ns != NS_OFF)
       return fail(ARDG_E_UNSUPPORTED,
                   "batch_create: meshes need one field, constant D, no velocity and zero Dirichlet data");
   }

@@ -20,11 +20,12 @@ enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 // tr1, ts1, tr2, ts2, g1, g2: Algorithm 1 with a nodal coefficient (reference
 // gradients of u~ at each sub-triangle's nodes from both sides' Bernstein
 // coefficients, nodal data on a sub-triangle -> diagonal values); b2n:
-// Bernstein coefficients -> nodal values.
+// Bernstein coefficients -> nodal values; kv: values of u~ at the diagonal
+// nodes from both sides' Bernstein coefficients.
 struct OpLayout {
   int Np, Nfp;
   int n2b, kr, ks, kbr, kbs, u1r, u1s, u2r, u2s, udr, uds, ubr, ubs, dr, ds, drsh, lift, tau, nr, ns;
-  int bf2n, w1, w2, tr1, ts1, tr2, ts2, g1, g2, b2n, total;
+  int bf2n, w1, w2, tr1, ts1, tr2, ts2, g1, g2, b2n, kv, total;
   __host__ __device__ constexpr OpLayout(int N)
       : Np((N + 1) * (N + 2) / 2), Nfp(N + 1),
         n2b(0),
@@ -57,7 +58,8 @@ struct OpLayout {
         g1(ts2 + Np * 2 * Np),
         g2(g1 + Nfp * Np),
         b2n(g2 + Nfp * Np),
-        total(b2n + Np * Np) {}
+        kv(b2n + Np * Np),
+        total(kv + Nfp * 2 * Np) {}
 };
 
 // Edge kernel implementations (values as ARDG_EDGE_* in the C ABI).
@@ -74,6 +76,11 @@ enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, E
 // DM_NODAL: a symmetric tensor (Dxx, Dxy, Dyy) at every node; DM_SOLUTION:
 // the tensor D0 times the solution.  Both with Algorithm 1's nodal products.
 enum DiffusionMode { DM_CONST = 0, DM_ALG1 = 1, DM_ALG2 = 2, DM_NODAL = 3, DM_SOLUTION = 4 };
+
+// The compressible Navier-Stokes system in place of the scalar equation
+// (values as ARDG_NS_* in the C ABI): off, Sutherland viscosity, or a
+// constant viscosity.
+enum NsMode { NS_OFF = 0, NS_SUTHERLAND = 1, NS_CONSTANT_MU = 2 };
 
 struct DevMesh {
   int N = 0;
@@ -106,6 +113,8 @@ struct DevMesh {
   int dmode = DM_CONST;           // DiffusionMode
   int edge_kernel = EDGE_AUTO;    // EdgeKernel
   int conv = 0;                   // convective term on
+  int ns = NS_OFF;                // NsMode: the four fields are (rho, rho u, rho v, E)
+  double gas[6] = {};             // gamma, R, Pr, mu_ref, T_ref, S (Sutherland constant)
   double Dfield[kMaxFields] = {};
   double vel[6] = {};             // v = (p0 + p2 x + p3 y, p1 + p4 x + p5 y)
 };
@@ -158,6 +167,12 @@ hipError_t launch_batch_to_f32(const BatchProb* probs, const int2* items, int ni
 // Edge kernel for a nodal tensor coefficient (DM_NODAL, DM_SOLUTION): one
 // lane per face, FP64 and FP32 (same contract as launch_edge_flux).
 hipError_t launch_edge_tensor(const DevMesh& m, int prec, int nfields, const void* u, void* flux, hipStream_t st);
+// Navier-Stokes: interface fluxes sJ (F + G)* . n1 of the four conserved
+// fields (Lax-Friedrichs + the aRDG viscous flux), [4][E][Nfp], and the
+// element kernel (volume term, lift, epilogue) over all four fields.
+hipError_t launch_edge_ns(const DevMesh& m, int prec, const void* q, void* flux, hipStream_t st);
+hipError_t launch_element_ns(const DevMesh& m, int prec, const void* vin, const void* flux, const Epilogue& epi,
+                             hipStream_t st);
 // Edge kernel with interior edges on the matrix cores (same contract as
 // launch_edge_flux).
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,

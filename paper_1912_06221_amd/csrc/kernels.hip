@@ -524,6 +524,8 @@ hipError_t edge_dispatch(const DevMesh& m, int nf, const void* u, void* flux, hi
 }
 
 hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void* u, void* flux, hipStream_t st) {
+  // the Navier-Stokes system takes its four fields together
+  if (m.ns != NS_OFF) return nfields == 4 ? launch_edge_ns(m, prec, u, flux, st) : hipErrorInvalidValue;
   // a nodal tensor coefficient has one kernel (whatever edge kernel is chosen)
   if (m.dmode == DM_NODAL || m.dmode == DM_SOLUTION) return launch_edge_tensor(m, prec, nfields, u, flux, st);
   // split-BF16 products exist only on the matrix cores: side-split tiles up
@@ -537,6 +539,7 @@ hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void*
 
 hipError_t launch_element(const DevMesh& m, int prec, int nfields, const void* vin, const void* flux,
                           const Epilogue& epi, hipStream_t st) {
+  if (m.ns != NS_OFF) return nfields == 4 ? launch_element_ns(m, prec, vin, flux, epi, st) : hipErrorInvalidValue;
   return launch_element_mfma(m, prec, nfields, vin, flux, epi, st);
 }
 

@@ -31,28 +31,6 @@
 
 namespace ardg {
 
-// Side k's Bernstein coefficients on its sub-triangle of one element field
-// given by nodal values v (rotated to face f, converted, subdivided at mu).
-template <int N, typename T>
-__device__ inline void project_side(cptr<T> op, const T* v, int f, double2 mu, T* b, T* trace) {
-  constexpr OpLayout L(N);
-  constexpr int Np = L.Np;
-  T t[Np];
-  rotate_to_face<N, T>(v, f, t, trace);
-  matvec<Np, Np, T>(op + L.n2b, t, b);
-  decasteljau<N, T>(b, mu);
-}
-
-// The (r, s) swap of the lattice: the mirror image of a sub-triangle's
-// Bernstein coefficients in the other half of the rhombus.
-template <int N, typename T>
-__device__ inline void lattice_swap(const T* b, T* out, T sign) {
-#pragma unroll
-  for (int j = 0; j <= N; ++j)
-#pragma unroll
-    for (int i = 0; i <= N - j; ++i) out[lat(N, i, j)] = sign * b[lat(N, j, i)];
-}
-
 template <int N, typename T, bool SOL>
 __global__ __launch_bounds__(256) void edge_tensor_kernel(DevMesh m, const T* __restrict__ u, T* __restrict__ flux,
                                                           int nf) {

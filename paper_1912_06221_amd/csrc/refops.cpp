@@ -312,6 +312,8 @@ RefOps build_refops(int N, bool* rank_ok) {
   o.KR = matmul(ER, RB);
   o.KS = matmul(ES, RB);
   o.recon_grad_nodal = vcat(matmul(ER, RV), matmul(ES, RV));
+  o.KV = matmul(E0, RB);
+  o.recon_value_nodal = matmul(E0, RV);
 
   // Algorithm 1: separate u~ onto the sub-triangles, differentiate in each
   // sub-triangle frame, reconstruct again from the nodal data (no second

@@ -39,9 +39,14 @@ struct RefOps {
   // map from nodal data on sub-triangle k to values at the diagonal nodes
   // (the second reconstruction) [Nfp][Np].
   Mat TR1, TS1, TR2, TS2, G1, G2;
+  // Values of u~ at the diagonal nodes from the Bernstein coefficients of
+  // both sub-triangles [Nfp][2Np] (the Navier-Stokes interface needs the
+  // reconstructed temperature and velocity, not only their gradients).
+  Mat KV;
   // The same maps on nodal sub-triangle data (for export / checking).
   Mat recon_grad_nodal;              // [2Nfp][2Np]
   Mat alg1_nodal;                    // [4Nfp][2Np]
+  Mat recon_value_nodal;             // [Nfp][2Np]
 };
 
 // Throws std::runtime_error on failure; sets *rank_ok false if the

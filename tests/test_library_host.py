@@ -80,6 +80,10 @@ def test_reconstruction_operators_match_oracle(L, N):
     ref = np.vstack([ER @ R @ Vb, ES @ R @ Vb])
     G = o.export(ardg.OPS_RECON_GRAD).reshape(2 * Nfp, 2 * Np)
     assert np.abs(G - ref).max() < 1e-12 * np.abs(ref).max()
+    # values of u~ at the diagonal nodes (the Navier-Stokes interface)
+    Vv = o.export(ardg.OPS_RECON_VALUE).reshape(Nfp, 2 * Np)
+    refv = E0 @ R @ Vb
+    assert np.abs(Vv - refv).max() < 1e-12 * np.abs(refv).max()
     # library A^+ is a pseudo-inverse of its own A
     A = o.export(ardg.OPS_RECON_A).reshape(2 * Np, (N + 1) ** 2)
     Rl = o.export(ardg.OPS_RECON_R).reshape((N + 1) ** 2, 2 * Np)
