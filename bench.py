@@ -17,8 +17,10 @@ captured before the timed region and launched inside it.
 
 Extra keys: the 256 x 256 x 2, N = 4 workload with element-wise D (contrast
 1e4, Algorithm 1 flux), the 512 x 512 x 2, N = 6 workload with log-uniform D
-(the precision workload: every mode's L2 error after 50 steps), and the 512
-independent problems advanced as one batch.
+(the precision workload: every mode's L2 error after 50 steps), the 512
+independent problems advanced as one batch, and the compressible
+Navier-Stokes workload (708 x 708 x 2, N = 3, four conserved fields, the
+isentropic vortex, low-storage RK) with its kernels' HBM fractions.
 
 `cpu_baseline` times the FP64 NumPy oracle (test infrastructure): its
 assembled right-hand side with the per-edge operators prebuilt, on strips of
@@ -51,8 +53,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_tensor.hip", "kernel_common.hpp",
-                  "edge_common.hpp", "mfma.hpp", "device.hpp")
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_tensor.hip", "kernels_ns.hip",
+                  "kernel_common.hpp", "edge_common.hpp", "mfma.hpp", "device.hpp")
 
 
 def kernel_source_hash():
@@ -323,6 +325,149 @@ def measure_case(case, args, dev, modes, error_steps):
     return res
 
 
+def ns_algorithmic_bytes(K, Np, Nfp, E_int, E_bdy, s):
+    """Bytes each Navier-Stokes kernel must move per launch (four fields,
+    each value counted once, low-storage RK averaged over its five stages):
+    edge    4 K Np s (state) + 88 E_int + 68 E_bdy (edge tables: element and
+            face codes, apex weights, parallelogram metric, sJ n) + 4 E_bdy Np 8
+            (exterior state) + 4 E Nfp s (flux write);
+    element 4 K Np s (stage input) + 4 E Nfp s (flux) + 60 K (affine map and
+            face map) + 4 K Np (8 + 8 + 8 + 6.4) (u^n write, u^n read beside
+            the stage input in FP32 only, residual write, residual read in four
+            of five stages) + 4 K Np s (next stage input, FP32 only)."""
+    E = E_int + E_bdy
+    dof = 4 * K * Np
+    edge = dof * s + 88 * E_int + 68 * E_bdy + 4 * E_bdy * Np * 8 + 4 * E * Nfp * s
+    if s == 8:      # the FP64 stage input is the state itself
+        elem = dof * 8 + 4 * E * Nfp * 8 + 60 * K + dof * (8 + 8 + 6.4)
+    else:
+        elem = dof * s + 4 * E * Nfp * s + 60 * K + dof * (8 + 8 + 8 + 6.4) + dof * s
+    return edge, elem
+
+
+class NSCase:
+    """The Navier-Stokes workload on the device (low-storage RK, the paper's
+    integrator)."""
+
+    def __init__(self, name, dev):
+        import torch
+        from paper_1912_06221_amd import ardg
+        self.name = name
+        spec = W.WORKLOADS[name]
+        self.spec = spec
+        cfg = spec["config"]
+        t0 = time.time()
+        self.mesh = W.split_square_mesh(spec["m"], spec["jitter"], seed=W.seed_for(cfg, "mesh"))
+        self.N = spec["N"]
+        self.nf = 4
+        self.ops = ardg.Ops(self.N)
+        self.lm = ardg.Mesh(self.ops, self.mesh.vxy, self.mesh.etov, device=0)
+        self.gas = dict(gamma=1.4, R=1.0, Pr=0.7, mu_ref=spec["mu_ref"], T_ref=1.0, S=0.4)
+        self.lm.set_navier_stokes(ardg.NS_SUTHERLAND, **self.gas)
+        vp = spec["vortex"]
+        X = self.lm.export(ardg.MESH_BFACE_GHOST_NODES).reshape(self.lm.E_bdy, self.ops.Np, 2)
+        ext = W.isentropic_vortex(X[..., 0], X[..., 1], **vp)          # [4][E_bdy][Np]
+        self.lm.set_boundary_data(ext[..., None], 0.0, 1.0)
+        rs = self.ops.export(ardg.OPS_NODES).reshape(-1, 2)
+        x, y = nodal_xy(self.mesh, rs)
+        self.u0 = W.isentropic_vortex(x, y, **vp)
+        self.K, self.Np, self.Nfp = self.mesh.K, self.ops.Np, self.ops.Nfp
+        self.dof = self.nf * self.K * self.Np
+        # explicit time step: the smaller of the acoustic limit h/((N+1)^2 (|u| + c))
+        # and the viscous limit h^2/((N+1)^4 max(nu, gamma nu / Pr)), h the
+        # smallest inscribed-circle diameter, with a safety factor 0.5
+        v = self.mesh.vxy[self.mesh.etov]
+        a = np.linalg.norm(v[:, 1] - v[:, 0], axis=1)
+        b = np.linalg.norm(v[:, 2] - v[:, 1], axis=1)
+        c = np.linalg.norm(v[:, 0] - v[:, 2], axis=1)
+        area = 0.5 * np.abs((v[:, 1, 0] - v[:, 0, 0]) * (v[:, 2, 1] - v[:, 0, 1])
+                            - (v[:, 2, 0] - v[:, 0, 0]) * (v[:, 1, 1] - v[:, 0, 1]))
+        h = float(np.min(4.0 * area / (a + b + c)))
+        rho, mx, my, E = self.u0
+        uu, vv = mx / rho, my / rho
+        p = 0.4 * (E - 0.5 * rho * (uu * uu + vv * vv))
+        lam = float(np.max(np.hypot(uu, vv) + np.sqrt(1.4 * p / rho)))
+        nu = float(np.max(spec["mu_ref"] * 1.5 / rho)) * max(1.0, 1.4 / 0.7)
+        q = (self.N + 1) ** 2
+        self.dt = 0.5 * min(h / (q * lam), h * h / (q * q * nu))
+        self.setup_s = time.time() - t0
+        log(f"bench: {name}: K={self.K} N={self.N} setup {self.setup_s:.1f} s, h={h:.3e}, dt={self.dt:.3e}")
+
+    def config(self):
+        return {"workload": self.name, "K": self.K, "N": self.N, "Np": self.Np, "DOF": self.dof,
+                "E_int": self.lm.E_int, "E_bdy": self.lm.E_bdy, "fields": 4, "scheme": "LSERK(5,4)",
+                "dt": self.dt, "gas": self.gas, "vortex": self.spec["vortex"]}
+
+    def time_mode(self, prec, steps, warmup, dev):
+        import torch
+        from paper_1912_06221_amd import ardg
+        u = torch.from_numpy(self.u0.copy()).to(dev)
+        work = ardg.alloc_workspace(self.lm.workspace_bytes(ardg.LSERK54, prec, 4), dev)
+        for _ in range(warmup):
+            self.lm.rk_step(u, work, self.dt, 1, scheme=ardg.LSERK54, precision=prec, nfields=4)
+        self.lm.rk_prepare(u, work, self.dt, steps, scheme=ardg.LSERK54, precision=prec, nfields=4)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        self.lm.rk_step(u, work, self.dt, steps, scheme=ardg.LSERK54, precision=prec, nfields=4)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        self.lm.check(u, nfields=4)
+        t_edge, t_elem = self.lm.stage_timing(u, work, self.dt, 40, scheme=ardg.LSERK54, precision=prec,
+                                              nfields=4)
+        return ms, t_edge, t_elem
+
+    def rhs_vs_oracle(self, prec, dev, nsample=12):
+        """max |rhs - rhs_oracle| / max |rhs_oracle| on sampled elements (one
+        right-hand side of the initial state)."""
+        import torch
+        from oracle.ns import Gas, NavierStokes
+        from paper_1912_06221_amd import ardg
+        g = self.gas
+        vp = self.spec["vortex"]
+        ns = NavierStokes(self.mesh.vxy, self.mesh.etov, self.N,
+                          Gas(gamma=g["gamma"], R=g["R"], Pr=g["Pr"], mu_ref=g["mu_ref"], T_ref=g["T_ref"],
+                              S=g["S"]),
+                          lambda x, y, t: W.isentropic_vortex(x, y, **vp), build_edges=False)
+        rng = np.random.default_rng(3)
+        els = sorted(set(rng.choice(self.K, size=nsample, replace=False).tolist()) | {0, self.K - 1})
+        dt = torch.float64 if prec == ardg.FP64 else torch.float32
+        x = torch.from_numpy(self.u0).to(dev).to(dt)
+        out = torch.empty_like(x)
+        self.lm.rhs_eval(x, out, precision=prec, nfields=4)
+        got = out.double().cpu().numpy()
+        ref = ns.rhs_elements(self.u0, els, 0.0)
+        return float(np.abs(got[:, els] - ref).max() / np.abs(ref).max())
+
+
+def bench_ns(args, dev):
+    from paper_1912_06221_amd import ardg
+    c = NSCase("ns_vortex_708x708_N3", dev)
+    out = {"config": c.config()}
+    ctr = stored_counters(c.name)
+    for mode, prec, s in (("fp64", ardg.FP64, 8), ("fp32", ardg.FP32, 4)):
+        ms, te, tl = c.time_mode(prec, args.steps, args.warmup, dev)
+        be, bl = ns_algorithmic_bytes(c.K, c.Np, c.Nfp, c.lm.E_int, c.lm.E_bdy, s)
+        r = {"ms_per_step": ms, "value": c.dof * 5 / (ms * 1e-3), "unit": "DOF*stage/s",
+             "edge_us": te * 1e3, "element_us": tl * 1e3, "edge_bytes": be, "element_bytes": bl,
+             "edge_GBps": be / (te * 1e-3) / 1e9, "element_GBps": bl / (tl * 1e-3) / 1e9}
+        r["edge_frac"] = r["edge_GBps"] / HBM_PEAK_GBS
+        r["element_frac"] = r["element_GBps"] / HBM_PEAK_GBS
+        r["edge_traffic"] = ctr.get(f"edge-{mode} hbm_bytes")
+        r["element_traffic"] = ctr.get(f"element-{mode} hbm_bytes")
+        vf = ctr.get(f"edge-{mode} valu_flops")
+        if vf is not None:
+            r[f"edge_valu_{mode}_frac"] = vf / (te * 1e-3) / 1e12 / PEAK_TFLOPS[mode]
+        if not args.no_errors:
+            r["rhs_err_vs_oracle_sampled"] = c.rhs_vs_oracle(prec, dev)
+        out[mode] = r
+        log(f"bench: {c.name} {mode}: {ms:.3f} ms/step (5 stages), edge {te*1e3:.1f} us "
+            f"({r['edge_frac']*100:.1f}% HBM), element {tl*1e3:.1f} us ({r['element_frac']*100:.1f}% HBM)")
+    return out
+
+
 def alg2_compare(case, args, dev):
     """Algorithm 2 (reconstructed coefficient times the reconstructed
     gradient) beside Algorithm 1 on an element-wise-D workload: FP64 step
@@ -528,6 +673,7 @@ def main():
     ap.add_argument("--no-errors", action="store_true", help="skip the error runs (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched workload")
+    ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes workload")
     ap.add_argument("--power-iters", type=int, default=60)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of 512 MiB first (counter calibration)")
@@ -623,6 +769,9 @@ def main():
         bb = line["batch"]
         log(f"bench: batch fp64 {bb['batched_fp64']['ms_per_step']:.3f} ms, fp32 "
             f"{bb['batched_fp32']['ms_per_step']:.3f} ms, per-mesh fp64 {bb['per_mesh_fp64']['ms_per_step']:.3f} ms")
+    if not args.no_ns:
+        line["navier_stokes"] = bench_ns(args, dev)
+        torch.cuda.empty_cache()
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -20,15 +20,8 @@ PRECS = {"fp64": (0, 1e-12), "fp32": (1, 2e-4)}
 LAWS = {"sutherland": 1, "constant": 2}
 
 
-def vortex_state(x, y, gamma=1.4, beta=5.0, uinf=(0.3, 0.2), c0=(0.5, 0.5), L=0.15):
-    xc, yc = (x - c0[0]) / L, (y - c0[1]) / L
-    f = np.exp(0.5 * (1 - xc * xc - yc * yc))
-    u = uinf[0] - beta / (2 * np.pi) * f * yc
-    v = uinf[1] + beta / (2 * np.pi) * f * xc
-    T = 1 - (gamma - 1) * beta ** 2 / (8 * gamma * np.pi ** 2) * f * f
-    rho = T ** (1 / (gamma - 1))
-    p = rho * T
-    return np.stack([rho, rho * u, rho * v, p / (gamma - 1) + 0.5 * rho * (u * u + v * v)])
+def vortex_state(x, y):
+    return W.isentropic_vortex(x, y, beta=5.0, uinf=(0.3, 0.2), c0=(0.5, 0.5), L=0.15)
 
 
 def exterior(x, y, t):

@@ -36,6 +36,12 @@ below are synthetic stand-ins with the same structure):
 * ``gaussian``: the paper's travelling Gaussian pulse of mass M released at
   time -D0/D, M / (4 pi (D t + D0)) exp(-|x - a t - x0|^2 / (4 (D t + D0))),
   an exact solution of u_t + a . grad u = D lap u (a = 0: pure diffusion).
+* ``isentropic_vortex``: the conserved variables (rho, rho u, rho v, E) of
+  the isentropic vortex of strength beta and radius L centred at c0,
+  convected with the free stream uinf (ideal gas, R = 1, p = rho^gamma), an
+  exact solution of the Euler equations; the Navier-Stokes workload's
+  initial and exterior state (the paper's Navier-Stokes tests use
+  manufactured solutions and a cylinder flow whose fields it does not print).
 """
 from __future__ import annotations
 
@@ -48,6 +54,7 @@ __all__ = [
     "Mesh", "split_square_mesh", "centroids", "circle_contrast_D",
     "loguniform_per_element", "fourier_modes", "manufactured",
     "random_nodal", "seed_for", "WORKLOADS", "batch_problems", "paper_grid", "gaussian",
+    "isentropic_vortex",
 ]
 
 
@@ -152,6 +159,13 @@ WORKLOADS = {
     "convdiff_708x708_N3_4f": dict(config=4, m=708, jitter=0.2, N=3, D="perfield",
                                    Dfield=(1e-4, 1e-3, 1e-2, 1.0), ic="fourier",
                                    velocity="rotation", steps=200, fields=4),
+    # compressible Navier-Stokes, four conserved fields: the vortex of radius
+    # 0.1 at the centre of the unit square, free stream (0.3, 0.2), Sutherland
+    # viscosity mu_ref = 1e-4 (Reynolds number 300 on the vortex radius),
+    # Pr = 0.7, gamma = 1.4; the exterior state is the initial vortex
+    "ns_vortex_708x708_N3": dict(config=5, m=708, jitter=0.2, N=3, D="navier-stokes",
+                                 ic="vortex", steps=100, fields=4, mu_ref=1e-4,
+                                 vortex=dict(beta=5.0, uinf=(0.3, 0.2), c0=(0.5, 0.5), L=0.1)),
 }
 
 
@@ -226,3 +240,19 @@ def gaussian(x, y, t, D=1.0, D0=2.0, x0=(5.0, 0.0), a=(0.0, 0.0), M=1.0):
     dx = x - a[0] * t - x0[0]
     dy = y - a[1] * t - x0[1]
     return M / (4.0 * math.pi * s) * np.exp(-(dx * dx + dy * dy) / (4.0 * s))
+
+
+def isentropic_vortex(x, y, t=0.0, gamma=1.4, beta=5.0, uinf=(0.3, 0.2), c0=(0.5, 0.5), L=0.1):
+    """(rho, rho u, rho v, E) [4, ...] of the isentropic vortex at time t:
+    f = exp((1 - r^2) / 2) with r the distance to c0 + uinf t over L,
+    u = uinf + beta / (2 pi) f (-y', x'), T = 1 - (gamma - 1) beta^2 f^2 /
+    (8 gamma pi^2), rho = T^(1/(gamma - 1)), p = rho T."""
+    xc = (x - c0[0] - uinf[0] * t) / L
+    yc = (y - c0[1] - uinf[1] * t) / L
+    f = np.exp(0.5 * (1.0 - xc * xc - yc * yc))
+    u = uinf[0] - beta / (2.0 * math.pi) * f * yc
+    v = uinf[1] + beta / (2.0 * math.pi) * f * xc
+    T = 1.0 - (gamma - 1.0) * beta ** 2 / (8.0 * gamma * math.pi ** 2) * f * f
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
