@@ -14,7 +14,9 @@ from gpu_common import library_mesh, make_case, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-PRECS = {"fp64": (0, 1e-12), "fp32": (1, 2e-4), "bf16x3": (2, 5e-2)}
+# FP32 / BF16X3 bars: about ten times the largest error measured on these
+# inputs (rhs: 3.0e-7 and 2.2e-5; FP32 states 2.1e-7)
+PRECS = {"fp64": (0, 1e-12), "fp32": (1, 5e-6), "bf16x3": (2, 2.5e-4)}
 
 
 def _g(x, y, t, f):
@@ -92,7 +94,7 @@ def test_boundary_data_time_stepping(scheme, prec):
     sch = ardg.RK4 if scheme == "rk4" else ardg.LSERK54
     step = rk4_step if scheme == "rk4" else lserk_step
     p = ardg.FP64 if prec == "fp64" else ardg.FP32
-    tol = 1e-12 if prec == "fp64" else 2e-4
+    tol = 1e-12 if prec == "fp64" else 2e-6
     dt, n, t0 = 1e-3, 30, 0.1
     ud = to_dev(u0[None])
     work = ardg.alloc_workspace(lm.workspace_bytes(sch, p, 1), ud.device)

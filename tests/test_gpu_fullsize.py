@@ -14,8 +14,11 @@ from gpu_common import to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-TOL32 = 2e-4
-TOLBF = 5e-2
+# about ten times the largest error measured on these inputs: FP32 rhs
+# 4.9e-7, FP32 RK4 increment 1.3e-7, BF16X3 rhs 1.4e-5
+TOL32 = 5e-6
+TOL32_STATE = 2e-6
+TOLBF = 2.5e-4
 
 
 def _setup(name, alg=1):
@@ -94,7 +97,7 @@ def test_fullsize_rk4_step_sampled():
     u0 = W.random_nodal(u0.shape, seed=11)
     dt = 2e-11
     ref = pr.rk4_step_elements(u0[0], dt, els)
-    for prec, tol in ((ardg.FP64, TOL64), (ardg.FP32, TOL32)):
+    for prec, tol in ((ardg.FP64, TOL64), (ardg.FP32, TOL32_STATE)):
         ud = to_dev(u0)
         work = ardg.alloc_workspace(lm.workspace_bytes(ardg.RK4, prec, 1), ud.device)
         lm.rk_step(ud, work, dt, 1, scheme=ardg.RK4, precision=prec)

@@ -4,8 +4,9 @@ The state is the isentropic vortex on a distorted split-square mesh with a
 seeded 2% perturbation; the exterior state is the unperturbed vortex scaled
 by (1 + 0.05 t), linear in t, so the library's Chebyshev-in-time
 representation reproduces it exactly.  Bars: FP64 1e-12 of max |rhs| (the
-arithmetic differs from the oracle's only in rounding order); FP32 2e-4 of
-max |rhs| (single-precision operators and fluxes, measured 1.2e-6 to 1.9e-6).
+arithmetic differs from the oracle's only in rounding order); FP32 2e-5 of
+max |rhs|, about ten times the largest error measured (1.9e-6; LSERK steps
+1.5e-6 of the increment).
 """
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ from gpu_common import to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-PRECS = {"fp64": (0, 1e-12), "fp32": (1, 2e-4)}
+PRECS = {"fp64": (0, 1e-12), "fp32": (1, 2e-5)}
 LAWS = {"sutherland": 1, "constant": 2}
 
 
@@ -121,7 +122,7 @@ def test_ns_lserk_steps_match_oracle(prec):
     inc = np.abs(ref - Q).max()
     err = np.abs(got - ref).max() / inc
     print(f"NS LSERK {prec}: max err / max increment = {err:.2e}")
-    assert err < (1e-11 if prec == "fp64" else 2e-4)
+    assert err < (1e-11 if prec == "fp64" else 2e-5)
 
 
 def test_ns_density_wave_is_exact_on_gpu():

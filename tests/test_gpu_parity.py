@@ -7,16 +7,15 @@ Tolerances:
   max|L u_r| for random data u_r of the same amplitude, because the discrete
   Laplacian's individual terms exceed its result by about N^4/h^2.  The RK
   state after k steps: ||du||_M / ||u||_M.
-* FP32 (operators and arithmetic in FP32, built from FP64): the same
-  measures with 2e-4 (FP32 rounding ~6e-8 amplified by the operator norm, up
-  to ~1e3 at N=6).  The FP64 RK update keeps state errors at that level.
-* BF16X3 (FP32 data, products on the BF16 matrix cores as hi*hi + hi*lo +
-  lo*hi with hi = bf16(x), lo = bf16(x - hi), FP32 accumulation): each
-  product keeps ~16 significant bits of its operands, a relative error of
-  about 2^-16 = 1.5e-5 per term instead of FP32's 2^-24; the same
-  amplification allowance as for FP32 (2e-4 / 2^-24 ~ 3.4e3) gives 5e-2 on
-  the max-norm measures.  The state after RK steps (FP64 update, rhs errors
-  scaled by dt) is held to the FP32 bound.
+* FP32 (operators and arithmetic in FP32, built from FP64) and BF16X3 (FP32
+  data, products on the BF16 matrix cores as hi*hi + hi*lo + lo*hi with
+  hi = bf16(x), lo = bf16(x - hi), FP32 accumulation): about ten times the
+  largest error measured on these inputs across the GPU suite (the kernels
+  are deterministic and the inputs seeded, so the measured values repeat):
+    FP32 flux / rhs measures 5e-6 (measured up to 5.9e-7), RK states 2e-6
+    (measured up to 2.1e-7);
+    BF16X3 flux / rhs measures 2.5e-4 (measured up to 2.4e-5), RK states
+    2.5e-5 (measured up to 2.3e-6).
 """
 import math
 
@@ -29,10 +28,11 @@ from gpu_common import library_mesh, make_case, oracle_problem, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-TOL32 = 2e-4
-TOLBF = 5e-2
+TOL32 = 5e-6
+TOLBF = 2.5e-4
+TOL_STATE = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 2.5e-5}
 
-PRECS = {"fp64": (0, 1e-12), "fp32": (1, 2e-4), "bf16x3": (2, 5e-2)}
+PRECS = {"fp64": (0, TOL64), "fp32": (1, TOL32), "bf16x3": (2, TOLBF)}
 
 
 def _flux_oracle(pr, u, nfields):
@@ -181,13 +181,13 @@ def test_time_stepping_heat_8x8(scheme, prec, N):
     ug = to_np(ud)[0]
     rel = mass_norm(pr, ug - uo) / mass_norm(pr, uo)
     print(f"  state rel err {rel:.2e}", flush=True)
-    assert rel <= (TOL64 if prec == "fp64" else TOL32)
+    assert rel <= TOL_STATE[prec]
     # graph replay: a second call continues from the new state
     lm.rk_step(ud, work, dt, nsteps, scheme=sch, precision=p)
     for _ in range(nsteps):
         uo = step(pr.rhs, uo, dt)
     rel2 = mass_norm(pr, to_np(ud)[0] - uo) / mass_norm(pr, uo)
-    assert rel2 <= (TOL64 if prec == "fp64" else TOL32)
+    assert rel2 <= TOL_STATE[prec]
     from oracle.rhs import error_norms
     l2, _ = error_norms(pr, to_np(ud)[0], lambda x, y: W.manufactured(x, y, 2 * nsteps * dt))
     assert l2 < 2e-3

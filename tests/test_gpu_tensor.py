@@ -12,7 +12,8 @@ from gpu_common import to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-12, 1: 2e-4}
+# FP32: about ten times the largest error measured on these inputs (5.9e-7)
+TOL = {0: 1e-12, 1: 5e-6}
 
 
 def _tensor_field(K, Np, seed):
