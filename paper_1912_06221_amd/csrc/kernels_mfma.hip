@@ -49,8 +49,12 @@ struct ElemShared {
   static constexpr int SQ = (RW > KW ? RW : KW) * 16;
   T sh[kMfmaTile * Np];
   T sqa[4][2][SQ];            // per wave: w_r, w_s, then q_x, q_y of its sub-tile, [node][column]
-  // FP32 data: Dr, Ds, LIFT read once per block, fragments built from here
-  T opl[sizeof(T) == 4 ? 2 * Np * Np + Np * 3 * (N + 1) : 1];
+  // Dr, Ds, LIFT read once per block with coalesced loads, fragments built
+  // from here (all but FP64 above N = 4, which gathers its fragments from the
+  // cache with the tile's loads)
+  static constexpr bool kOpLds = sizeof(T) == 4 || N <= 4;
+  T opl[kOpLds ? 2 * Np * Np + Np * 3 * (N + 1) : 1];
+  T rs1[2][RW];               // reference coordinates + 1 of the nodes (convection)
 };
 
 // One 64-element tile starting at element k0 of field `field`; all 256
@@ -93,16 +97,24 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
 #pragma unroll
   for (int f = 0; f < 3; ++f) code[f] = m.elem_face[f * m.K + k];
 
-  // FP32 data: Dr and Ds (adjacent in the operator buffer) and LIFT into LDS
-  // with coalesced loads, and each wave builds its fragments from there after
-  // the barrier instead of gathering them from the cache once per lane
-  // (measured faster for FP32; FP64 gathers its fragments with the other
-  // early loads)
-  constexpr bool kOpLds = sizeof(T) == 4;
+  // Dr and Ds (adjacent in the operator buffer) and LIFT into LDS with
+  // coalesced loads; each wave builds its fragments from there after the
+  // barrier instead of gathering them from the cache once per lane.  FP32,
+  // and FP64 up to N = 4, build the fragments where each product uses them,
+  // so they are not live across the tile's loads (one more wave per SIMD);
+  // the split-BF16 fragments, whose splitting costs arithmetic, are built
+  // once.
+  constexpr bool kOpLds = ElemShared<N, P>::kOpLds;
+  constexpr bool kLazy = kOpLds && !std::is_same<P, Bf16x3>::value;
   constexpr int NO1 = 2 * Np * Np, NO = NO1 + Np * NJ;
   T* opl = S.opl;
   if (kOpLds)
     for (int i = threadIdx.x; i < NO; i += kMfmaThreads) opl[i] = opg[i < NO1 ? L.dr + i : L.lift + (i - NO1)];
+  if (CONV && threadIdx.x < RW) {
+    const int nd = threadIdx.x < Np ? threadIdx.x : 0;
+    S.rs1[0][threadIdx.x] = opg[L.nr + nd] + T(1);
+    S.rs1[1][threadIdx.x] = opg[L.ns + nd] + T(1);
+  }
   TileIO<TileShape<N, kMfmaTile, kMfmaThreads>::Q> io;
   tile_begin<N, T, kMfmaTile, kMfmaThreads>(m, k0, field, vin, epi, sh, io, kPre);
 
@@ -125,29 +137,37 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       G[c][t] = sgn * x;
     }
 
-  // operator fragments: row 16 mt + col, columns kidx(c, grp, .)
-  frag_t aDr[MT][KC], aDs[MT][KC], aL[MT][KL];
-  auto build_frags = [&](const T* odr, const T* ods, const T* olift) {
-  #pragma unroll
+  // operator fragments (from LDS, or gathered from the operator buffer):
+  // row 16 mt + col, columns kidx(c, grp, .)
+  const T* odr = kOpLds ? opl : opg + L.dr;
+  const T* olift = kOpLds ? opl + NO1 : opg + L.lift;
+  auto build_d = [&](frag_t (&aDr)[MT][KC], frag_t (&aDs)[MT][KC]) {
+#pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = 16 * mt + col;
-  #pragma unroll
+#pragma unroll
       for (int c = 0; c < KC; ++c) {
         T vr[KPL], vs[KPL];
-  #pragma unroll
+#pragma unroll
         for (int t = 0; t < KPL; ++t) {
           const int kk = kidx<M>(c, grp, t);
           const bool ok = row < Np && kk < Np;
           vr[t] = ok ? odr[row * Np + kk] : T(0);
-          vs[t] = ok ? ods[row * Np + kk] : T(0);
+          vs[t] = ok ? odr[Np * Np + row * Np + kk] : T(0);
         }
         aDr[mt][c] = M::make(vr);
         aDs[mt][c] = M::make(vs);
       }
-  #pragma unroll
+    }
+  };
+  auto build_l = [&](frag_t (&aL)[MT][KL]) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = 16 * mt + col;
+#pragma unroll
       for (int c = 0; c < KL; ++c) {
         T vl[KPL];
-  #pragma unroll
+#pragma unroll
         for (int t = 0; t < KPL; ++t) {
           const int kk = kidx<M>(c, grp, t);
           vl[t] = (row < Np && kk < NJ) ? olift[row * NJ + kk] : T(0);
@@ -156,33 +176,16 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       }
     }
   };
-  if (!kOpLds) build_frags(opg + L.dr, opg + L.ds, opg + L.lift);
-  // reference coordinates (+1) of the nodes this lane touches (convection)
-  T r1a[MT][4], s1a[MT][4], r1f[KL][KPL], s1f[KL][KPL];
-  if (CONV) {
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int node = 16 * mt + M::row(grp, r);
-        const int nc = node < Np ? node : 0;
-        r1a[mt][r] = opg[L.nr + nc] + T(1);
-        s1a[mt][r] = opg[L.ns + nc] + T(1);
-      }
-#pragma unroll
-    for (int c = 0; c < KL; ++c)
-#pragma unroll
-      for (int t = 0; t < KPL; ++t) {
-        const int q = kidx<M>(c, grp, t);
-        const int qc = q < NJ ? q : 0;
-        const int f = qc / Nfp;
-        const int nd = fnode(N, f, qc - f * Nfp);
-        r1f[c][t] = opg[L.nr + nd] + T(1);
-        s1f[c][t] = opg[L.ns + nd] + T(1);
-      }
+  frag_t aDr[MT][KC], aDs[MT][KC], aL[MT][KL];
+  if (!kOpLds) {
+    build_d(aDr, aDs);
+    build_l(aL);
   }
   __syncthreads();
-  if (kOpLds) build_frags(opl, opl + Np * Np, opl + NO1);
+  if (kOpLds && !kLazy) {
+    build_d(aDr, aDs);
+    build_l(aL);
+  }
 
   // ---- compute ----
   const ElemGeom gm = elem_geom(p1, p2, p3);
@@ -204,6 +207,7 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
     bu[c] = M::make(v);
   }
   acc_t ur[MT], us[MT];
+  if (kLazy) build_d(aDr, aDs);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     ur[mt] = M::zero();
@@ -248,8 +252,9 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       T wr = D * (rx * qx + ry * qy);
       T ws = D * (sx * qx + sy * qy);
       if (CONV) {
-        const T vx = (T)ev.x1 + r1a[mt][r] * (T)ev.xr + s1a[mt][r] * (T)ev.xs;
-        const T vy = (T)ev.y1 + r1a[mt][r] * (T)ev.yr + s1a[mt][r] * (T)ev.ys;
+        const T r1 = S.rs1[0][node], s1 = S.rs1[1][node];
+        const T vx = (T)ev.x1 + r1 * (T)ev.xr + s1 * (T)ev.xs;
+        const T vy = (T)ev.y1 + r1 * (T)ev.yr + s1 * (T)ev.ys;
         const T un = (valid && node < Np) ? sh[el * Np + (node < Np ? node : 0)] : T(0);
         wr -= (rx * vx + ry * vy) * un;
         ws -= (sx * vx + sy * vy) * un;
@@ -275,6 +280,7 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       bs[c] = M::make(vs);
     }
     // two independent accumulator chains (Dr and Ds), summed afterwards
+    if (kLazy) build_d(aDr, aDs);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       acc_t rr = M::zero(), rs = M::zero();
@@ -314,14 +320,16 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       const T nx = (T)sn.x, ny = (T)sn.y;
       T jv = G[c][t] - D * (nx * sq[0][nd * 16 + col] + ny * sq[1][nd * 16 + col]);
       if (CONV) {
-        const T vx = (T)ev.x1 + r1f[c][t] * (T)ev.xr + s1f[c][t] * (T)ev.xs;
-        const T vy = (T)ev.y1 + r1f[c][t] * (T)ev.yr + s1f[c][t] * (T)ev.ys;
+        const T r1 = S.rs1[0][nd], s1 = S.rs1[1][nd];
+        const T vx = (T)ev.x1 + r1 * (T)ev.xr + s1 * (T)ev.xs;
+        const T vy = (T)ev.y1 + r1 * (T)ev.yr + s1 * (T)ev.ys;
         jv += (nx * vx + ny * vy) * sh[el * Np + nd];
       }
       vj[t] = (valid && q < NJ) ? iJ * jv : T(0);
     }
     bj[c] = M::make(vj);
   }
+  if (kLazy) build_l(aL);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     acc_t rl = M::zero();
