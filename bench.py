@@ -47,13 +47,15 @@ HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 HEADLINE = "convdiff_708x708_N3_4f"
 ROTATION = (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)
+# edge kernel implementations (ardg_mesh_set_kernels)
+EDGE_KERNELS = {"auto": 0, "split": 1, "lane": 2, "staged": 5}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_tensor.hip", "kernels_ns.hip",
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_edge_staged.hip", "kernels_tensor.hip", "kernels_ns.hip",
                   "kernel_common.hpp", "edge_common.hpp", "mfma.hpp", "device.hpp")
 
 
@@ -138,10 +140,11 @@ def algorithmic_flops(K, Np, Nfp, N, E_int, alg1, nfields):
 class Case:
     """One workload on the device: library mesh, initial data, time step."""
 
-    def __init__(self, name, dev, power_iters):
+    def __init__(self, name, dev, power_iters, edge_kernel="auto"):
         import torch
         from paper_1912_06221_amd import ardg
         self.name = name
+        self.edge_kernel = edge_kernel
         spec = W.WORKLOADS[name]
         self.spec = spec
         cfg = spec["config"]
@@ -151,6 +154,7 @@ class Case:
         self.nf = spec["fields"]
         self.ops = ardg.Ops(self.N)
         self.lm = ardg.Mesh(self.ops, self.mesh.vxy, self.mesh.etov, device=0)
+        self.lm.set_kernels(EDGE_KERNELS[edge_kernel])
         self.D, self.D_mode = workload_D(spec, self.mesh)
         self.alg1 = self.D_mode == "element"
         if self.alg1:
@@ -189,7 +193,7 @@ class Case:
         return {"workload": self.name, "K": self.K, "N": self.N, "Np": self.Np, "DOF": self.dof,
                 "E_int": self.lm.E_int, "E_bdy": self.lm.E_bdy, "fields": self.nf,
                 "D": self.spec["D"], "velocity": self.spec.get("velocity"), "scheme": "RK4",
-                "dt": self.dt, "config_steps": self.spec["steps"]}
+                "dt": self.dt, "config_steps": self.spec["steps"], "edge_kernel": self.edge_kernel}
 
     def time_mode(self, prec, steps, warmup, dev):
         """ms per RK4 step over `steps` graph-replayed steps, and the per-kernel
@@ -675,6 +679,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched workload")
     ap.add_argument("--no-ns", action="store_true", help="skip the Navier-Stokes workload")
     ap.add_argument("--power-iters", type=int, default=60)
+    ap.add_argument("--edge-kernel", default="auto", choices=sorted(EDGE_KERNELS),
+                    help="edge kernel implementation (default: chosen by the library)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device copy of 512 MiB first (counter calibration)")
     args = ap.parse_args()
@@ -702,7 +708,7 @@ def main():
         del a, b
 
     modes = [m for m in args.modes.split(",") if m]
-    head = Case(args.workload, dev, args.power_iters)
+    head = Case(args.workload, dev, args.power_iters, args.edge_kernel)
     hr = measure_case(head, args, dev, modes, 0 if args.no_errors else head.spec["steps"])
     r64 = hr["fp64"]
     dom = "element" if r64["element_us"] >= r64["edge_us"] else "edge"
@@ -748,7 +754,7 @@ def main():
         line["errors"] = hr["errors"]
     extras = {}
     for name in [x for x in args.extras.split(",") if x]:
-        c = Case(name, dev, args.power_iters)
+        c = Case(name, dev, args.power_iters, args.edge_kernel)
         # the precision workload states every mode's error after its steps
         steps = c.spec["steps"] if (not args.no_errors and name.startswith("loguniform")) else 0
         r = measure_case(c, args, dev, modes, steps)

@@ -272,7 +272,7 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
   T v[Np];
 #pragma unroll
   for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
-  const T D = DM != DM_CONST ? (T)m.Delem[k] : (T)m.Dfield[field];
+  const T D = DM != DM_CONST ? (T)m.Delem[k] : (T)field_D(m, field);
   T t[Np], c[Np];
   rotate_to_face<N, T>(v, fa, t, trace);
   matvec<Np, Np, T>(op + L.n2b, t, c);
@@ -315,6 +315,20 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
   }
 }
 
+// Upwind flux of a boundary face (u+ outside: 0, or the prescribed exterior
+// state), subtracted from the diffusive flux F.
+template <int N, typename T>
+__device__ inline void boundary_upwind(const DevMesh& m, cptr<T> op, double2 vn, const T* tr, const T* gtr, T* F) {
+  constexpr OpLayout L(N);
+  constexpr int Nfp = L.Nfp;
+#pragma unroll
+  for (int j = 0; j < Nfp; ++j) {
+    const T tau = op[L.tau + j];
+    const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
+    F[j] -= vnj * ((vnj > (T)0) ? tr[j] : gtr[j]);
+  }
+}
+
 // Boundary face e with its upwind convective flux (u+ outside: 0, or the
 // prescribed exterior state), written to the flux array.
 template <int N, typename T, int DM>
@@ -327,17 +341,65 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   T F[Nfp], tr[Nfp], gtr[Nfp];
   double2 vn = make_double2(0.0, 0.0);
   boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr, vn, gtr);
+  if (m.conv) boundary_upwind<N, T>(m, op, vn, tr, gtr, F);
+  T* out = flux + ((int64_t)field * E + e) * Nfp;
+#pragma unroll
+  for (int j = 0; j < Nfp; ++j) out[j] = F[j];
+}
+
+// The flux of one interior edge from both sides' Bernstein coefficients in
+// their rotated frames (c[0]: side 1, c[1]: side 2, before the subdivision):
+// de Casteljau subdivision at each side's apex, the reconstruction operator
+// (Algorithm 1's blocks with element-wise D, Algorithm 2's weights), and
+// with convection the upwind flux from the sides' nodal traces tr1, tr2 (each
+// in its own counter-clockwise order).  F receives sJ * flux.
+template <int N, typename T, int DM, bool PF>
+__device__ inline void interior_flux(const DevMesh& m, cptr<T> op, int field, T (&c)[2][(N + 1) * (N + 2) / 2],
+                                     double2 mu1, double2 mu2, double2 g, double2 vn, double D1d, double D2d,
+                                     const T* tr1, const T* tr2, T* F) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp;
+  decasteljau<N, T>(c[0], mu1);
+  decasteljau<N, T>(c[1], mu2);
+  const T* cc = &c[0][0];
+  const T gR = (T)g.x, gS = (T)g.y;
+  if (DM == DM_ALG1) {
+    const T D1 = (T)D1d, D2 = (T)D2d;
+    if (D1d == D2d) {
+      // equal coefficients: Algorithm 1 reduces exactly to D (U1 - U2) c
+      T gg[2 * Nfp];
+      matvec_sel<PF, 2 * Nfp, 2 * Np, T>(op + L.udr, cc, gg);
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j) F[j] = D1 * (gR * gg[j] + gS * gg[Nfp + j]);
+    } else {
+      T gg[4 * Nfp];
+      matvec_sel<PF, 4 * Nfp, 2 * Np, T>(op + L.u1r, cc, gg);
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j)
+        F[j] = D1 * (gR * gg[j] + gS * gg[Nfp + j]) - D2 * (gR * gg[2 * Nfp + j] + gS * gg[3 * Nfp + j]);
+    }
+  } else {
+    const T D = (T)field_D(m, field);
+    T gg[2 * Nfp];
+    matvec_sel<PF, 2 * Nfp, 2 * Np, T>(op + L.kr, cc, gg);
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T Dj = DM == DM_ALG2 ? alg2_coef<N, T>(op, j, (T)D1d, (T)D2d) : D;
+      F[j] = Dj * (gR * gg[j] + gS * gg[Nfp + j]);
+    }
+  }
   if (m.conv) {
+    // upwind flux f* = max(n.v,0) u- + min(n.v,0) u+, subtracted from the
+    // diffusive flux; n.v is linear along the edge (affine velocity)
 #pragma unroll
     for (int j = 0; j < Nfp; ++j) {
       const T tau = op[L.tau + j];
       const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
-      F[j] -= vnj * ((vnj > (T)0) ? tr[j] : gtr[j]);
+      const T up = tr2[N - j];
+      const T fs = (vnj > (T)0) ? vnj * tr1[j] : vnj * up;
+      F[j] -= fs;
     }
   }
-  T* out = flux + ((int64_t)field * E + e) * Nfp;
-#pragma unroll
-  for (int j = 0; j < Nfp; ++j) out[j] = F[j];
 }
 
 // One lane per edge.
@@ -364,10 +426,10 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
       D1d = m.Delem[k1];
       D2d = m.Delem[k2];
     }
-    // rotate, convert to Bernstein coefficients, subdivide each side at its
-    // apex.  Up to moderate order both elements are loaded at once and
-    // converted with one pass over the conversion matrix; above it the sides
-    // go one after the other to stay within the register file.
+    // rotate, convert to Bernstein coefficients.  Up to moderate order both
+    // elements are loaded at once and converted with one pass over the
+    // conversion matrix; above it the sides go one after the other to stay
+    // within the register file.
     T c[2][Np];
     if (kBoth) {
       T v[2][Np], t[2][Np];
@@ -389,53 +451,11 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
         matvec_sel<kBoth, Np, Np, T>(op + L.n2b, t, c[sd]);
       }
     }
-    decasteljau<N, T>(c[0], mu1);
-    decasteljau<N, T>(c[1], mu2);
-    const T* cc = &c[0][0];
-    const T gR = (T)g.x, gS = (T)g.y;
-    if (DM == DM_ALG1) {
-      const T D1 = (T)D1d, D2 = (T)D2d;
-      if (D1d == D2d) {
-        // equal coefficients: Algorithm 1 reduces exactly to D (U1 - U2) c
-        T gg[2 * Nfp];
-        matvec_sel<kBoth, 2 * Nfp, 2 * Np, T>(op + L.udr, cc, gg);
-#pragma unroll
-        for (int j = 0; j < Nfp; ++j) F[j] = D1 * (gR * gg[j] + gS * gg[Nfp + j]);
-      } else {
-        T gg[4 * Nfp];
-        matvec_sel<kBoth, 4 * Nfp, 2 * Np, T>(op + L.u1r, cc, gg);
-#pragma unroll
-        for (int j = 0; j < Nfp; ++j)
-          F[j] = D1 * (gR * gg[j] + gS * gg[Nfp + j]) - D2 * (gR * gg[2 * Nfp + j] + gS * gg[3 * Nfp + j]);
-      }
-    } else {
-      const T D = (T)m.Dfield[field];
-      T gg[2 * Nfp];
-      matvec_sel<kBoth, 2 * Nfp, 2 * Np, T>(op + L.kr, cc, gg);
-#pragma unroll
-      for (int j = 0; j < Nfp; ++j) {
-        const T Dj = DM == DM_ALG2 ? alg2_coef<N, T>(op, j, (T)D1d, (T)D2d) : D;
-        F[j] = Dj * (gR * gg[j] + gS * gg[Nfp + j]);
-      }
-    }
+    interior_flux<N, T, DM, kBoth>(m, op, field, c, mu1, mu2, g, vn, D1d, D2d, tr1, tr2, F);
   } else {
     T gtr[Nfp];
     boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr1, vn, gtr);
-    // side 2's trace in its own order: u+ outside (0, or the exterior state)
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) tr2[j] = gtr[N - j];
-  }
-  if (m.conv) {
-    // upwind flux f* = max(n.v,0) u- + min(n.v,0) u+, subtracted from the
-    // diffusive flux; n.v is linear along the edge (affine velocity)
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) {
-      const T tau = op[L.tau + j];
-      const T vnj = (T)vn.x + tau * (T)(vn.y - vn.x);
-      const T up = tr2[N - j];
-      const T fs = (vnj > (T)0) ? vnj * tr1[j] : vnj * up;
-      F[j] -= fs;
-    }
+    if (m.conv) boundary_upwind<N, T>(m, op, vn, tr1, gtr, F);
   }
   T* out = flux + ((int64_t)field * E + e) * Nfp;
 #pragma unroll

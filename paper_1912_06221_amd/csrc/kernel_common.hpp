@@ -78,6 +78,14 @@ template <> __device__ inline cptr<float> opbase<float>(const DevMesh& m) {
   return (cptr<float>)uniform_ptr(m.ops32);
 }
 
+// The constant D of a field, for a wave-uniform field index: a scalar load
+// of the device copy (the kernel-argument array, indexed at run time, would
+// be read through a generic address, whose wait also holds every scalar load
+// before it).
+__device__ inline double field_D(const DevMesh& m, int field) {
+  return ((cptr<double>)uniform_ptr(m.Dfield_dev))[__builtin_amdgcn_readfirstlane(field)];
+}
+
 // Affine map of a triangle (v1, v2, v3) onto the reference triangle: x_r =
 // (v2 - v1) / 2, x_s = (v3 - v1) / 2, J = x_r y_s - x_s y_r, and the inverse
 // metric r_x = y_s / J, r_y = -x_s / J, s_x = -y_r / J, s_y = x_r / J
@@ -135,13 +143,14 @@ template <int N> struct ElemTune {
 
 // One tile = TILE consecutive elements handled by NT threads.  Their nodal
 // values form one contiguous chunk of the [F][K][Np] array: tile_begin stages
-// it through LDS (sh, TILE*Np entries) with coalesced loads and fetches the
+// it through LDS (sh, TileShape::LDS entries) with coalesced loads and fetches the
 // operands of the Runge-Kutta update with the same coalesced pattern; the
 // element compute replaces sh's values by du/dt; tile_end runs the update over
 // the chunk's degrees of freedom with coalesced global traffic.  Each thread
 // owns Q = ceil(TILE*Np/NT) of the chunk's entries, i = thread + q*NT.
-template <int Q>
+template <int Q, typename T>
 struct TileIO {
+  T x[Q];                // the tile's stage input, in flight to LDS
   double Up[Q], Ap[Q];
   int nel, ndof;
   int64_t base;
@@ -152,12 +161,17 @@ template <int N, int TILE, int NT>
 struct TileShape {
   static constexpr int Np = (N + 1) * (N + 2) / 2;
   static constexpr int Q = (TILE * Np + NT - 1) / NT;
+  static constexpr int LDS = Q * NT;   // entries of the tile's LDS buffer (padded)
 };
 
+// Issues the global loads of a tile (stage input, and the update operands
+// when prefetch is set) into registers.  Loads are issued unconditionally
+// from clamped (in-tile) indices and masked afterwards: a load under a
+// branch is followed by a wait at the branch's end, which would serialise
+// the round trips.
 template <int N, typename T, int TILE, int NT = TILE>
-__device__ inline void tile_begin(const DevMesh& m, int64_t k0, int field, const T* __restrict__ vin,
-                                  const Epilogue& epi, T* sh, TileIO<TileShape<N, TILE, NT>::Q>& io,
-                                  bool prefetch) {
+__device__ inline void tile_load(const DevMesh& m, int64_t k0, int field, const T* __restrict__ vin,
+                                 const Epilogue& epi, TileIO<TileShape<N, TILE, NT>::Q, T>& io, bool prefetch) {
   constexpr int Np = TileShape<N, TILE, NT>::Np, Q = TileShape<N, TILE, NT>::Q;
   const int t = threadIdx.x;
   io.nel = (int)((m.K - k0) < TILE ? (m.K - k0) : TILE);
@@ -165,38 +179,49 @@ __device__ inline void tile_begin(const DevMesh& m, int64_t k0, int field, const
   io.base = ((int64_t)field * m.K + k0) * Np;
   io.rk = epi.kind != EPI_RHS;
   io.need_acc = io.rk && epi.stage != 0;
-  // Loads are issued unconditionally from clamped (in-tile) indices and masked
-  // afterwards: a load under a branch is followed by a wait at the branch's
-  // end, which would serialise the round trips.
-  T x[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = t + q * NT;
-    x[q] = vin[io.base + (i < io.ndof ? i : 0)];
+    io.x[q] = vin[io.base + (i < io.ndof ? i : 0)];
   }
-  if (prefetch && io.rk) {
-    const double* U = epi.u + io.base;
-    const double* A = io.need_acc ? epi.acc + io.base : epi.u + io.base;
+  if (prefetch) {
+    // without an update (right-hand side only) the operand loads read the
+    // stage input's first value: no branch around them; the accumulator is
+    // read (and used) from stage 1 on
+    const double* U = io.rk ? epi.u + io.base : (const double*)vin;
+    const double* A = io.need_acc ? epi.acc + io.base : U;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int i = t + q * NT;
-      const int ic = i < io.ndof ? i : 0;
+      const int ic = (io.rk && i < io.ndof) ? i : 0;
       io.Up[q] = U[ic];
       io.Ap[q] = A[ic];
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (!io.need_acc) io.Ap[q] = 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int i = t + q * NT;
-    if (i < io.ndof) sh[i] = x[q];
   }
 }
 
+// Stores the loaded stage input into the tile's LDS buffer (TileShape::LDS
+// entries): unconditionally, so that no branch asks for the loads' wait
+// early; entries past the tile's degrees of freedom hold copies of its first
+// value and are never read back as results.
 template <int N, typename T, int TILE, int NT = TILE>
-__device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, TILE, NT>::Q>& io,
+__device__ inline void tile_stage(T* sh, const TileIO<TileShape<N, TILE, NT>::Q, T>& io) {
+  constexpr int Q = TileShape<N, TILE, NT>::Q;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sh[threadIdx.x + q * NT] = io.x[q];
+}
+
+// tile_load + tile_stage (sh: TileShape::LDS entries).
+template <int N, typename T, int TILE, int NT = TILE>
+__device__ inline void tile_begin(const DevMesh& m, int64_t k0, int field, const T* __restrict__ vin,
+                                  const Epilogue& epi, T* sh, TileIO<TileShape<N, TILE, NT>::Q, T>& io,
+                                  bool prefetch) {
+  tile_load<N, T, TILE, NT>(m, k0, field, vin, epi, io, prefetch);
+  tile_stage<N, T, TILE, NT>(sh, io);
+}
+
+template <int N, typename T, int TILE, int NT = TILE>
+__device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, TILE, NT>::Q, T>& io,
                                 bool prefetched) {
   constexpr int Q = TileShape<N, TILE, NT>::Q;
   const int t = threadIdx.x;

@@ -150,7 +150,7 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
       F[j] = a1 * a[0] + b1 * a[1] + a2 * a[2] + b2 * a[3];
     });
   } else {
-    const T D = DM == DM_ALG1 ? (T)in.D1 : (T)m.Dfield[field];
+    const T D = DM == DM_ALG1 ? (T)in.D1 : (T)field_D(m, field);
     const T a1 = D * gR, b1 = D * gS;
     auto emit = [&](int j, const T* a) { F[j] = a1 * a[0] + b1 * a[1]; };
     matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (DM == DM_ALG1 ? L.udr : L.kr) + s * Np, c, emit);
@@ -253,7 +253,7 @@ __device__ inline void load_elem_in(const DevMesh& m, int64_t k, int field,
   in.p1 = m.vert[3 * k];
   in.p2 = m.vert[3 * k + 1];
   in.p3 = m.vert[3 * k + 2];
-  in.D = m.dmode != DM_CONST ? m.Delem[k] : m.Dfield[field];
+  in.D = m.dmode != DM_CONST ? m.Delem[k] : field_D(m, field);
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const int code = m.elem_face[f * m.K + k];
@@ -349,7 +349,7 @@ __device__ inline void element_tile(const DevMesh& m, cptr<T> op, int64_t k0, in
   constexpr int Np = (N + 1) * (N + 2) / 2;
   constexpr bool kPre = ElemTune<N>::prefetch;
   const int t = threadIdx.x;
-  TileIO<TileShape<N, TILE, TILE>::Q> io;
+  TileIO<TileShape<N, TILE, TILE>::Q, T> io;
   tile_begin<N, T, TILE>(m, k0, field, vin, epi, sh, io, kPre);
   ElemIn<N + 1, T> in;
   if (t < io.nel) load_elem_in<N, T>(m, k0 + t, field, flux, in);
@@ -533,6 +533,7 @@ hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void*
   if (m.edge_kernel == EDGE_SPLIT_MFMA || (prec == PREC_BF16X3 && m.edge_kernel == EDGE_AUTO && m.N <= 3))
     return launch_edge_split_mfma(m, prec, nfields, u, flux, st);
   if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) return launch_edge_mfma(m, prec, nfields, u, flux, st);
+  if (m.edge_kernel == EDGE_STAGED) return launch_edge_staged(m, prec, nfields, u, flux, st);
   return prec == PREC_FP64 ? edge_dispatch<double>(m, nfields, u, flux, st)
                            : edge_dispatch<float>(m, nfields, u, flux, st);
 }

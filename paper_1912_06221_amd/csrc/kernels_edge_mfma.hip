@@ -173,7 +173,7 @@ __device__ inline void edge_tile_mfma(const DevMesh& m, const typename Mma<P>::T
   }
 
   // flux at the diagonal nodes; lane group grp holds nodes of edge 16 sb + col
-  const T Dc = (T)m.Dfield[field];
+  const T Dc = (T)field_D(m, field);
 #pragma unroll
   for (int sb = 0; sb < 4; ++sb) {
     const int el = 16 * sb + col;
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
       F[j] = a1 * a[0] + b1 * a[1] + a2 * a[2] + b2 * a[3];
     });
   } else {
-    const T D = DM == DM_ALG1 ? (T)D1d : (T)m.Dfield[field];
+    const T D = DM == DM_ALG1 ? (T)D1d : (T)field_D(m, field);
     const T a1 = D * gR, b1 = D * gS;
     auto emit = [&](int j, const T* a) { F[j] = a1 * a[0] + b1 * a[1]; };
     matvec_groups<2, Nfp, Nfp, Np, K2, T, decltype(emit), 16>(op + (DM == DM_ALG1 ? L.udr : L.kr) + s * Np, c, emit);

@@ -47,14 +47,16 @@ struct ElemShared {
   static constexpr int KC = (Np + M::KSTEP - 1) / M::KSTEP;
   static constexpr int RW = 16 * MT, KW = M::KSTEP * KC;
   static constexpr int SQ = (RW > KW ? RW : KW) * 16;
-  T sh[kMfmaTile * Np];
+  T sh[TileShape<N, kMfmaTile, kMfmaThreads>::LDS];
   T sqa[4][2][SQ];            // per wave: w_r, w_s, then q_x, q_y of its sub-tile, [node][column]
   // Dr, Ds, LIFT read once per block with coalesced loads, fragments built
   // from here (all but FP64 above N = 4, which gathers its fragments from the
   // cache with the tile's loads)
   static constexpr bool kOpLds = sizeof(T) == 4 || N <= 4;
-  T opl[kOpLds ? 2 * Np * Np + Np * 3 * (N + 1) : 1];
-  T rs1[2][RW];               // reference coordinates + 1 of the nodes (convection)
+  static constexpr int NO = 2 * Np * Np + Np * 3 * (N + 1);
+  static constexpr int QO = (NO + 255) / 256;      // entries per thread of the copy
+  T opl[kOpLds ? QO * 256 : 1];
+  T rs1[2][64];               // reference coordinates + 1 of the nodes (convection)
 };
 
 // One 64-element tile starting at element k0 of field `field`; all 256
@@ -88,14 +90,20 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
   const T* opg = (const T*)(sizeof(T) == 8 ? (const void*)m.ops64 : (const void*)m.ops32);
 
   // ---- loads: element data, face map, stage input, update operands ----
+  // Every global load of the tile is issued before the first wait, and the
+  // LDS stores that follow are unconditional, so the only dependent round
+  // trip is face map -> fluxes.
   const int el = st * 16 + col;
   const bool valid = k0 + el < m.K;
   const int64_t k = valid ? k0 + el : k0;
-  const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
-  const double Dd = TENS ? 1.0 : (m.dmode != DM_CONST ? m.Delem[k] : m.Dfield[field]);
   int code[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) code[f] = m.elem_face[f * m.K + k];
+  const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
+  // D: element-wise, or the field's constant (one load from either table,
+  // no branch)
+  const bool Dk = m.dmode != DM_CONST;
+  const double Dd = TENS ? 1.0 : (Dk ? m.Delem : m.Dfield_dev)[Dk ? k : (int64_t)field];
 
   // Dr and Ds (adjacent in the operator buffer) and LIFT into LDS with
   // coalesced loads; each wave builds its fragments from there after the
@@ -106,17 +114,25 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
   // once.
   constexpr bool kOpLds = ElemShared<N, P>::kOpLds;
   constexpr bool kLazy = kOpLds && !std::is_same<P, Bf16x3>::value;
-  constexpr int NO1 = 2 * Np * Np, NO = NO1 + Np * NJ;
+  constexpr int NO1 = 2 * Np * Np, NO = NO1 + Np * NJ, QO = ElemShared<N, P>::QO;
   T* opl = S.opl;
-  if (kOpLds)
-    for (int i = threadIdx.x; i < NO; i += kMfmaThreads) opl[i] = opg[i < NO1 ? L.dr + i : L.lift + (i - NO1)];
-  if (CONV && threadIdx.x < RW) {
-    const int nd = threadIdx.x < Np ? threadIdx.x : 0;
-    S.rs1[0][threadIdx.x] = opg[L.nr + nd] + T(1);
-    S.rs1[1][threadIdx.x] = opg[L.ns + nd] + T(1);
+  T ov[kOpLds ? QO : 1];
+  if (kOpLds) {
+#pragma unroll
+    for (int q = 0; q < QO; ++q) {
+      const int i = threadIdx.x + q * kMfmaThreads;
+      const int ic = i < NO ? i : 0;
+      ov[q] = opg[ic < NO1 ? L.dr + ic : L.lift + (ic - NO1)];
+    }
   }
-  TileIO<TileShape<N, kMfmaTile, kMfmaThreads>::Q> io;
-  tile_begin<N, T, kMfmaTile, kMfmaThreads>(m, k0, field, vin, epi, sh, io, kPre);
+  T rsv[2] = {T(0), T(0)};
+  if (CONV) {
+    const int nd = (threadIdx.x & 63) < Np ? (threadIdx.x & 63) : 0;
+    rsv[0] = opg[L.nr + nd] + T(1);
+    rsv[1] = opg[L.ns + nd] + T(1);
+  }
+  TileIO<TileShape<N, kMfmaTile, kMfmaThreads>::Q, T> io;
+  tile_load<N, T, kMfmaTile, kMfmaThreads>(m, k0, field, vin, epi, io, kPre);
 
   // face fluxes in the B layout of the lift: value q = kidx(c, grp, t) is node
   // q % Nfp of face q / Nfp, read from its edge (reversed and negated on side
@@ -136,6 +152,18 @@ __device__ inline void element_mfma_tile(const DevMesh& m, int64_t k0, int field
       const T sgn = (valid && q < NJ) ? (side2 ? T(-1) : T(1)) : T(0);
       G[c][t] = sgn * x;
     }
+
+  // LDS stores of the loaded operators, node coordinates and stage input
+  if (kOpLds) {
+#pragma unroll
+    for (int q = 0; q < QO; ++q) opl[threadIdx.x + q * kMfmaThreads] = ov[q];
+  }
+  if (CONV) {
+    // every wave stores the same 64 values (no branch on the thread index)
+    S.rs1[0][threadIdx.x & 63] = rsv[0];
+    S.rs1[1][threadIdx.x & 63] = rsv[1];
+  }
+  tile_stage<N, T, kMfmaTile, kMfmaThreads>(sh, io);
 
   // operator fragments (from LDS, or gathered from the operator buffer):
   // row 16 mt + col, columns kidx(c, grp, .)
