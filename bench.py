@@ -48,14 +48,14 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 HEADLINE = "convdiff_708x708_N3_4f"
 ROTATION = (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)
 # edge kernel implementations (ardg_mesh_set_kernels)
-EDGE_KERNELS = {"auto": 0, "split": 1, "lane": 2, "staged": 5}
+EDGE_KERNELS = {"auto": 0, "split": 1, "lane": 2}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_edge_staged.hip", "kernels_tensor.hip", "kernels_ns.hip",
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_tensor.hip", "kernels_ns.hip",
                   "kernel_common.hpp", "edge_common.hpp", "mfma.hpp", "device.hpp")
 
 

@@ -73,9 +73,7 @@ enum {
   ARDG_EDGE_SPLIT = 1,       /* two waves per 64-edge tile, one per side, vector unit        */
   ARDG_EDGE_LANE = 2,        /* one lane per edge, vector unit                               */
   ARDG_EDGE_MFMA = 3,        /* one wave per 64 edges on the matrix cores                    */
-  ARDG_EDGE_SPLIT_MFMA = 4,  /* side-split tiles, nodal -> Bernstein on the matrix cores     */
-  ARDG_EDGE_STAGED = 5       /* tiles of <= 256 edges whose distinct elements are staged in
-                                LDS and converted to Bernstein form once, vector unit       */
+  ARDG_EDGE_SPLIT_MFMA = 4   /* side-split tiles, nodal -> Bernstein on the matrix cores     */
 };
 
 /* ardg_ops_export selectors (row-major double arrays). */
@@ -114,14 +112,7 @@ enum {
   ARDG_MESH_BFACE_GHOST_NODES = 5  /* double [E_bdy][Np][2]: physical points of the nodes of each
                                 boundary face's ghost sub-triangle (P2, B, A) (the reference
                                 nodes mapped with those vertices): where the exterior state
-                                of ardg_mesh_set_boundary_data is sampled                    */,
-  ARDG_MESH_STAGE_TILES = 6, /* int32 [ntiles+1][2]: first interior edge and first entry of
-                                ARDG_MESH_STAGE_ELEMS of each staged edge tile (the last row
-                                closes the last tile): consecutive interior edges, at most 256
-                                of them, touching at most 256 distinct elements              */
-  ARDG_MESH_STAGE_ELEMS = 7, /* int32: each tile's distinct elements, ascending              */
-  ARDG_MESH_STAGE_SLOTS = 8  /* int32 [E_int]: l1 | l2 << 8 | f1 << 16 | f2 << 18, the
-                                positions of the edge's sides in its tile's element list     */
+                                of ardg_mesh_set_boundary_data is sampled                    */
 };
 
 typedef struct ardg_ops_s* ardg_ops;
@@ -206,11 +197,7 @@ ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfield
  * N >= 5) and one lane per edge otherwise, and for ARDG_BF16X3 the
  * matrix-core kernels (side-split up to N = 3).  Split-BF16 products exist
  * only on the matrix cores, so with ARDG_BF16X3 the vector-unit choices
- * (ARDG_EDGE_SPLIT, ARDG_EDGE_LANE, ARDG_EDGE_STAGED) run ARDG_EDGE_MFMA.
- * The staged tiles (built by ardg_mesh_create for every mesh) use the
- * rotation identity of the Bernstein basis: relabelling a triangle's
- * vertices permutes Bernstein multi-indices as it permutes the node lattice
- * (section "Reordering nodes in the reference domain").  Drops the mesh's
+ * (ARDG_EDGE_SPLIT, ARDG_EDGE_LANE) run ARDG_EDGE_MFMA.  Drops the mesh's
  * captured step graphs.  Errors: E_INVALID_ARG. */
 ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel);
 

@@ -21,7 +21,7 @@ RK4, LSERK54 = 0, 1
 D_CONST, D_ELEMENT, D_ELEMENT_ALG2, D_NODAL, D_SOLUTION = 0, 1, 2, 3, 4
 VEL_NONE, VEL_AFFINE = 0, 1
 NS_OFF, NS_SUTHERLAND, NS_CONSTANT_MU = 0, 1, 2
-EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA, EDGE_STAGED = 0, 1, 2, 3, 4, 5
+EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA = 0, 1, 2, 3, 4
 
 OPS_NODES, OPS_V, OPS_DR, OPS_DS, OPS_MASS, OPS_LIFT = 0, 1, 2, 3, 4, 5
 OPS_FACE_NODES, OPS_ROT_PERM, OPS_RECON_A, OPS_RECON_R = 6, 7, 8, 9
@@ -29,7 +29,6 @@ OPS_RECON_GRAD, OPS_ALG1_GRAD, OPS_N2B, OPS_ALG2_W = 10, 11, 12, 13
 OPS_RECON_VALUE = 14
 MESH_EDGES, MESH_BFACES, MESH_EDGE_GEOM, MESH_BFACE_GEOM, MESH_ELEM_FACES = 0, 1, 2, 3, 4
 MESH_BFACE_GHOST_NODES = 5
-MESH_STAGE_TILES, MESH_STAGE_ELEMS, MESH_STAGE_SLOTS = 6, 7, 8
 
 
 class ArdgError(RuntimeError):
@@ -177,8 +176,7 @@ class Mesh:
     def export(self, which: int) -> np.ndarray:
         n = c_int64()
         lib().ardg_mesh_export(self.handle, which, None, 0, ctypes.byref(n))
-        is_int = which in (MESH_EDGES, MESH_BFACES, MESH_ELEM_FACES, MESH_STAGE_TILES, MESH_STAGE_ELEMS,
-                          MESH_STAGE_SLOTS)
+        is_int = which in (MESH_EDGES, MESH_BFACES, MESH_ELEM_FACES)
         out = np.empty(n.value, dtype=np.int32 if is_int else np.float64)
         _check(lib().ardg_mesh_export(self.handle, which, out.ctypes.data_as(c_void_p),
                                       out.nbytes, ctypes.byref(n)))

@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         cmds.append(host + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_edge_staged.hip", "kernels_tensor.hip", "kernels_ns.hip", "noalloc.hip"):
+    for src in ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_tensor.hip", "kernels_ns.hip", "noalloc.hip"):
         kobj = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmds.append([hipcc, f"--offload-arch={ARCH}"] + common + HIP_DEVICE_FLAGS +
                     ["-c", os.path.join(CSRC, src), "-o", kobj])

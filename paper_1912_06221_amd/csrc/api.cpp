@@ -349,13 +349,10 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
       for (int f = 0; f < 3; ++f) efc[f * h.K + k] = h.elem_face[3 * k + f];
     std::vector<float> packed32(m->packed.begin(), m->packed.end());
     std::vector<double> Dinit(kMaxFields, 1.0);
-    std::vector<int2> stiles(h.stile_edge.size());
-    for (size_t t = 0; t < stiles.size(); ++t) stiles[t] = make_int2(h.stile_edge[t], h.stile_elem[t]);
 
-    int2 *d_ef, *d_stiles; double2 *d_mu1, *d_mu2, *d_gam, *d_bmu, *d_bgam, *d_vert;
+    int2* d_ef; double2 *d_mu1, *d_mu2, *d_gam, *d_bmu, *d_bgam, *d_vert;
     double* d_Dfield;
-    int *d_bk, *d_efc, *d_sulist;
-    uint32_t* d_seloc;
+    int *d_bk, *d_efc;
     double* d_ops64;
     float* d_ops32;
     ardg_status s;
@@ -365,7 +362,7 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
     if (ptr) m->allocs.push_back((void*)ptr);
     UP(ef, d_ef) UP(mu1, d_mu1) UP(mu2, d_mu2) UP(gam, d_gam) UP(bk, d_bk) UP(bmu, d_bmu)
     UP(bgam, d_bgam) UP(vert, d_vert) UP(efc, d_efc) UP(m->packed, d_ops64) UP(packed32, d_ops32)
-    UP(stiles, d_stiles) UP(h.sulist, d_sulist) UP(h.seloc, d_seloc) UP(Dinit, d_Dfield)
+    UP(Dinit, d_Dfield)
 #undef UP
     m->dm.ef = d_ef;
     m->dm.mu1 = d_mu1;
@@ -380,10 +377,6 @@ ardg_status ardg_mesh_create(ardg_ops ops, const double* vxy, int64_t Nv, const 
     m->dm.ops32 = d_ops32;
     m->dm.Dfield_dev = d_Dfield;
     m->Dfield_dev = d_Dfield;
-    m->dm.stiles = d_stiles;
-    m->dm.sulist = d_sulist;
-    m->dm.seloc = d_seloc;
-    m->dm.ntiles = (int64_t)stiles.size() - 1;
     *out = m.release();
     return ARDG_OK;
   } catch (const std::bad_alloc&) {
@@ -425,13 +418,6 @@ ardg_status ardg_mesh_export(ardg_mesh mesh, int32_t which, void* dst, int64_t c
       for (int64_t b = 0; b < h.E_bdy; ++b) { iv.push_back(h.bk[b]); iv.push_back(h.bf[b]); }
       break;
     case ARDG_MESH_ELEM_FACES: iv = h.elem_face; break;
-    case ARDG_MESH_STAGE_TILES:
-      for (size_t t = 0; t < h.stile_edge.size(); ++t) { iv.push_back(h.stile_edge[t]); iv.push_back(h.stile_elem[t]); }
-      break;
-    case ARDG_MESH_STAGE_ELEMS: iv = h.sulist; break;
-    case ARDG_MESH_STAGE_SLOTS:
-      for (uint32_t v : h.seloc) iv.push_back((int32_t)v);
-      break;
     case ARDG_MESH_EDGE_GEOM:
       is_int = false;
       for (int64_t e = 0; e < h.E_int; ++e) {
@@ -735,7 +721,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel) {
   if (!mesh) return fail(ARDG_E_INVALID_ARG, "set_kernels: null handle");
-  if (edge_kernel < ARDG_EDGE_AUTO || edge_kernel > ARDG_EDGE_STAGED)
+  if (edge_kernel < ARDG_EDGE_AUTO || edge_kernel > ARDG_EDGE_SPLIT_MFMA)
     return fail(ARDG_E_INVALID_ARG, "set_kernels: unknown edge kernel");
   mesh->dm.edge_kernel = edge_kernel;
   mesh->drop_graphs();

@@ -67,8 +67,7 @@ struct OpLayout {
 // latency-bound (few waves per SIMD, or high order with few waves resident)
 // and EDGE_LANE otherwise; split-BF16 products run on EDGE_SPLIT_MFMA up to
 // N = 3 and on EDGE_MFMA above.
-// EDGE_STAGED stages each tile's distinct elements through LDS (FP64, FP32).
-enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, EDGE_SPLIT_MFMA = 4, EDGE_STAGED = 5 };
+enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, EDGE_SPLIT_MFMA = 4 };
 
 // Diffusion coefficient forms (values as ARDG_D_* in the C ABI): one
 // constant per field, or element-wise with the flux of Algorithm 1
@@ -98,15 +97,6 @@ struct DevMesh {
   const int* elem_face = nullptr; // [3][K] (edge << 1) | side
   const double* Delem = nullptr;  // [K] when D is element-wise
   const double2* vn = nullptr;    // [E] n1.v at A and at B (affine velocity)
-  // staged edge tiles: tile t holds interior edges [stiles[t].x,
-  // stiles[t+1].x) and the distinct elements sulist[stiles[t].y ..
-  // stiles[t+1].y) (at most 256 of each, elements ascending); per interior
-  // edge, its sides' positions in that list and their faces:
-  // l1 | l2 << 8 | f1 << 16 | f2 << 18
-  const int2* stiles = nullptr;
-  const int* sulist = nullptr;
-  const unsigned* seloc = nullptr;
-  int64_t ntiles = 0;
   // prescribed exterior state at the nodes of each boundary face's ghost
   // sub-triangle (P2, B, A), [F][E_bdy][Np] at the current stage time, or
   // null (zero Dirichlet data through the mirror ghost)
@@ -184,10 +174,6 @@ hipError_t launch_edge_tensor(const DevMesh& m, int prec, int nfields, const voi
 hipError_t launch_edge_ns(const DevMesh& m, int prec, const void* q, void* flux, hipStream_t st);
 hipError_t launch_element_ns(const DevMesh& m, int prec, const void* vin, const void* flux, const Epilogue& epi,
                              hipStream_t st);
-// Edge kernel with each tile's distinct elements staged through LDS and
-// converted once (same contract as launch_edge_flux; FP64 and FP32).
-hipError_t launch_edge_staged(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
-                              hipStream_t st);
 // Edge kernel with interior edges on the matrix cores (same contract as
 // launch_edge_flux).
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,

@@ -533,7 +533,6 @@ hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void*
   if (m.edge_kernel == EDGE_SPLIT_MFMA || (prec == PREC_BF16X3 && m.edge_kernel == EDGE_AUTO && m.N <= 3))
     return launch_edge_split_mfma(m, prec, nfields, u, flux, st);
   if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) return launch_edge_mfma(m, prec, nfields, u, flux, st);
-  if (m.edge_kernel == EDGE_STAGED) return launch_edge_staged(m, prec, nfields, u, flux, st);
   return prec == PREC_FP64 ? edge_dispatch<double>(m, nfields, u, flux, st)
                            : edge_dispatch<float>(m, nfields, u, flux, st);
 }

@@ -237,41 +237,7 @@ int build_host_mesh(const double* vxy, int64_t Nv, const int32_t* etov, int64_t 
     gammas(P, A, B, n, &m.bgam[2 * b]);
     m.elem_face[3 * k + fa] = int32_t((m.E_int + b) << 1);
   }
-  build_stage_tiles(m);
   return ARDG_OK;
-}
-
-void build_stage_tiles(HostMesh& m) {
-  m.stile_edge.clear();
-  m.stile_elem.clear();
-  m.sulist.clear();
-  m.seloc.assign(m.E_int, 0u);
-  std::vector<int32_t> stamp(m.K, -1), slot(m.K, 0), cur;
-  int64_t e = 0;
-  int32_t tile = 0;
-  while (e < m.E_int) {
-    m.stile_edge.push_back((int32_t)e);
-    m.stile_elem.push_back((int32_t)m.sulist.size());
-    cur.clear();
-    const int64_t e0 = e;
-    while (e < m.E_int && e - e0 < kStageMax) {
-      const int32_t k1 = m.e1[e], k2 = m.e2[e];
-      const int need = (stamp[k1] != tile) + (stamp[k2] != tile);
-      if ((int)cur.size() + need > kStageMax) break;
-      if (stamp[k1] != tile) { stamp[k1] = tile; cur.push_back(k1); }
-      if (stamp[k2] != tile) { stamp[k2] = tile; cur.push_back(k2); }
-      ++e;
-    }
-    std::sort(cur.begin(), cur.end());
-    for (size_t i = 0; i < cur.size(); ++i) slot[cur[i]] = (int32_t)i;
-    m.sulist.insert(m.sulist.end(), cur.begin(), cur.end());
-    for (int64_t q = e0; q < e; ++q)
-      m.seloc[q] = (uint32_t)slot[m.e1[q]] | ((uint32_t)slot[m.e2[q]] << 8) | ((uint32_t)m.f1[q] << 16) |
-                   ((uint32_t)m.f2[q] << 18);
-    ++tile;
-  }
-  m.stile_edge.push_back((int32_t)m.E_int);
-  m.stile_elem.push_back((int32_t)m.sulist.size());
 }
 
 }  // namespace ardg

@@ -23,20 +23,8 @@ struct HostMesh {
   std::vector<int32_t> bk, bf;             // [E_bdy]
   std::vector<double> bP1, bmu, bgam;      // [E_bdy][2]
   std::vector<int32_t> elem_face;          // [K][3] (edge << 1) | side
-  // staged edge tiles: consecutive interior edges, at most kStageMax of them,
-  // touching at most kStageMax distinct elements.  Tile t: edges
-  // [stile_edge[t], stile_edge[t+1]), distinct elements (ascending)
-  // sulist[stile_elem[t] .. stile_elem[t+1]); per interior edge, the
-  // positions of its sides in its tile's list: l1 | l2 << 8 | f1 << 16 | f2 << 18
-  std::vector<int32_t> stile_edge, stile_elem, sulist;
-  std::vector<uint32_t> seloc;
   double min_J = 0.0, min_area_ratio = 1.0;
 };
-
-constexpr int kStageMax = 256;
-
-// Cuts the interior edges into the staged tiles (fills the s* members).
-void build_stage_tiles(HostMesh& m);
 
 // Returns 0 on success or a negative ardg status with a message in err.
 int build_host_mesh(const double* vxy, int64_t Nv, const int32_t* etov, int64_t K,

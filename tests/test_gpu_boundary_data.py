@@ -69,7 +69,7 @@ def test_boundary_data_flux_and_rhs(case, prec):
     assert err <= tol
     # the same through every edge kernel implementation (FP64)
     if prec == "fp64":
-        for kern in (ardg.EDGE_SPLIT, ardg.EDGE_LANE, ardg.EDGE_MFMA, ardg.EDGE_SPLIT_MFMA, ardg.EDGE_STAGED):
+        for kern in (ardg.EDGE_SPLIT, ardg.EDGE_LANE, ardg.EDGE_MFMA, ardg.EDGE_SPLIT_MFMA):
             lm.set_kernels(kern)
             lm.rhs_eval(ud, rhs, precision=p, nfields=nf, t=t)
             e2 = np.abs(to_np(rhs) - ro).max() / np.abs(ro).max()

@@ -152,61 +152,6 @@ def test_mesh_setup_matches_oracle(L, m, jit):
         assert abs(lm.info.min_area_ratio - 1.0) < 1e-12   # all parallelograms
 
 
-
-def _check_stage_tiles(lm, E_int, edges):
-    tiles = lm.export(ardg.MESH_STAGE_TILES).reshape(-1, 2)
-    elems = lm.export(ardg.MESH_STAGE_ELEMS)
-    slots = lm.export(ardg.MESH_STAGE_SLOTS).astype(np.int64) & 0xFFFFFFFF
-    assert tiles[0, 0] == 0 and tiles[0, 1] == 0
-    assert tiles[-1, 0] == E_int and tiles[-1, 1] == elems.size
-    assert slots.size == E_int
-    ne = np.diff(tiles[:, 0])
-    nu = np.diff(tiles[:, 1])
-    assert (ne >= 1).all() and (ne <= 256).all() and (nu >= 1).all() and (nu <= 256).all()
-    for t in range(tiles.shape[0] - 1):
-        ul = elems[tiles[t, 1]:tiles[t + 1, 1]]
-        assert (np.diff(ul) > 0).all()                   # distinct, ascending
-        used = np.zeros(ul.size, dtype=bool)
-        for e in range(tiles[t, 0], tiles[t + 1, 0]):
-            k1, f1, k2, f2 = edges[e]
-            s = slots[e]
-            l1, l2, fa, fb = s & 0xFF, (s >> 8) & 0xFF, (s >> 16) & 3, (s >> 18) & 3
-            assert ul[l1] == k1 and ul[l2] == k2 and fa == f1 and fb == f2
-            used[l1] = used[l2] = True
-        assert used.all()                                # no element staged for nothing
-    # a tile closes only when the next edge would exceed one of the limits
-    for t in range(tiles.shape[0] - 2):
-        if ne[t] < 256:
-            e = tiles[t + 1, 0]
-            ul = set(elems[tiles[t, 1]:tiles[t + 1, 1]].tolist())
-            extra = len({edges[e][0], edges[e][2]} - ul)
-            assert len(ul) + extra > 256
-
-
-@pytest.mark.parametrize("m,jit", [(3, 0.0), (14, 0.2), (40, 0.2)])
-def test_stage_tiles_cover_every_interior_edge(L, m, jit):
-    """The staged edge kernel's tiles: every interior edge in exactly one
-    tile, in order, at most 256 edges and 256 distinct elements per tile, and
-    each edge's slots name its own two elements and faces."""
-    mesh = W.split_square_mesh(m, jit, seed=m)
-    lm = ardg.Mesh(ardg.Ops(2), mesh.vxy, mesh.etov, device=-1)
-    edges = lm.export(ardg.MESH_EDGES).reshape(-1, 4)
-    _check_stage_tiles(lm, edges.shape[0], edges)
-
-
-def test_stage_tiles_shuffled_numbering(L):
-    """With a random element numbering a tile's edges scatter over the mesh:
-    the tiles still obey both limits (the distinct-element limit closes them
-    first)."""
-    mesh = W.split_square_mesh(30, 0.2, seed=5)
-    perm = np.random.default_rng(4).permutation(mesh.K)
-    etov = mesh.etov[perm]
-    lm = ardg.Mesh(ardg.Ops(1), mesh.vxy, etov, device=-1)
-    edges = lm.export(ardg.MESH_EDGES).reshape(-1, 4)
-    _check_stage_tiles(lm, edges.shape[0], edges)
-    tiles = lm.export(ardg.MESH_STAGE_TILES).reshape(-1, 2)
-    assert (np.diff(tiles[:, 1]) == 256).sum() >= 1
-
 def test_error_paths(L):
     o = ardg.Ops(2)
     mesh = W.split_square_mesh(2, 0.0)
