@@ -118,39 +118,46 @@ __device__ inline void primitive_field(const GasC<T>& g, const S* q, int64_t str
   }
 }
 
-// One primitive field's reconstruction on an edge: the value and the
-// physical gradient at the diagonal nodes.
-template <int N, int F, typename T>
-__device__ inline void recon_field(const DevMesh& m, cptr<T> op, const GasC<T>& g, const T* q, int64_t KN,
-                                   bool interior, int k1, int fa, double2 mu1, int k2, int fb, double2 mu2,
-                                   int64_t bi, T rx, T ry, T sx, T sy, T* val, T* gx, T* gy) {
+// One side's share of the reconstruction of the three primitive fields on an
+// edge.  The side's conserved values are read once; u, v and T at its nodes
+// are rotated to the face, converted to Bernstein coefficients and
+// subdivided at the apex (the ghost sub-triangle of a boundary face is
+// already in its frame: GHOST), and the operator columns acting on this
+// side's coefficients (SIDE 0: the first Np, 1: the last Np) are added into
+// the value and the reference gradient at the diagonal nodes.  The flux is
+// linear in each side's coefficients, so the two sides' shares add up.
+template <int N, int SIDE, bool GHOST, typename T, typename S>
+__device__ inline void recon_side(cptr<T> op, const GasC<T>& g, const S* q, int64_t stride, int64_t off, int f,
+                                  double2 mu, T (&val)[3][N + 1], T (&dR)[3][N + 1], T (&dS)[3][N + 1]) {
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
-  T c[2 * Np];
-  {
-    T pv[Np], tr[Nfp];
-    primitive_field<N, F, T, T>(g, q, KN, (int64_t)k1 * Np, pv);
-    project_side<N, T>(op, pv, fa, mu1, c, tr);
-  }
-  if (interior) {
-    T pv[Np], tr[Nfp];
-    primitive_field<N, F, T, T>(g, q, KN, (int64_t)k2 * Np, pv);
-    project_side<N, T>(op, pv, fb, mu2, c + Np, tr);
-  } else {
-    // the exterior state at the ghost sub-triangle's nodes, already in its
-    // own frame (P2, B, A): no rotation, no subdivision
-    T pv[Np];
-    primitive_field<N, F, T, double>(g, m.ghost, m.E_bdy * Np, bi * Np, pv);
-    matvec<Np, Np, T>(op + L.n2b, pv, c + Np);
-  }
-  T dR[Nfp], dS[Nfp];
-  matvec<Nfp, 2 * Np, T>(op + L.kv, c, val);
-  matvec<Nfp, 2 * Np, T>(op + L.kr, c, dR);
-  matvec<Nfp, 2 * Np, T>(op + L.ks, c, dS);
+  T pv[3][Np];
 #pragma unroll
-  for (int j = 0; j < Nfp; ++j) {
-    gx[j] = rx * dR[j] + sx * dS[j];
-    gy[j] = ry * dR[j] + sy * dS[j];
+  for (int n = 0; n < Np; ++n) {
+    const T rho = (T)q[off + n], mx = (T)q[stride + off + n], my = (T)q[2 * stride + off + n];
+    const T E = (T)q[3 * stride + off + n];
+    T p;
+    primitives(g, rho, mx, my, E, pv[0][n], pv[1][n], p, pv[2][n]);
+  }
+#pragma unroll
+  for (int F = 0; F < 3; ++F) {
+    T c[Np];
+    if (GHOST) {
+      matvec<Np, Np, T>(op + L.n2b, pv[F], c);
+    } else {
+      T tr[Nfp];
+      project_side<N, T>(op, pv[F], f, mu, c, tr);
+    }
+    T a[Nfp], b[Nfp], d[Nfp];
+    matvec_ld<Nfp, Np, 2 * Np, T>(op + L.kv + SIDE * Np, c, a);
+    matvec_ld<Nfp, Np, 2 * Np, T>(op + L.kr + SIDE * Np, c, b);
+    matvec_ld<Nfp, Np, 2 * Np, T>(op + L.ks + SIDE * Np, c, d);
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      val[F][j] += a[j];
+      dR[F][j] += b[j];
+      dS[F][j] += d[j];
+    }
   }
 }
 
@@ -188,11 +195,29 @@ __global__ __launch_bounds__(256) void edge_ns_kernel(DevMesh m, const T* __rest
   const T rx = (T)gpm.x, ry = (T)gpm.y, sx = (T)gpm.z, sy = (T)gpm.w;
   const T snx = (T)snd.x, sny = (T)snd.y;
 
-  // reconstructed (u, v, T) and their physical gradients at the diagonal nodes
+  // reconstructed (u, v, T) and their physical gradients at the diagonal
+  // nodes: each side's share in turn, so that one side's values are live at
+  // a time
   T val[3][Nfp], gx[3][Nfp], gy[3][Nfp];
-  recon_field<N, 0, T>(m, op, g, q, KN, interior, k1, fa, mu1, k2, fb, mu2, bi, rx, ry, sx, sy, val[0], gx[0], gy[0]);
-  recon_field<N, 1, T>(m, op, g, q, KN, interior, k1, fa, mu1, k2, fb, mu2, bi, rx, ry, sx, sy, val[1], gx[1], gy[1]);
-  recon_field<N, 2, T>(m, op, g, q, KN, interior, k1, fa, mu1, k2, fb, mu2, bi, rx, ry, sx, sy, val[2], gx[2], gy[2]);
+  {
+    T dR[3][Nfp], dS[3][Nfp];
+#pragma unroll
+    for (int F = 0; F < 3; ++F)
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j) val[F][j] = dR[F][j] = dS[F][j] = T(0);
+    recon_side<N, 0, false, T, T>(op, g, q, KN, (int64_t)k1 * Np, fa, mu1, val, dR, dS);
+    if (interior)
+      recon_side<N, 1, false, T, T>(op, g, q, KN, (int64_t)k2 * Np, fb, mu2, val, dR, dS);
+    else
+      recon_side<N, 1, true, T, double>(op, g, m.ghost, m.E_bdy * Np, bi * Np, 0, mu2, val, dR, dS);
+#pragma unroll
+    for (int F = 0; F < 3; ++F)
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j) {
+        gx[F][j] = rx * dR[F][j] + sx * dS[F][j];
+        gy[F][j] = ry * dR[F][j] + sy * dS[F][j];
+      }
+  }
 
   // face traces: side 1's node j meets side 2's node N - j; at a boundary
   // face the exterior state at the ghost's node (j, N - j) of its lattice
