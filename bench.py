@@ -55,16 +55,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip", "kernels_tensor.hip", "kernels_ns.hip",
+# device sources each workload's kernels are compiled from (a stored counter
+# summary is used only while these hash to the value it records)
+KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "kernels_edge_mfma.hip",
                   "kernel_common.hpp", "edge_common.hpp", "mfma.hpp", "device.hpp")
+NS_KERNEL_SOURCES = ("kernels_ns.hip", "kernel_common.hpp", "edge_common.hpp", "device.hpp")
 
 
-def kernel_source_hash():
-    """SHA-256 over the device-code sources, to tie stored counter data to the
-    kernels it was measured on."""
+def sources_of(workload):
+    return NS_KERNEL_SOURCES if workload.startswith("ns_") else KERNEL_SOURCES
+
+
+def kernel_source_hash(workload=None):
+    """SHA-256 over the device-code sources of a workload's kernels, to tie
+    stored counter data to the kernels it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (sources_of(workload) if workload else KERNEL_SOURCES):
         with open(os.path.join(ROOT, "paper_1912_06221_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -86,7 +93,7 @@ def stored_counters(workload):
             elif line.startswith("per-launch "):
                 k, v = line[len("per-launch "):].split(":", 1)
                 vals[k.strip()] = float(v)
-    if src != kernel_source_hash():
+    if src != kernel_source_hash(workload):
         return {}
     return vals
 
