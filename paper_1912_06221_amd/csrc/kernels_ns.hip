@@ -222,6 +222,12 @@ __global__ __launch_bounds__(256) void edge_ns_kernel(DevMesh m, const T* __rest
   // face traces: side 1's node j meets side 2's node N - j; at a boundary
   // face the exterior state at the ghost's node (j, N - j) of its lattice
   const T sJ = sqrt(snx * snx + sny * sny);
+  // FP32: the lane's fluxes wait in LDS (its own column) until every node is
+  // done, so that each field's Nfp values leave as one contiguous write
+  // (FP64 writes them node by node: the register file is full)
+  constexpr bool kStage = sizeof(T) == 4;
+  __shared__ T sOut[kStage ? 4 : 1][kStage ? Nfp : 1][kStage ? 256 : 1];
+  const int tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < Nfp; ++j) {
     const int64_t i1 = (int64_t)k1 * Np + fnode(N, fa, j);
@@ -257,7 +263,22 @@ __global__ __launch_bounds__(256) void edge_ns_kernel(DevMesh m, const T* __rest
 #pragma unroll
     for (int cc = 1; cc < 4; ++cc) H[cc] += Gx[cc - 1] * snx + Gy[cc - 1] * sny;
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) flux[((int64_t)cc * E + e) * Nfp + j] = H[cc];
+    for (int cc = 0; cc < 4; ++cc) {
+      if constexpr (kStage)
+        sOut[cc][j][tid] = H[cc];
+      else
+        flux[((int64_t)cc * E + e) * Nfp + j] = H[cc];
+    }
+  }
+  if constexpr (kStage) {
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      T h[Nfp];
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j) h[j] = sOut[cc][j][tid];
+#pragma unroll
+      for (int j = 0; j < Nfp; ++j) flux[((int64_t)cc * E + e) * Nfp + j] = h[j];
+    }
   }
 }
 
@@ -283,11 +304,12 @@ struct NsTile {
 };
 
 // Runge-Kutta epilogue for one degree of freedom (the same update as the
-// scalar element kernels' tile epilogue).
+// scalar element kernels' tile epilogue), with the update operands U and A
+// already loaded (A is read from stage 1 on).
 template <typename T>
-__device__ inline void epilogue_dof(const Epilogue& epi, int64_t i, T r_t) {
+__device__ inline void epilogue_dof(const Epilogue& epi, int64_t i, T r_t, double U, double A, bool act) {
   if (epi.kind == EPI_RHS) {
-    ((T*)epi.rhs_out)[i] = r_t;
+    if (act) ((T*)epi.rhs_out)[i] = r_t;
     return;
   }
   const double r = (double)r_t, dt = epi.dt;
@@ -296,34 +318,51 @@ __device__ inline void epilogue_dof(const Epilogue& epi, int64_t i, T r_t) {
     const int s = epi.stage;
     if (s < 3) {
       const double c = (s < 2) ? 0.5 * dt : dt;
-      epi.acc[i] = (s == 0) ? r : epi.acc[i] + 2.0 * r;
-      if (vn) vn[i] = (T)(epi.u[i] + c * r);
+      if (act) {
+        epi.acc[i] = (s == 0) ? r : A + 2.0 * r;
+        if (vn) vn[i] = (T)(U + c * r);
+      }
     } else {
-      const double un = epi.u[i] + dt / 6.0 * (epi.acc[i] + r);
-      epi.u[i] = un;
-      if (vn) vn[i] = (T)un;
+      const double un = U + dt / 6.0 * (A + r);
+      if (act) {
+        epi.u[i] = un;
+        if (vn) vn[i] = (T)un;
+      }
     }
   } else {
     const double rr = dt * r;
-    const double res = (epi.stage == 0) ? rr : epi.a * epi.acc[i] + rr;
-    epi.acc[i] = res;
-    const double un = epi.u[i] + epi.b * res;
-    epi.u[i] = un;
-    if (vn) vn[i] = (T)un;
+    const double res = (epi.stage == 0) ? rr : epi.a * A + rr;
+    const double un = U + epi.b * res;
+    if (act) {
+      epi.acc[i] = res;
+      epi.u[i] = un;
+      if (vn) vn[i] = (T)un;
+    }
   }
 }
 
+// One block: TE elements, one thread per element node.  Every global load
+// of the tile -- the operators for LDS, the conserved values, each
+// element's vertices (by one thread per element), the face map and the
+// interface fluxes of this thread's face nodes, and the update operands --
+// is issued before the first wait; indices are clamped and results masked,
+// so no load sits under a branch.  Per-element geometry (inverse metric, 1/J,
+// sJ n of each face) is formed once and shared through LDS.
 template <int N, typename T>
 __global__ __launch_bounds__(256) void element_ns_kernel(DevMesh m, const T* __restrict__ vin,
                                                          const T* __restrict__ flux, Epilogue epi) {
   using Tl = NsTile<N>;
   constexpr OpLayout L(N);
   constexpr int Np = Tl::Np, Nfp = Tl::Nfp, TE = Tl::TE, ND = Tl::ND, NJ = Tl::NJ;
+  constexpr int NO = 2 * Np * Np + Np * NJ;        // Dr, Ds, LIFT
+  constexpr int QO = (NO + 255) / 256;
+  constexpr int QJ = (TE * NJ + 255) / 256;        // face nodes per thread
   __shared__ T sQ[4][ND];
   __shared__ T sP[3][ND];        // u, v, T
   __shared__ T sH[8][ND];        // H_x then H_y of the four fields
-  __shared__ T sJv[4][TE * NJ];  // lift inputs
-  __shared__ T sOp[2 * Np * Np + Np * NJ];   // Dr, Ds, LIFT
+  __shared__ T sJv[4][QJ * 256]; // lift inputs
+  __shared__ T sOp[QO * 256];    // Dr, Ds, LIFT
+  __shared__ double sG[TE][11];  // r_x, r_y, s_x, s_y, 1/J, sJ n of the three faces
   const cptr<T> op = opbase<T>(m);
   const GasC<T> g = gas_consts<T>(m);
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
@@ -333,33 +372,94 @@ __global__ __launch_bounds__(256) void element_ns_kernel(DevMesh m, const T* __r
   const int ndof = nel * Np;
   const int64_t KN = m.K * Np;
   const int64_t E = m.E_int + m.E_bdy;
-
-  for (int i = t; i < 2 * Np * Np; i += blockDim.x) sOp[i] = op[L.dr + i];   // Dr then Ds (adjacent)
-  for (int i = t; i < Np * NJ; i += blockDim.x) sOp[2 * Np * Np + i] = op[L.lift + i];
   const bool act = t < ndof;
-  const int el = act ? t / Np : 0, n = act ? t - (t / Np) * Np : 0;
-  const int64_t k = k0 + el;
-  if (act) {
-    T Q[4];
+  const int tc = act ? t : 0;
+  const int el = tc / Np, n = tc - (tc / Np) * Np;
+
+  // ---- loads ----
+  int code[QJ];
+#pragma unroll
+  for (int r = 0; r < QJ; ++r) {
+    const int idx = t + r * 256;
+    const int ic = idx < nel * NJ ? idx : 0;
+    const int e2 = ic / NJ, f = (ic - e2 * NJ) / Nfp;
+    code[r] = m.elem_face[f * m.K + k0 + e2];
+  }
+  T ov[QO];
+#pragma unroll
+  for (int r = 0; r < QO; ++r) {
+    const int i = t + r * 256;
+    const int ic = i < NO ? i : 0;
+    ov[r] = ic < 2 * Np * Np ? op[L.dr + ic] : op[L.lift + ic - 2 * Np * Np];
+  }
+  T Q[4];
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) Q[cc] = vin[cc * KN + k0 * Np + tc];
+  const int64_t kv = k0 + (t < nel ? t : 0);
+  const double2 p1 = m.vert[3 * kv], p2 = m.vert[3 * kv + 1], p3 = m.vert[3 * kv + 2];
+  // update operands (read from the stage input's first value when there is
+  // no update: no branch around the loads)
+  const bool rk = epi.kind != EPI_RHS;
+  const bool need_acc = rk && epi.stage != 0;
+  const double* Ub = rk ? epi.u : (const double*)vin;
+  const double* Ab = need_acc ? epi.acc : Ub;
+  double Up[4], Ap[4];
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) {
+    const int64_t i = rk ? cc * KN + k0 * Np + tc : 0;
+    Up[cc] = Ub[i];
+    Ap[cc] = Ab[i];
+  }
+  // interface fluxes of this thread's face nodes, side 1's order and sign
+  T Gs[QJ][4];
+#pragma unroll
+  for (int r = 0; r < QJ; ++r) {
+    const int idx = t + r * 256;
+    const int ic = idx < nel * NJ ? idx : 0;
+    const int j = (ic - (ic / NJ) * NJ) % Nfp;
+    const bool side2 = code[r] & 1;
+    const int64_t fo = (int64_t)(code[r] >> 1) * Nfp + (side2 ? Nfp - 1 - j : j);
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
-      Q[cc] = vin[cc * KN + k0 * Np + t];
-      sQ[cc][t] = Q[cc];
+      const T x = flux[(int64_t)cc * E * Nfp + fo];
+      Gs[r][cc] = side2 ? -x : x;
     }
+  }
+
+  // ---- LDS: operators, conserved and primitive values, geometry ----
+#pragma unroll
+  for (int r = 0; r < QO; ++r) sOp[t + r * 256] = ov[r];
+  if (act) {
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) sQ[cc][t] = Q[cc];
     T u, v, p, Tt;
     primitives(g, Q[0], Q[1], Q[2], Q[3], u, v, p, Tt);
     sP[0][t] = u;
     sP[1][t] = v;
     sP[2][t] = Tt;
   }
+  if (t < TE) {
+    const ElemGeom gm = elem_geom(p1, p2, p3);
+    double* G = sG[t];
+    G[0] = gm.rx;
+    G[1] = gm.ry;
+    G[2] = gm.sx;
+    G[3] = gm.sy;
+    G[4] = gm.iJ;
+    // sJ n of face f, (t_y, -t_x) / 2 for its counter-clockwise edge vector t
+    G[5] = 0.5 * (p2.y - p1.y);
+    G[6] = -0.5 * (p2.x - p1.x);
+    G[7] = 0.5 * (p3.y - p2.y);
+    G[8] = -0.5 * (p3.x - p2.x);
+    G[9] = 0.5 * (p1.y - p3.y);
+    G[10] = -0.5 * (p1.x - p3.x);
+  }
   __syncthreads();
 
-  const double2 p1 = m.vert[3 * k], p2 = m.vert[3 * k + 1], p3 = m.vert[3 * k + 2];
-  const ElemGeom gm = elem_geom(p1, p2, p3);
-  const T rx = (T)gm.rx, ry = (T)gm.ry, sx = (T)gm.sx, sy = (T)gm.sy;
   const T* Dr = sOp;
   const T* Ds = sOp + Np * Np;
   const T* Lf = sOp + 2 * Np * Np;
+  const T rx = (T)sG[el][0], ry = (T)sG[el][1], sx = (T)sG[el][2], sy = (T)sG[el][3];
   if (act) {
     // nodal gradients of u, v, T and the fluxes H = F + G at this node
     T gxv[3], gyv[3];
@@ -391,33 +491,25 @@ __global__ __launch_bounds__(256) void element_ns_kernel(DevMesh m, const T* __r
   }
   __syncthreads();
 
-  // lift inputs (1/J) (sn_f . H(Q-) - sJ H* . n_f) of every face node
-  for (int idx = t; idx < nel * NJ; idx += blockDim.x) {
-    const int e2 = idx / NJ, qf = idx - e2 * NJ;
-    const int f = qf / Nfp, j = qf - f * Nfp;
-    const int64_t kk = k0 + e2;
-    const ElemGeom ge = elem_geom(m.vert[3 * kk], m.vert[3 * kk + 1], m.vert[3 * kk + 2]);
-    // sJ n of face f from its two vertices, (t_y, -t_x) / 2 for t = b - a,
-    // without a branch on f: with f varying across the lanes of this loop,
-    // the three-way branch of face_sjn came out of hipcc -O3 (ROCm 7.2,
-    // gfx950) computing face 3's x component under the wrong lanes' mask
-    const double2 va = m.vert[3 * kk + f], vb = m.vert[3 * kk + (f == 2 ? 0 : f + 1)];
-    const double2 sn = make_double2(0.5 * (vb.y - va.y), -0.5 * (vb.x - va.x));
-    const int code = m.elem_face[f * m.K + kk];
-    const bool side2 = code & 1;
-    const int64_t fo = (int64_t)(code >> 1) * Nfp + (side2 ? Nfp - 1 - j : j);
-    const int nd = e2 * Np + fnode(N, f, j);
-    const T iJ = (T)ge.iJ;
+  // lift inputs (1/J) (sn_f . H(Q-) - sJ H* . n_f) of this thread's face nodes
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const T Gs = flux[(int64_t)cc * E * Nfp + fo];
-      const T hn = (T)sn.x * sH[cc][nd] + (T)sn.y * sH[4 + cc][nd];
-      sJv[cc][idx] = iJ * (hn - (side2 ? -Gs : Gs));
+  for (int r = 0; r < QJ; ++r) {
+    const int idx = t + r * 256;
+    if (idx < nel * NJ) {
+      const int e2 = idx / NJ, qf = idx - e2 * NJ;
+      const int f = qf / Nfp, j = qf - f * Nfp;
+      const int nd = e2 * Np + fnode(N, f, j);
+      const double* G = sG[e2];
+      const T snx = (T)G[5 + 2 * f], sny = (T)G[6 + 2 * f], iJ = (T)G[4];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const T hn = snx * sH[cc][nd] + sny * sH[4 + cc][nd];
+        sJv[cc][idx] = iJ * (hn - Gs[r][cc]);
+      }
     }
   }
   __syncthreads();
 
-  if (!act) return;
 #pragma unroll
   for (int cc = 0; cc < 4; ++cc) {
     T drx = T(0), dry = T(0), dsx = T(0), dsy = T(0);
@@ -432,7 +524,7 @@ __global__ __launch_bounds__(256) void element_ns_kernel(DevMesh m, const T* __r
     T r = -(rx * drx + ry * dry + sx * dsx + sy * dsy);
 #pragma unroll
     for (int qf = 0; qf < NJ; ++qf) r = fma(Lf[n * NJ + qf], sJv[cc][el * NJ + qf], r);
-    epilogue_dof<T>(epi, cc * KN + k0 * Np + t, r);
+    epilogue_dof<T>(epi, cc * KN + k0 * Np + tc, r, Up[cc], Ap[cc], act);
   }
 }
 
