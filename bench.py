@@ -48,7 +48,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 HEADLINE = "convdiff_708x708_N3_4f"
 ROTATION = (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)
 # edge kernel implementations (ardg_mesh_set_kernels)
-EDGE_KERNELS = {"auto": 0, "split": 1, "lane": 2}
+EDGE_KERNELS = {"auto": 0, "split": 1, "lane": 2, "mfma": 3, "split_mfma": 4}
 
 
 def log(msg):
@@ -120,16 +120,36 @@ def workload_D(spec, mesh):
     return np.array(spec.get("Dfield", [spec.get("Dval", 1.0)]), dtype=float), "const"
 
 
-def algorithmic_bytes(K, Np, Nfp, E_int, s, alg1, nfields):
+def rk4_dof_bytes(s, f64):
+    """Bytes per degree of freedom of one classic RK4 stage's element kernel
+    outside the operator data, averaged over the four stages: stage input,
+    state and accumulator reads, accumulator or state write, next stage
+    input (s bytes per value of the stage vectors; FP64 reads the state
+    itself at stage 0 and writes no stage vector at stage 3; the accumulator
+    carries the new state as it forms, so stage 3 reads no state):
+      stage 0: [s] + 8 (u) + 8 (A write) + s
+      stage 1, 2: s + 8 (u) + 8 (A) + 8 (A write) + s
+      stage 3: s + 8 (A) + 8 (u write) + [s]."""
+    st0 = (0 if f64 else s) + 16 + s
+    st12 = s + 24 + s
+    st3 = s + 16 + (0 if f64 else s)
+    return (st0 + 2 * st12 + st3) / 4.0
+
+
+def algorithmic_bytes(K, Np, Nfp, E_int, E_bdy, s, alg1, nfields, conv):
     """Bytes each kernel must move per launch, each value counted once:
-    edge    F K Np s (state) + 60 E_int (edge table) + 8 K (element D,
-            Algorithm 1) + F E_int Nfp s (flux write);
-    element F K Np s (stage input) + F E_int Nfp s (flux) + 48 K (affine map)
-            + F K Np (8 + 16) (u^n read, accumulator read and write, FP64)
-            + F K Np s (next stage input)."""
+    edge    F K Np s (state) + 56 E_int + 36 E_bdy (edge and boundary-face
+            tables) + 16 E (n.v at the edge's ends, with convection) + 8 K
+            (element D, Algorithm 1) + F E Nfp s (flux write);
+    element F E Nfp s (fluxes) + 60 K (vertices, face map) + 8 K (element
+            D) + F K Np rk4_dof_bytes (stage vectors, state, accumulator;
+            the stage average, as the timing is)."""
+    E = E_int + E_bdy
     dof = nfields * K * Np
-    edge = dof * s + 60 * E_int + (8 * K if alg1 else 0) + nfields * E_int * Nfp * s
-    elem = dof * s + nfields * E_int * Nfp * s + 48 * K + dof * 24 + dof * s
+    f64 = s == 8
+    edge = dof * s + 56 * E_int + 36 * E_bdy + (16 * E if conv else 0) + (8 * K if alg1 else 0) \
+        + nfields * E * Nfp * s
+    elem = nfields * E * Nfp * s + 60 * K + (8 * K if alg1 else 0) + dof * rk4_dof_bytes(s, f64)
     return edge, elem
 
 
@@ -270,7 +290,8 @@ class Case:
 
 
 def kernel_rates(case, t_edge_ms, t_elem_ms, s, prec_name):
-    b_edge, b_elem = algorithmic_bytes(case.K, case.Np, case.Nfp, case.lm.E_int, s, case.alg1, case.nf)
+    b_edge, b_elem = algorithmic_bytes(case.K, case.Np, case.Nfp, case.lm.E_int, case.lm.E_bdy, s, case.alg1,
+                                       case.nf, case.vel is not None)
     f_edge, f_elem = algorithmic_flops(case.K, case.Np, case.Nfp, case.N, case.lm.E_int, case.alg1, case.nf)
     te, tl = t_edge_ms * 1e-3, t_elem_ms * 1e-3
     peak = PEAK_TFLOPS[prec_name]

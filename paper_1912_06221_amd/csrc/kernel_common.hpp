@@ -141,6 +141,10 @@ template <int N> struct ElemTune {
   static constexpr int waves = N <= 4 ? 2 : 1;
 };
 
+// The last stage of classic RK4, which reads the accumulator but not the
+// state.
+__device__ inline bool last_rk4(const Epilogue& epi) { return epi.kind == EPI_RK4 && epi.stage == 3; }
+
 // One tile = TILE consecutive elements handled by NT threads.  Their nodal
 // values form one contiguous chunk of the [F][K][Np] array: tile_begin stages
 // it through LDS (sh, TileShape::LDS entries) with coalesced loads and fetches the
@@ -188,7 +192,9 @@ __device__ inline void tile_load(const DevMesh& m, int64_t k0, int field, const 
     // without an update (right-hand side only) the operand loads read the
     // stage input's first value: no branch around them; the accumulator is
     // read (and used) from stage 1 on
-    const double* U = io.rk ? epi.u + io.base : (const double*)vin;
+    // (the last classic RK4 stage needs only the accumulator: its state
+    // loads read the accumulator's addresses again, no second stream)
+    const double* U = io.rk ? (last_rk4(epi) ? epi.acc : epi.u) + io.base : (const double*)vin;
     const double* A = io.need_acc ? epi.acc + io.base : U;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -240,28 +246,30 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
   T* vn = epi.vnext ? (T*)epi.vnext + io.base : nullptr;
   const double dt = epi.dt;
   if (!prefetched) {
-    const double* Asrc = io.need_acc ? A : U;
+    const double* Usrc = last_rk4(epi) ? A : U;
+    const double* Asrc = io.need_acc ? A : Usrc;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int i = t + q * NT;
       const int ic = i < ndof ? i : 0;
-      io.Up[q] = U[ic];
+      io.Up[q] = Usrc[ic];
       io.Ap[q] = Asrc[ic];
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (!io.need_acc) io.Ap[q] = 0.0;
   }
   if (epi.kind == EPI_RK4) {
+    // classic RK4 with the accumulator holding the new state as it forms:
+    // A = u + dt/6 k1, A += dt/3 k2, A += dt/3 k3, u = A + dt/6 k4, and the
+    // next stage input u + dt/2 k1, u + dt/2 k2, u + dt k3
     const int s = epi.stage;
     if (s < 3) {
       const double c = (s < 2) ? 0.5 * dt : dt;
+      const double w = (s == 0) ? dt / 6.0 : dt / 3.0;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
         if (i < ndof) {
           const double r = (double)sh[i];
-          A[i] = (s == 0) ? r : io.Ap[q] + 2.0 * r;
+          A[i] = ((s == 0) ? io.Up[q] : io.Ap[q]) + w * r;
           if (vn) vn[i] = (T)(io.Up[q] + c * r);
         }
       }
@@ -270,7 +278,7 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
       for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
         if (i < ndof) {
-          const double un = io.Up[q] + dt / 6.0 * (io.Ap[q] + (double)sh[i]);
+          const double un = io.Ap[q] + dt / 6.0 * (double)sh[i];
           U[i] = un;
           if (vn) vn[i] = (T)un;
         }

@@ -529,8 +529,11 @@ hipError_t launch_edge_flux(const DevMesh& m, int prec, int nfields, const void*
   // a nodal tensor coefficient has one kernel (whatever edge kernel is chosen)
   if (m.dmode == DM_NODAL || m.dmode == DM_SOLUTION) return launch_edge_tensor(m, prec, nfields, u, flux, st);
   // split-BF16 products exist only on the matrix cores: side-split tiles up
-  // to N = 3, one wave per tile above (measured faster)
-  if (m.edge_kernel == EDGE_SPLIT_MFMA || (prec == PREC_BF16X3 && m.edge_kernel == EDGE_AUTO && m.N <= 3))
+  // to N = 3, one wave per tile above (measured faster).  FP64 from N = 5 on
+  // also converts on the matrix cores (512x512 N = 6: 238 us against 271 us
+  // on the vector unit)
+  if (m.edge_kernel == EDGE_SPLIT_MFMA ||
+      (m.edge_kernel == EDGE_AUTO && ((prec == PREC_BF16X3 && m.N <= 3) || (prec == PREC_FP64 && m.N >= 5))))
     return launch_edge_split_mfma(m, prec, nfields, u, flux, st);
   if (m.edge_kernel == EDGE_MFMA || prec == PREC_BF16X3) return launch_edge_mfma(m, prec, nfields, u, flux, st);
   return prec == PREC_FP64 ? edge_dispatch<double>(m, nfields, u, flux, st)

@@ -315,15 +315,17 @@ __device__ inline void epilogue_dof(const Epilogue& epi, int64_t i, T r_t, doubl
   const double r = (double)r_t, dt = epi.dt;
   T* vn = (T*)epi.vnext;
   if (epi.kind == EPI_RK4) {
+    // the accumulator holds the new state as it forms (as in tile_end)
     const int s = epi.stage;
     if (s < 3) {
       const double c = (s < 2) ? 0.5 * dt : dt;
+      const double w = (s == 0) ? dt / 6.0 : dt / 3.0;
       if (act) {
-        epi.acc[i] = (s == 0) ? r : A + 2.0 * r;
+        epi.acc[i] = ((s == 0) ? U : A) + w * r;
         if (vn) vn[i] = (T)(U + c * r);
       }
     } else {
-      const double un = U + dt / 6.0 * (A + r);
+      const double un = A + dt / 6.0 * r;
       if (act) {
         epi.u[i] = un;
         if (vn) vn[i] = (T)un;
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(256) void element_ns_kernel(DevMesh m, const T* __r
   // no update: no branch around the loads)
   const bool rk = epi.kind != EPI_RHS;
   const bool need_acc = rk && epi.stage != 0;
-  const double* Ub = rk ? epi.u : (const double*)vin;
+  const double* Ub = rk ? (last_rk4(epi) ? epi.acc : epi.u) : (const double*)vin;
   const double* Ab = need_acc ? epi.acc : Ub;
   double Up[4], Ap[4];
 #pragma unroll
