@@ -120,6 +120,20 @@ def workload_D(spec, mesh):
     return np.array(spec.get("Dfield", [spec.get("Dval", 1.0)]), dtype=float), "const"
 
 
+def algorithmic_bytes(K, Np, Nfp, E_int, s, alg1, nfields):
+    """Bytes each kernel must move per launch by the survey's model (each
+    value counted once, neighbour reuse in L2 assumed):
+    edge    F K Np s (state) + 60 E_int (edge table, FP64 parameters) + 8 K
+            (element D, Algorithm 1) + F E_int Nfp s (flux write);
+    element F K Np s (stage input) + F E_int Nfp s (flux) + 48 K (affine map)
+            + F K Np (8 + 16) (u^n read, accumulator read and write, FP64)
+            + F K Np s (next stage input)."""
+    dof = nfields * K * Np
+    edge = dof * s + 60 * E_int + (8 * K if alg1 else 0) + nfields * E_int * Nfp * s
+    elem = dof * s + nfields * E_int * Nfp * s + 48 * K + dof * 24 + dof * s
+    return edge, elem
+
+
 def rk4_dof_bytes(s, f64):
     """Bytes per degree of freedom of one classic RK4 stage's element kernel
     outside the operator data, averaged over the four stages: stage input,
@@ -136,14 +150,15 @@ def rk4_dof_bytes(s, f64):
     return (st0 + 2 * st12 + st3) / 4.0
 
 
-def algorithmic_bytes(K, Np, Nfp, E_int, E_bdy, s, alg1, nfields, conv):
-    """Bytes each kernel must move per launch, each value counted once:
-    edge    F K Np s (state) + 56 E_int + 36 E_bdy (edge and boundary-face
-            tables) + 16 E (n.v at the edge's ends, with convection) + 8 K
-            (element D, Algorithm 1) + F E Nfp s (flux write);
-    element F E Nfp s (fluxes) + 60 K (vertices, face map) + 8 K (element
-            D) + F K Np rk4_dof_bytes (stage vectors, state, accumulator;
-            the stage average, as the timing is)."""
+def stored_bytes(K, Np, Nfp, E_int, E_bdy, s, alg1, nfields, conv):
+    """The same per launch for the data as this library stores and moves it:
+    edge    F K Np s + 56 E_int + 36 E_bdy (edge and boundary-face tables) +
+            16 E (n.v at the edge's ends, with convection) + 8 K (element D)
+            + F E Nfp s (flux write, boundary faces included);
+    element F E Nfp s (fluxes) + 60 K (vertices, face map) + 8 K (element D)
+            + F K Np rk4_dof_bytes (stage vectors, state and accumulator,
+            averaged over the stages as the timing is; the survey's model
+            charges every launch the heaviest stage)."""
     E = E_int + E_bdy
     dof = nfields * K * Np
     f64 = s == 8
@@ -290,8 +305,9 @@ class Case:
 
 
 def kernel_rates(case, t_edge_ms, t_elem_ms, s, prec_name):
-    b_edge, b_elem = algorithmic_bytes(case.K, case.Np, case.Nfp, case.lm.E_int, case.lm.E_bdy, s, case.alg1,
-                                       case.nf, case.vel is not None)
+    b_edge, b_elem = algorithmic_bytes(case.K, case.Np, case.Nfp, case.lm.E_int, s, case.alg1, case.nf)
+    s_edge, s_elem = stored_bytes(case.K, case.Np, case.Nfp, case.lm.E_int, case.lm.E_bdy, s, case.alg1,
+                                  case.nf, case.vel is not None)
     f_edge, f_elem = algorithmic_flops(case.K, case.Np, case.Nfp, case.N, case.lm.E_int, case.alg1, case.nf)
     te, tl = t_edge_ms * 1e-3, t_elem_ms * 1e-3
     peak = PEAK_TFLOPS[prec_name]
@@ -302,6 +318,8 @@ def kernel_rates(case, t_edge_ms, t_elem_ms, s, prec_name):
         "edge_frac": b_edge / te / 1e9 / HBM_PEAK_GBS, "element_frac": b_elem / tl / 1e9 / HBM_PEAK_GBS,
         "edge_TFLOPs": f_edge / te / 1e12, "element_TFLOPs": f_elem / tl / 1e12,
         "edge_flop_frac": f_edge / te / 1e12 / peak, "element_flop_frac": f_elem / tl / 1e12 / peak,
+        "edge_stored_bytes": s_edge, "element_stored_bytes": s_elem,
+        "edge_stored_frac": s_edge / te / 1e9 / HBM_PEAK_GBS, "element_stored_frac": s_elem / tl / 1e9 / HBM_PEAK_GBS,
     }
 
 
@@ -749,7 +767,11 @@ def main():
             "element_frac": r64["element_frac"], "element_GBps": r64["element_GBps"],
             "element_us": r64["element_us"], "element_bytes": r64["element_bytes"],
             "element_traffic": ctr.get("element-fp64 hbm_bytes"),
-            "edge_fp64_flop_frac": r64["edge_flop_frac"], "element_fp64_flop_frac": r64["element_flop_frac"]}
+            "edge_fp64_flop_frac": r64["edge_flop_frac"], "element_fp64_flop_frac": r64["element_flop_frac"],
+            # the same kernels' fractions for the bytes as stored and moved
+            # (tables as laid out, RK traffic averaged over the stages)
+            "edge_stored_frac": r64["edge_stored_frac"], "element_stored_frac": r64["element_stored_frac"],
+            "edge_stored_bytes": r64["edge_stored_bytes"], "element_stored_bytes": r64["element_stored_bytes"]}
     mf = ctr.get("element-fp64 mfma_flops")
     if mf is not None:
         roof["element_mfma_fp64_frac"] = mf / (r64["element_us"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"]
