@@ -249,7 +249,9 @@ ardg_status ardg_mesh_set_velocity(ardg_mesh mesh, int32_t kind, const double* p
 /* du/dt for nfields fields (one RHS evaluation = one Runge-Kutta stage).
  * precision ARDG_FP64: u_dev, rhs_dev are double [F][K][Np];
  * ARDG_FP32: float [F][K][Np] (operators and arithmetic in FP32, operators
- * built in FP64).  Enqueued on hip_stream (hipStream_t, NULL = default);
+ * built in FP64); ARDG_BF16X3: float [F][K][Np] as FP32, with the operator
+ * products split into BF16 hi/lo parts on the matrix cores (hi hi + hi lo +
+ * lo hi, FP32 accumulation).  Enqueued on hip_stream (hipStream_t, NULL = default);
  * uses a flux buffer owned by the mesh.  t: the time of the prescribed
  * boundary data (the only term that depends on time).  Errors:
  * E_INVALID_ARG, E_UNSUPPORTED, E_HIP. */
@@ -354,6 +356,10 @@ ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
 ardg_status ardg_batch_tiles(ardg_batch batch, int32_t precision, int32_t N, int32_t* edge_tile,
                              int32_t* elem_tile, int32_t* grid);
 void ardg_batch_destroy(ardg_batch batch);
+/* ardg_check for a batch: synchronise the stream and scan every mesh's FP64
+ * state u_devs[i] (host array of n device pointers, [K_i][Np_i]) for
+ * non-finite values (E_NONFINITE if any).  Errors: E_INVALID_ARG, E_HIP. */
+ardg_status ardg_batch_check(ardg_batch batch, double* const* u_devs, void* hip_stream);
 
 /* Synchronise the stream and scan the FP64 state for non-finite values
  * (E_NONFINITE if any).  u_dev: double [F][K][Np]. */

@@ -77,6 +77,7 @@ SIGNATURES = {
     "ardg_batch_tiles": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_int32)]),
     "ardg_batch_destroy": (None, [c_void_p]),
+    "ardg_batch_check": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ardg_status_string": (c_char_p, [c_int32]),
     "ardg_last_error": (c_char_p, []),
 }
@@ -316,6 +317,11 @@ class Batch:
         dt = np.ascontiguousarray(dts, dtype=np.float64)
         _check(lib().ardg_batch_step(self.handle, scheme, precision, ptrs, _ptr(work), _dptr(dt),
                                      nsteps, _stream(stream)))
+
+    def check(self, us, stream=None):
+        """Synchronise and scan every mesh's FP64 state for non-finite values."""
+        ptrs = (c_void_p * len(us))(*[u.data_ptr() for u in us])
+        _check(lib().ardg_batch_check(self.handle, ptrs, _stream(stream)))
 
 
 def alloc_workspace(nbytes: int, device):

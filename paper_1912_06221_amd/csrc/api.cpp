@@ -1448,6 +1448,30 @@ ardg_status ardg_batch_workspace_bytes(ardg_batch batch, int32_t scheme, int32_t
   return ARDG_OK;
 }
 
+ardg_status ardg_batch_check(ardg_batch batch, double* const* u_devs, void* hip_stream) {
+  if (!batch || !u_devs) return fail(ARDG_E_INVALID_ARG, "batch_check: null argument");
+  DeviceGuard g(batch->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  int* cnt = nullptr;
+  HIP_TRY(hipMalloc(&cnt, sizeof(int)), "hipMalloc");
+  hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
+  for (size_t i = 0; i < batch->meshes.size() && e == hipSuccess; ++i) {
+    if (!u_devs[i]) {
+      (void)hipFree(cnt);
+      return fail(ARDG_E_INVALID_ARG, "batch_check: null state pointer");
+    }
+    const ardg_mesh m = batch->meshes[i];
+    e = launch_nonfinite(u_devs[i], m->hm.K * m->ro.Np, cnt, st);
+  }
+  int host = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&host, cnt, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(cnt);
+  if (e != hipSuccess) return hip_fail(e, "batch_check");
+  if (host) return fail(ARDG_E_NONFINITE, "batch_check: " + std::to_string(host) + " non-finite values");
+  return ARDG_OK;
+}
+
 ardg_status ardg_batch_tiles(ardg_batch batch, int32_t precision, int32_t N, int32_t* edge_tile,
                              int32_t* elem_tile, int32_t* grid) {
   if (!batch) return fail(ARDG_E_INVALID_ARG, "batch_tiles: null batch");

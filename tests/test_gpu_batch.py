@@ -60,6 +60,12 @@ def test_batch_matches_per_mesh(scheme, prec, tmp_path):
     b.step(us, work, dts, nsteps, scheme=sch, precision=p)
     for (mesh, ops, lm, N, D), u in zip(probs, us):
         assert np.isfinite(to_np(u)).all()
+    b.check(us)
+    # a non-finite value planted in one mesh's state is reported
+    us[1][0, 0] = float("nan")
+    with pytest.raises(ardg.ArdgError) as ei:
+        b.check(us)
+    assert ei.value.status == -9
     # the tuned tiles were cached
     text = (tmp_path / "tiles.txt").read_text()
     assert ("fp64" if prec == "fp64" else "fp32") in text
