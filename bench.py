@@ -48,7 +48,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 HEADLINE = "convdiff_708x708_N3_4f"
 ROTATION = (0.0, 0.0, 0.0, -1.0, 1.0, 0.0)
 # edge kernel implementations (ardg_mesh_set_kernels)
-EDGE_KERNELS = {"auto": 0, "split": 1, "lane": 2, "mfma": 3, "split_mfma": 4}
+EDGE_KERNELS = {"auto": 0, "split": 1, "lane": 2, "mfma": 3, "split_mfma": 4, "fields": 5}
 
 
 def log(msg):

@@ -73,7 +73,9 @@ enum {
   ARDG_EDGE_SPLIT = 1,       /* two waves per 64-edge tile, one per side, vector unit        */
   ARDG_EDGE_LANE = 2,        /* one lane per edge, vector unit                               */
   ARDG_EDGE_MFMA = 3,        /* one wave per 64 edges on the matrix cores                    */
-  ARDG_EDGE_SPLIT_MFMA = 4   /* side-split tiles, nodal -> Bernstein on the matrix cores     */
+  ARDG_EDGE_SPLIT_MFMA = 4,  /* side-split tiles, nodal -> Bernstein on the matrix cores     */
+  ARDG_EDGE_FIELDS = 5       /* one lane per edge for every field (constant D), the next field
+                                loaded during the current one's flux                         */
 };
 
 /* ardg_ops_export selectors (row-major double arrays). */

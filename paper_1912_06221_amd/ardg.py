@@ -21,7 +21,7 @@ RK4, LSERK54 = 0, 1
 D_CONST, D_ELEMENT, D_ELEMENT_ALG2, D_NODAL, D_SOLUTION = 0, 1, 2, 3, 4
 VEL_NONE, VEL_AFFINE = 0, 1
 NS_OFF, NS_SUTHERLAND, NS_CONSTANT_MU = 0, 1, 2
-EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA = 0, 1, 2, 3, 4
+EDGE_AUTO, EDGE_SPLIT, EDGE_LANE, EDGE_MFMA, EDGE_SPLIT_MFMA, EDGE_FIELDS = 0, 1, 2, 3, 4, 5
 
 OPS_NODES, OPS_V, OPS_DR, OPS_DS, OPS_MASS, OPS_LIFT = 0, 1, 2, 3, 4, 5
 OPS_FACE_NODES, OPS_ROT_PERM, OPS_RECON_A, OPS_RECON_R = 6, 7, 8, 9

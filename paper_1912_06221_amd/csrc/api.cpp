@@ -721,7 +721,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 ardg_status ardg_mesh_set_kernels(ardg_mesh mesh, int32_t edge_kernel) {
   if (!mesh) return fail(ARDG_E_INVALID_ARG, "set_kernels: null handle");
-  if (edge_kernel < ARDG_EDGE_AUTO || edge_kernel > ARDG_EDGE_SPLIT_MFMA)
+  if (edge_kernel < ARDG_EDGE_AUTO || edge_kernel > ARDG_EDGE_FIELDS)
     return fail(ARDG_E_INVALID_ARG, "set_kernels: unknown edge kernel");
   mesh->dm.edge_kernel = edge_kernel;
   mesh->drop_graphs();

@@ -67,7 +67,7 @@ struct OpLayout {
 // latency-bound (few waves per SIMD, or high order with few waves resident)
 // and EDGE_LANE otherwise; split-BF16 products run on EDGE_SPLIT_MFMA up to
 // N = 3 and on EDGE_MFMA above.
-enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, EDGE_SPLIT_MFMA = 4 };
+enum EdgeKernel { EDGE_AUTO = 0, EDGE_SPLIT = 1, EDGE_LANE = 2, EDGE_MFMA = 3, EDGE_SPLIT_MFMA = 4, EDGE_FIELDS = 5 };
 
 // Diffusion coefficient forms (values as ARDG_D_* in the C ABI): one
 // constant per field, or element-wise with the flux of Algorithm 1

@@ -263,7 +263,7 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
     const int s = epi.stage;
     if (s < 3) {
       const double c = (s < 2) ? 0.5 * dt : dt;
-      const double w = (s == 0) ? dt / 6.0 : dt / 3.0;
+      const double w = dt * ((s == 0) ? (1.0 / 6.0) : (1.0 / 3.0));
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
@@ -278,7 +278,7 @@ __device__ inline void tile_end(const Epilogue& epi, T* sh, TileIO<TileShape<N, 
       for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
         if (i < ndof) {
-          const double un = io.Ap[q] + dt / 6.0 * (double)sh[i];
+          const double un = io.Ap[q] + dt * (1.0 / 6.0) * (double)sh[i];
           U[i] = un;
           if (vn) vn[i] = (T)un;
         }

@@ -55,6 +55,73 @@ __global__ __launch_bounds__(256) void edge_flux_kernel(DevMesh m, const T* __re
   edge_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
 }
 
+// Several fields with constant D: one lane per interior edge takes every
+// field.  The edge's table (elements, faces, apex weights, gamma, n.v) is
+// read once, and the next field's element values are loaded while the
+// current field's flux is formed, so only the first field waits for its
+// data.  Blocks [0, nb_bdy * nf) take the boundary faces (256 per block, one
+// field each), the others 256 interior edges each, in contiguous ranges per
+// XCD.
+template <int N, typename T>
+__global__ __launch_bounds__(256) void edge_fields_kernel(DevMesh m, const T* __restrict__ u,
+                                                          T* __restrict__ flux, int nb_bdy, int nf) {
+  constexpr OpLayout L(N);
+  constexpr int Np = L.Np, Nfp = L.Nfp;
+  constexpr bool kBoth = sizeof(T) == 8 ? N <= 4 : N <= 5;
+  const cptr<T> op = opbase<T>(m);
+  const int64_t b = blockIdx.x;
+  const int64_t nbt = (int64_t)nb_bdy * nf;
+  const int64_t E = m.E_int + m.E_bdy;
+  if (b < nbt) {
+    const int field = (int)(b % nf);
+    const int64_t e = m.E_int + (b / nf) * 256 + threadIdx.x;
+    if (e < E) boundary_body<N, T, DM_CONST>(m, op, e, field, u, flux);
+    return;
+  }
+  // nb_bdy is a multiple of 8, so b - nbt keeps b's XCD
+  const int64_t e = xcd_block(b - nbt, (int64_t)gridDim.x - nbt) * 256 + threadIdx.x;
+  if (e >= m.E_int) return;
+  const int2 ef = m.ef[e];
+  const double2 g = m.gam[e], mu1 = m.mu1[e], mu2 = m.mu2[e];
+  double2 vn = make_double2(0.0, 0.0);
+  if (m.conv) vn = m.vn[e];
+  const int64_t k1 = ef.x & 0x3fffffff, k2 = ef.y & 0x3fffffff;
+  const int fa = (int)((unsigned)ef.x >> 30), fb = (int)((unsigned)ef.y >> 30);
+  const int64_t KN = m.K * Np;
+  const T* u1 = u + k1 * Np;
+  const T* u2 = u + k2 * Np;
+  T v[2][Np];
+#pragma unroll
+  for (int n = 0; n < Np; ++n) {
+    v[0][n] = u1[n];
+    v[1][n] = u2[n];
+  }
+  for (int f = 0; f < nf; ++f) {
+    // the next field's values (the last field loads itself again: no branch)
+    const int64_t on = (int64_t)(f + 1 < nf ? f + 1 : f) * KN;
+    T w[2][Np];
+#pragma unroll
+    for (int n = 0; n < Np; ++n) {
+      w[0][n] = u1[on + n];
+      w[1][n] = u2[on + n];
+    }
+    T t[2][Np], c[2][Np], tr1[Nfp], tr2[Nfp];
+    rotate_to_face<N, T>(v[0], fa, t[0], tr1);
+    rotate_to_face<N, T>(v[1], fb, t[1], tr2);
+    matvec_n<Np, Np, 2, T>(op + L.n2b, t, c);
+    T F[Nfp];
+    interior_flux<N, T, DM_CONST, kBoth>(m, op, f, c, mu1, mu2, g, vn, 0.0, 0.0, tr1, tr2, F);
+    T* out = flux + ((int64_t)f * E + e) * Nfp;
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) out[j] = F[j];
+#pragma unroll
+    for (int n = 0; n < Np; ++n) {
+      v[0][n] = w[0][n];
+      v[1][n] = w[1][n];
+    }
+  }
+}
+
 // Interior edges split by side: a block of two waves takes a tile of 64
 // edges; wave s (s = 0, 1) gathers, rotates, converts and subdivides element
 // s+1 of every edge and applies the columns of the reconstruction operator
@@ -463,10 +530,22 @@ __global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* c
 // launchers
 // ---------------------------------------------------------------------------
 
+// the automatic choice takes the multi-field kernel for several fields
+constexpr bool kFieldsAuto = false;
+
 template <int N, typename T>
 hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   const int64_t E = m.E_int + m.E_bdy;
   if (E == 0) return hipSuccess;
+  if (m.edge_kernel == EDGE_FIELDS || (m.edge_kernel == EDGE_AUTO && kFieldsAuto && nfields > 1 &&
+                                        m.dmode == DM_CONST && N <= 4)) {
+    if (m.dmode != DM_CONST) return hipErrorInvalidValue;
+    const int64_t nbb = ((m.E_bdy + 255) / 256 + 7) / 8 * 8;
+    const int64_t nbi = (m.E_int + 255) / 256;
+    hipLaunchKernelGGL((edge_fields_kernel<N, T>), dim3((unsigned)(nbb * nfields + nbi)), dim3(256), 0, st, m,
+                       (const T*)u, (T*)flux, (int)nbb, nfields);
+    return hipGetLastError();
+  }
   bool split = m.edge_kernel == EDGE_SPLIT;
   if (m.edge_kernel == EDGE_AUTO) {
     // one thread per edge: about 8 waves per SIMD (1024 SIMDs) hide the

@@ -319,13 +319,13 @@ __device__ inline void epilogue_dof(const Epilogue& epi, int64_t i, T r_t, doubl
     const int s = epi.stage;
     if (s < 3) {
       const double c = (s < 2) ? 0.5 * dt : dt;
-      const double w = (s == 0) ? dt / 6.0 : dt / 3.0;
+      const double w = dt * ((s == 0) ? (1.0 / 6.0) : (1.0 / 3.0));
       if (act) {
         epi.acc[i] = ((s == 0) ? U : A) + w * r;
         if (vn) vn[i] = (T)(U + c * r);
       }
     } else {
-      const double un = A + dt / 6.0 * r;
+      const double un = A + dt * (1.0 / 6.0) * r;
       if (act) {
         epi.u[i] = un;
         if (vn) vn[i] = (T)un;

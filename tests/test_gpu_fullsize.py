@@ -137,10 +137,11 @@ def test_fullsize_alg2_rhs_sampled(name):
 
 @pytest.mark.parametrize("name", ["convdiff_708x708_N3_4f", "contrast_256x256_N4"])
 def test_fullsize_edge_kernels_agree(name):
-    """Both vector-unit edge kernels at the full sizes: the side-split tiles'
-    whole flux array agrees with the one-lane-per-edge kernel's (every edge,
-    including the last, ragged tile and the boundary faces), and the RHS
-    through the side-split kernel matches the oracle on sampled elements."""
+    """The vector-unit edge kernels at the full sizes: the side-split tiles'
+    (and, with per-field constant D, the multi-field lanes') whole flux
+    array agrees with the one-lane-per-edge kernel's (every edge, including
+    the last, ragged tile and the boundary faces), and the RHS through the
+    last of them matches the oracle on sampled elements."""
     import torch
     from paper_1912_06221_amd import ardg
     print(f"full-size edge kernels {name}", flush=True)
@@ -152,14 +153,16 @@ def test_fullsize_edge_kernels_agree(name):
     for prec, dt, tol in ((ardg.FP64, torch.float64, TOL64), (ardg.FP32, torch.float32, TOL32)):
         x = ud.to(dt)
         fl = {}
-        for kern in (ardg.EDGE_LANE, ardg.EDGE_SPLIT):
+        kerns = (ardg.EDGE_LANE, ardg.EDGE_SPLIT) + ((ardg.EDGE_FIELDS,) if spec["D"] == "perfield" else ())
+        for kern in kerns:
             lm.set_kernels(kern)
             f = torch.empty((nf, lm.E, ops.Nfp), dtype=dt, device=ud.device)
             lm.edge_flux_eval(x, f, precision=prec, nfields=nf)
             fl[kern] = to_np(f)
-        d = np.abs(fl[ardg.EDGE_SPLIT] - fl[ardg.EDGE_LANE]).max() / np.abs(fl[ardg.EDGE_LANE]).max()
-        print(f"  prec={prec} split vs lane flux {d:.2e}", flush=True)
-        assert d <= tol
+        for kern in kerns[1:]:
+            d = np.abs(fl[kern] - fl[ardg.EDGE_LANE]).max() / np.abs(fl[ardg.EDGE_LANE]).max()
+            print(f"  prec={prec} kernel {kern} vs lane flux {d:.2e}", flush=True)
+            assert d <= tol
         out = torch.empty_like(x)
         lm.rhs_eval(x, out, precision=prec, nfields=nf)
         got = to_np(out)

@@ -291,7 +291,9 @@ def test_matrix_core_and_vector_kernels_agree(case, prec):
     tol = TOL64 if prec == "fp64" else TOL32
     outs = {}
     variants = {"default": ardg.EDGE_AUTO, "split": ardg.EDGE_SPLIT, "split-mfma": ardg.EDGE_SPLIT_MFMA,
-                "lane": ardg.EDGE_LANE, "mfma": ardg.EDGE_MFMA}
+                "lane": ardg.EDGE_LANE, "mfma": ardg.EDGE_MFMA, "fields": ardg.EDGE_FIELDS}
+    if dk.startswith("blocks"):
+        del variants["fields"]      # the multi-field lanes take constant D only
     for variant, kern in variants.items():
         ops, lm = library_mesh(mesh, N, D_mode, D, vel, 1)
         lm.set_kernels(kern)
