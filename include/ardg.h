@@ -197,8 +197,9 @@ ardg_status ardg_mesh_set_diffusion(ardg_mesh mesh, int32_t mode, int32_t nfield
  * default ARDG_EDGE_AUTO takes the side-split tiles where one lane per edge
  * would leave the chip latency-bound (fewer than ~8 waves per SIMD, or
  * N >= 5; in FP64 from N = 5 on with the conversion on the matrix cores)
- * and one lane per edge otherwise, and for ARDG_BF16X3 the matrix-core
- * kernels (side-split up to N = 3).  Split-BF16 products exist
+ * and one lane per edge otherwise (in FP32 with several constant-D fields,
+ * ARDG_EDGE_FIELDS), and for ARDG_BF16X3 the matrix-core kernels
+ * (side-split up to N = 3).  Split-BF16 products exist
  * only on the matrix cores, so with ARDG_BF16X3 the vector-unit choices
  * (ARDG_EDGE_SPLIT, ARDG_EDGE_LANE) run ARDG_EDGE_MFMA.  Drops the mesh's
  * captured step graphs.  Errors: E_INVALID_ARG. */
