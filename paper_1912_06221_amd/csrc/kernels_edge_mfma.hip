@@ -292,9 +292,12 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
 // through its own LDS rows to one lane per edge for the subdivision and its
 // side's columns of the reconstruction operator (vector unit, scalar operands,
 // as in the vector-unit split kernel).  The conversion runs on the matrix pipe
-// beside the other waves' vector work.
+// beside the other waves' vector work.  At least two waves per SIMD: in FP64 at
+// N = 6 with Algorithm 1 the register file otherwise holds one wave, which
+// then waits out every gather alone (C3-sized mesh: 240 us at one wave, 157 us
+// at two with ten registers spilled).
 template <int N, typename P, int DM, bool CONV>
-__global__ __launch_bounds__(2 * kEdgeTile) void edge_smfma_kernel(DevMesh m,
+__global__ __launch_bounds__(2 * kEdgeTile) __attribute__((amdgpu_waves_per_eu(2))) void edge_smfma_kernel(DevMesh m,
                                                                    const typename Mma<P>::T* __restrict__ u,
                                                                    typename Mma<P>::T* __restrict__ flux,
                                                                    int nb_bdy, int nf) {
