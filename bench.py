@@ -754,6 +754,8 @@ def main():
         del a, b
 
     modes = [m for m in args.modes.split(",") if m]
+    if "fp64" not in modes:
+        sys.exit("bench: --modes must include fp64 (the headline path)")
     head = Case(args.workload, dev, args.power_iters, args.edge_kernel)
     hr = measure_case(head, args, dev, modes, 0 if args.no_errors else head.spec["steps"])
     r64 = hr["fp64"]

@@ -248,8 +248,20 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
 // operator, one lane per face): their serial chain is the longest of the
 // launch, so they start first and run beside the interior tiles.  The other
 // blocks take one tile of 64 interior edges each.
+// Waves per SIMD the compiler must leave room for, where a few spilled
+// registers buy one more resident wave (Algorithm 1, whose four-block
+// reconstruction holds the most): FP64 at N = 4, 2 -> 3 waves with two
+// registers spilled (256x256 N = 4: 19.7 -> 16.8 us); FP32 at N = 6, 3 -> 4
+// with eight (512x512 N = 6: 95.8 -> 86.8 us).
+template <int N, typename T, int DM>
+struct SplitTune {
+  static constexpr int waves =
+      DM != DM_ALG1 ? 1 : ((sizeof(T) == 8 && N == 4) ? 3 : ((sizeof(T) == 4 && N == 6) ? 4 : 1));
+};
+
 template <int N, typename T, int DM, bool CONV>
-__global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
+__global__ __launch_bounds__(2 * kSplitTile) __attribute__((amdgpu_waves_per_eu(SplitTune<N, T, DM>::waves)))
+void edge_split_kernel(DevMesh m, const T* __restrict__ u,
                                                                     T* __restrict__ flux, int nb_bdy, int nf) {
   __shared__ SplitShared<N, T> S;
   const int64_t b = blockIdx.x;
