@@ -240,7 +240,7 @@ class Case:
     def time_mode(self, prec, steps, warmup, dev):
         """ms per RK4 step over `steps` graph-replayed steps, and the per-kernel
         average durations (HIP events on the launch stream, from replays of a
-        40-stage graph and of its element kernels alone)."""
+        40-stage graph and of its element kernels alone; median of three)."""
         import torch
         from paper_1912_06221_amd import ardg
         u = torch.from_numpy(self.u0.copy()).to(dev)
@@ -257,8 +257,12 @@ class Case:
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         self.lm.check(u, nfields=self.nf)
-        t_edge, t_elem = self.lm.stage_timing(u, work, self.dt, 40, scheme=ardg.RK4, precision=prec,
-                                              nfields=self.nf)
+        # the median of three timing-hook runs (single runs of the same
+        # kernels scatter by several per cent)
+        runs = [self.lm.stage_timing(u, work, self.dt, 40, scheme=ardg.RK4, precision=prec, nfields=self.nf)
+                for _ in range(3)]
+        t_edge = float(np.median([r[0] for r in runs]))
+        t_elem = float(np.median([r[1] for r in runs]))
         return ms, t_edge, t_elem
 
     def run_steps(self, prec, nsteps, dev, dt):
@@ -465,8 +469,10 @@ class NSCase:
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         self.lm.check(u, nfields=4)
-        t_edge, t_elem = self.lm.stage_timing(u, work, self.dt, 40, scheme=ardg.LSERK54, precision=prec,
-                                              nfields=4)
+        runs = [self.lm.stage_timing(u, work, self.dt, 40, scheme=ardg.LSERK54, precision=prec, nfields=4)
+                for _ in range(3)]
+        t_edge = float(np.median([r[0] for r in runs]))
+        t_elem = float(np.median([r[1] for r in runs]))
         return ms, t_edge, t_elem
 
     def rhs_vs_oracle(self, prec, dev, nsample=12):
