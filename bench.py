@@ -659,6 +659,29 @@ def _oracle_worker(vxy, etov, N, D, D_mode, vel, nf, reps, seed, barrier, queue)
     queue.put((setup, time.time() - t0, reps * u.size))
 
 
+def copy_bandwidth(dev, mib=512, reps=10):
+    """Achievable HBM rate on this device: the median over `reps` timed
+    device-to-device copies of `mib` MiB (bytes read + written per second,
+    GB/s)."""
+    import torch
+    a = torch.empty(mib * 1024 * 1024 // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        b.copy_(a)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * mib * 1024 * 1024 / float(np.median(ts)) / 1e9
+
+
 def cpu_baseline(name, rows_per_worker=2, reps=4):
     """The oracle's assembled RHS (edge operators prebuilt, setup reported
     apart) on strips of cell rows of the workload's mesh, one strip per worker
@@ -780,6 +803,13 @@ def main():
             # (tables as laid out, RK traffic averaged over the stages)
             "edge_stored_frac": r64["edge_stored_frac"], "element_stored_frac": r64["element_stored_frac"],
             "edge_stored_bytes": r64["edge_stored_bytes"], "element_stored_bytes": r64["element_stored_bytes"]}
+    # the same rates against what a plain device copy reaches on this machine
+    cbw = copy_bandwidth(dev)
+    roof["copy_GBps"] = cbw
+    roof["edge_frac_of_copy"] = r64["edge_GBps"] / cbw
+    roof["element_frac_of_copy"] = r64["element_GBps"] / cbw
+    log(f"bench: device copy {cbw:.0f} GB/s (read + write); FP64 edge {r64['edge_GBps'] / cbw:.1%}, "
+        f"element {r64['element_GBps'] / cbw:.1%} of it")
     mf = ctr.get("element-fp64 mfma_flops")
     if mf is not None:
         roof["element_mfma_fp64_frac"] = mf / (r64["element_us"] * 1e-6) / 1e12 / PEAK_TFLOPS["fp64"]
