@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
 // as in the vector-unit split kernel).  The conversion runs on the matrix pipe
 // beside the other waves' vector work.  At least two waves per SIMD: in FP64 at
 // N = 6 with Algorithm 1 the register file otherwise holds one wave, which
-// then waits out every gather alone (C3-sized mesh: 240 us at one wave, 157 us
+// then waits out every gather alone (512x512 mesh, N = 6: 240 us at one wave, 157 us
 // at two with ten registers spilled).
 template <int N, typename P, int DM, bool CONV>
 __global__ __launch_bounds__(2 * kEdgeTile) __attribute__((amdgpu_waves_per_eu(2))) void edge_smfma_kernel(DevMesh m,
