@@ -166,8 +166,10 @@ __global__ __launch_bounds__(256) void edge_ns_kernel(DevMesh m, const T* __rest
   constexpr OpLayout L(N);
   constexpr int Np = L.Np, Nfp = L.Nfp;
   const int64_t E = m.E_int + m.E_bdy;
-  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+  const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
+  // lanes past the last face take the last face's data (every lane reaches
+  // the block's barrier before the write-out)
+  const int64_t e = (e0 + threadIdx.x < E) ? e0 + threadIdx.x : E - 1;
   const cptr<T> op = opbase<T>(m);
   const GasC<T> g = gas_consts<T>(m);
   const int64_t KN = m.K * Np;
@@ -222,11 +224,13 @@ __global__ __launch_bounds__(256) void edge_ns_kernel(DevMesh m, const T* __rest
   // face traces: side 1's node j meets side 2's node N - j; at a boundary
   // face the exterior state at the ghost's node (j, N - j) of its lattice
   const T sJ = sqrt(snx * snx + sny * sny);
-  // FP32: the lane's fluxes wait in LDS (its own column) until every node is
-  // done, so that each field's Nfp values leave as one contiguous write
-  // (FP64 writes them node by node: the register file is full)
-  constexpr bool kStage = sizeof(T) == 4;
-  __shared__ T sOut[kStage ? 4 : 1][kStage ? Nfp : 1][kStage ? 256 : 1];
+  // The fluxes wait in LDS, [field][face][node] with rows padded to Nfp + 1
+  // (conflict-free node-by-node stores), until the block's faces are done;
+  // then each field's block of 256 Nfp values leaves in coalesced writes.
+  // Written node by node from the lanes, the FP64 fluxes cost 2.7 times
+  // their bytes in HBM writes (partial lines).
+  constexpr int RS = Nfp + 1;
+  __shared__ T sOut[4][256 * RS];
   const int tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < Nfp; ++j) {
@@ -263,21 +267,18 @@ __global__ __launch_bounds__(256) void edge_ns_kernel(DevMesh m, const T* __rest
 #pragma unroll
     for (int cc = 1; cc < 4; ++cc) H[cc] += Gx[cc - 1] * snx + Gy[cc - 1] * sny;
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      if constexpr (kStage)
-        sOut[cc][j][tid] = H[cc];
-      else
-        flux[((int64_t)cc * E + e) * Nfp + j] = H[cc];
-    }
+    for (int cc = 0; cc < 4; ++cc) sOut[cc][tid * RS + j] = H[cc];
   }
-  if constexpr (kStage) {
+  __syncthreads();
+  const int nface = (int)((E - e0) < 256 ? (E - e0) : 256);
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      T h[Nfp];
+  for (int cc = 0; cc < 4; ++cc) {
+    T* out = flux + ((int64_t)cc * E + e0) * Nfp;
 #pragma unroll
-      for (int j = 0; j < Nfp; ++j) h[j] = sOut[cc][j][tid];
-#pragma unroll
-      for (int j = 0; j < Nfp; ++j) flux[((int64_t)cc * E + e) * Nfp + j] = h[j];
+    for (int r = 0; r < Nfp; ++r) {
+      const int idx = tid + r * 256;
+      const int f = idx / Nfp, j = idx - f * Nfp;
+      if (f < nface) out[idx] = sOut[cc][f * RS + j];
     }
   }
 }
