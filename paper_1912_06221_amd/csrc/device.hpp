@@ -179,6 +179,13 @@ hipError_t launch_element_ns(const DevMesh& m, int prec, const void* vin, const 
 hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                             hipStream_t st);
 // Side-split tiles with the nodal -> Bernstein conversion on the matrix cores.
+// Boundary faces with prescribed exterior data, one lane per face in a launch
+// of their own (compute type FP64 or FP32), for the side-split launches: their
+// tile kernels carry only the mirror-ghost boundary path, whose registers stay
+// near the interior tiles' (the prescribed-state path holds about twice as
+// many, and the allocation of a kernel covers every path in it).
+hipError_t launch_boundary_faces(const DevMesh& m, bool f64, int nfields, const void* u, void* flux,
+                                 hipStream_t st);
 hipError_t launch_edge_split_mfma(const DevMesh& m, int prec, int nfields, const void* u, void* flux,
                                   hipStream_t st);
 // Batched element kernel on the matrix cores (64-element tiles).

@@ -259,7 +259,7 @@ __device__ inline T alg2_coef(cptr<T> op, int j, T D1, T D2) {
 // coefficients, and gtrace receives its values on the face (side-1 order)
 // for the upwind flux.  F receives sJ * flux, trace the element's values on
 // the face, vn the stored n.v (convection).
-template <int N, typename T, int DM>
+template <int N, typename T, int DM, bool GH = true>
 __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ uf, T* F, T* trace, double2& vn, T* gtrace) {
   constexpr OpLayout L(N);
@@ -273,37 +273,43 @@ __device__ inline void boundary_flux(const DevMesh& m, cptr<T> op, int64_t e, in
 #pragma unroll
   for (int n = 0; n < Np; ++n) v[n] = uf[(int64_t)k * Np + n];
   const T D = DM != DM_CONST ? (T)m.Delem[k] : (T)field_D(m, field);
+  const T gR = (T)g.x, gS = (T)g.y;
+  if (GH && m.ghost) {
+    // the element's sub-triangle (cb[0]) and the exterior state on the ghost
+    // sub-triangle (P2, B, A), nodal -> Bernstein (cb[1]); the ghost carries
+    // the element's D, so Algorithm 1 takes its equal-coefficient form
+    // D (U1 - U2), as the constant-coefficient operator does.  One row of the
+    // 2 Nfp x 2 Np operator at a time: this path shares its kernel's register
+    // allocation with the interior edges.
+    T cb[2][Np];
+    {
+      T t[Np];
+      rotate_to_face<N, T>(v, fa, t, trace);
+      matvec<Np, Np, T>(op + L.n2b, t, cb[0]);
+    }
+    decasteljau<N, T>(cb[0], mu);
+    {
+      T gv[Np];
+      const double* gs = m.ghost + ((int64_t)field * m.E_bdy + b) * Np;
+#pragma unroll
+      for (int n = 0; n < Np; ++n) gv[n] = (T)gs[n];
+#pragma unroll
+      for (int j = 0; j <= N; ++j) gtrace[j] = gv[lat(N, j, N - j)];
+      matvec<Np, Np, T>(op + L.n2b, gv, cb[1]);
+    }
+    T gg[2 * Nfp];
+    matvec<2 * Nfp, 2 * Np, T>(op + (DM == DM_ALG1 ? L.udr : L.kr), &cb[0][0], gg);
+#pragma unroll
+    for (int j = 0; j < Nfp; ++j) {
+      const T Dj = DM == DM_ALG2 ? alg2_coef<N, T>(op, j, D, D) : D;
+      F[j] = Dj * (gR * gg[j] + gS * gg[Nfp + j]);
+    }
+    return;
+  }
   T t[Np], c[Np];
   rotate_to_face<N, T>(v, fa, t, trace);
   matvec<Np, Np, T>(op + L.n2b, t, c);
   decasteljau<N, T>(c, mu);
-  const T gR = (T)g.x, gS = (T)g.y;
-  if (m.ghost) {
-    // exterior state on the ghost sub-triangle (P2, B, A): nodal -> Bernstein
-    T gv[Np], bg[Np];
-    const double* gs = m.ghost + ((int64_t)field * m.E_bdy + b) * Np;
-#pragma unroll
-    for (int n = 0; n < Np; ++n) gv[n] = (T)gs[n];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) gtrace[j] = gv[lat(N, j, N - j)];
-    matvec<Np, Np, T>(op + L.n2b, gv, bg);
-    constexpr int R = DM == DM_ALG1 ? 4 * Nfp : 2 * Nfp;
-    T g1[R], g2[R];
-    matvec_ld<R, Np, 2 * Np, T>(op + (DM == DM_ALG1 ? L.u1r : L.kr), c, g1);
-    matvec_ld<R, Np, 2 * Np, T>(op + (DM == DM_ALG1 ? L.u1r : L.kr) + Np, bg, g2);
-#pragma unroll
-    for (int j = 0; j < Nfp; ++j) {
-      if (DM == DM_ALG1) {
-        // the ghost carries the element's D: D1 = D2 = D
-        F[j] = D * (gR * (g1[j] + g2[j]) + gS * (g1[Nfp + j] + g2[Nfp + j]) -
-                    gR * (g1[2 * Nfp + j] + g2[2 * Nfp + j]) - gS * (g1[3 * Nfp + j] + g2[3 * Nfp + j]));
-      } else {
-        const T Dj = DM == DM_ALG2 ? alg2_coef<N, T>(op, j, D, D) : D;
-        F[j] = Dj * (gR * (g1[j] + g2[j]) + gS * (g1[Nfp + j] + g2[Nfp + j]));
-      }
-    }
-    return;
-  }
 #pragma unroll
   for (int j = 0; j <= N; ++j) gtrace[j] = T(0);   // u+ = 0 outside the domain
   T gb[2 * Nfp];
@@ -330,8 +336,10 @@ __device__ inline void boundary_upwind(const DevMesh& m, cptr<T> op, double2 vn,
 }
 
 // Boundary face e with its upwind convective flux (u+ outside: 0, or the
-// prescribed exterior state), written to the flux array.
-template <int N, typename T, int DM>
+// prescribed exterior state), written to the flux array.  GH = false leaves
+// out the prescribed-state path (its caller never sees exterior data), which
+// holds about twice the registers of the mirror-ghost path.
+template <int N, typename T, int DM, bool GH = true>
 __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                      const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -340,7 +348,7 @@ __device__ inline void boundary_body(const DevMesh& m, cptr<T> op, int64_t e, in
   const T* uf = u + (int64_t)field * m.K * Np;
   T F[Nfp], tr[Nfp], gtr[Nfp];
   double2 vn = make_double2(0.0, 0.0);
-  boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr, vn, gtr);
+  boundary_flux<N, T, DM, GH>(m, op, e, field, uf, F, tr, vn, gtr);
   if (m.conv) boundary_upwind<N, T>(m, op, vn, tr, gtr, F);
   T* out = flux + ((int64_t)field * E + e) * Nfp;
 #pragma unroll

@@ -248,28 +248,18 @@ __device__ inline void edge_split_finish(const DevMesh& m, int field, T* __restr
 // operator, one lane per face): their serial chain is the longest of the
 // launch, so they start first and run beside the interior tiles.  The other
 // blocks take one tile of 64 interior edges each.
-// Waves per SIMD the compiler must leave room for, where a few spilled
-// registers buy one more resident wave (Algorithm 1, whose four-block
-// reconstruction holds the most): FP64 at N = 4, 2 -> 3 waves with two
-// registers spilled (256x256 N = 4: 19.7 -> 16.8 us); FP32 at N = 6, 3 -> 4
-// with eight (512x512 N = 6: 95.8 -> 86.8 us).
-template <int N, typename T, int DM>
-struct SplitTune {
-  static constexpr int waves =
-      DM != DM_ALG1 ? 1 : ((sizeof(T) == 8 && N == 4) ? 3 : ((sizeof(T) == 4 && N == 6) ? 4 : 1));
-};
-
 template <int N, typename T, int DM, bool CONV>
-__global__ __launch_bounds__(2 * kSplitTile) __attribute__((amdgpu_waves_per_eu(SplitTune<N, T, DM>::waves)))
-void edge_split_kernel(DevMesh m, const T* __restrict__ u,
+__global__ __launch_bounds__(2 * kSplitTile) void edge_split_kernel(DevMesh m, const T* __restrict__ u,
                                                                     T* __restrict__ flux, int nb_bdy, int nf) {
   __shared__ SplitShared<N, T> S;
   const int64_t b = blockIdx.x;
   const int64_t nbt = (int64_t)nb_bdy * nf;
   if (b < nbt) {
+    // mirror-ghost faces only (with exterior data the faces take their own
+    // launch and nb_bdy is 0)
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * (2 * kSplitTile) + threadIdx.x;
-    if (e < m.E_int + m.E_bdy) boundary_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
+    if (e < m.E_int + m.E_bdy) boundary_body<N, T, DM, false>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   // nb_bdy is a multiple of 8, so b - nbt keeps b's XCD
@@ -543,6 +533,51 @@ __global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* c
 // ---------------------------------------------------------------------------
 
 
+// One lane per boundary face, 64 faces of one field per block (field
+// b % nf): the boundary faces of the side-split launches when exterior data
+// is prescribed.
+template <int N, typename T, int DM>
+__global__ __launch_bounds__(64) void edge_bdy_kernel(DevMesh m, const T* __restrict__ u, T* __restrict__ flux,
+                                                      int nf) {
+  const int field = (int)(blockIdx.x % nf);
+  const int64_t e = m.E_int + (int64_t)(blockIdx.x / nf) * 64 + threadIdx.x;
+  if (e < m.E_int + m.E_bdy) boundary_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
+}
+
+template <int N, typename T>
+hipError_t bdy_launch_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
+  if (m.E_bdy == 0) return hipSuccess;
+  dim3 grid((unsigned)((m.E_bdy + 63) / 64 * nfields));
+#define ARDG_BDY_LAUNCH(A) \
+  hipLaunchKernelGGL((edge_bdy_kernel<N, T, A>), grid, dim3(64), 0, st, m, (const T*)u, (T*)flux, nfields)
+  switch (m.dmode) {
+    case DM_CONST: ARDG_BDY_LAUNCH(DM_CONST); break;
+    case DM_ALG1: ARDG_BDY_LAUNCH(DM_ALG1); break;
+    case DM_ALG2: ARDG_BDY_LAUNCH(DM_ALG2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef ARDG_BDY_LAUNCH
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bdy_dispatch(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
+  switch (m.N) {
+    case 1: return bdy_launch_t<1, T>(m, nfields, u, flux, st);
+    case 2: return bdy_launch_t<2, T>(m, nfields, u, flux, st);
+    case 3: return bdy_launch_t<3, T>(m, nfields, u, flux, st);
+    case 4: return bdy_launch_t<4, T>(m, nfields, u, flux, st);
+    case 5: return bdy_launch_t<5, T>(m, nfields, u, flux, st);
+    case 6: return bdy_launch_t<6, T>(m, nfields, u, flux, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_boundary_faces(const DevMesh& m, bool f64, int nfields, const void* u, void* flux,
+                                 hipStream_t st) {
+  return f64 ? bdy_dispatch<double>(m, nfields, u, flux, st) : bdy_dispatch<float>(m, nfields, u, flux, st);
+}
+
 template <int N, typename T>
 hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   const int64_t E = m.E_int + m.E_bdy;
@@ -569,7 +604,13 @@ hipError_t edge_launch_t(const DevMesh& m, int nfields, const void* u, void* flu
   }
   if (split) {
     const int64_t nbi = (m.E_int + kSplitTile - 1) / kSplitTile;
-    const int64_t nbb = ((m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile) + 7) / 8 * 8;
+    int64_t nbb = ((m.E_bdy + 2 * kSplitTile - 1) / (2 * kSplitTile) + 7) / 8 * 8;
+    if (m.ghost) {
+      const hipError_t eb = launch_boundary_faces(m, sizeof(T) == 8, nfields, u, flux, st);
+      if (eb != hipSuccess) return eb;
+      nbb = 0;
+    }
+    if (nbi + nbb == 0) return hipSuccess;
     dim3 grid((unsigned)((nbi + nbb) * nfields));
 #define ARDG_SPLIT_LAUNCH(A, C)                                                                  \
   hipLaunchKernelGGL((edge_split_kernel<N, T, A, C>), grid, dim3(2 * kSplitTile), 0, st, m,       \

@@ -292,12 +292,15 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
 // through its own LDS rows to one lane per edge for the subdivision and its
 // side's columns of the reconstruction operator (vector unit, scalar operands,
 // as in the vector-unit split kernel).  The conversion runs on the matrix pipe
-// beside the other waves' vector work.  At least two waves per SIMD: in FP64 at
-// N = 6 with Algorithm 1 the register file otherwise holds one wave, which
-// then waits out every gather alone (512x512 mesh, N = 6: 240 us at one wave, 157 us
-// at two with ten registers spilled).
+// beside the other waves' vector work.  The boundary blocks carry only the
+// mirror-ghost path (with exterior data the faces take a launch of their own,
+// launch_boundary_faces): in FP64 at N = 6 with Algorithm 1 the tiles need
+// about 100 registers, the mirror-ghost path about 150 and the
+// prescribed-state path about 250.  At least three waves per SIMD: the
+// compiler then keeps the accumulators out of the matrix registers and fits
+// 154 registers without spilling.
 template <int N, typename P, int DM, bool CONV>
-__global__ __launch_bounds__(2 * kEdgeTile) __attribute__((amdgpu_waves_per_eu(2))) void edge_smfma_kernel(DevMesh m,
+__global__ __launch_bounds__(2 * kEdgeTile) __attribute__((amdgpu_waves_per_eu(3))) void edge_smfma_kernel(DevMesh m,
                                                                    const typename Mma<P>::T* __restrict__ u,
                                                                    typename Mma<P>::T* __restrict__ flux,
                                                                    int nb_bdy, int nf) {
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(2 * kEdgeTile) __attribute__((amdgpu_waves_per_eu(2
     // boundary faces first (mirror-ghost operator, one lane per face)
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * (2 * kEdgeTile) + threadIdx.x;
-    if (e < E) boundary_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, DM, false>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   int64_t tile;
@@ -470,7 +473,13 @@ hipError_t edge_smfma_t(const DevMesh& m, int nfields, const void* u, void* flux
   using T = typename Mma<P>::T;
   if (m.E_int + m.E_bdy == 0) return hipSuccess;
   const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
-  const int64_t nbb = ((m.E_bdy + 2 * kEdgeTile - 1) / (2 * kEdgeTile) + 7) / 8 * 8;
+  int64_t nbb = ((m.E_bdy + 2 * kEdgeTile - 1) / (2 * kEdgeTile) + 7) / 8 * 8;
+  if (m.ghost) {
+    const hipError_t eb = launch_boundary_faces(m, sizeof(T) == 8, nfields, u, flux, st);
+    if (eb != hipSuccess) return eb;
+    nbb = 0;
+  }
+  if (nbi + nbb == 0) return hipSuccess;
   dim3 grid((unsigned)((nbi + nbb) * nfields));
   const T* uu = (const T*)u;
   T* ff = (T*)flux;
