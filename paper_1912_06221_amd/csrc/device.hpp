@@ -180,8 +180,8 @@ hipError_t launch_edge_mfma(const DevMesh& m, int prec, int nfields, const void*
                             hipStream_t st);
 // Side-split tiles with the nodal -> Bernstein conversion on the matrix cores.
 // Boundary faces with prescribed exterior data, one lane per face in a launch
-// of their own (compute type FP64 or FP32), for the side-split launches: their
-// tile kernels carry only the mirror-ghost boundary path, whose registers stay
+// of their own (compute type FP64 or FP32), for the tiled launches (side-split
+// and matrix-core): their tile kernels carry only the mirror-ghost boundary path, whose registers stay
 // near the interior tiles' (the prescribed-state path holds about twice as
 // many, and the allocation of a kernel covers every path in it).
 hipError_t launch_boundary_faces(const DevMesh& m, bool f64, int nfields, const void* u, void* flux,

@@ -534,7 +534,7 @@ __global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* c
 
 
 // One lane per boundary face, 64 faces of one field per block (field
-// b % nf): the boundary faces of the side-split launches when exterior data
+// b % nf): the boundary faces of the tiled launches when exterior data
 // is prescribed.
 template <int N, typename T, int DM>
 __global__ __launch_bounds__(64) void edge_bdy_kernel(DevMesh m, const T* __restrict__ u, T* __restrict__ flux,

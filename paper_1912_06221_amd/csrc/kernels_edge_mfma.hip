@@ -229,10 +229,12 @@ __global__ __launch_bounds__(kEdgeTile) void edge_mfma_kernel(DevMesh m,
   if (b < nbt) {
     // boundary faces: mirror-ghost operator on the vector unit, one lane per
     // face, in the first blocks so that their long serial chain runs beside
-    // the interior tiles
+    // the interior tiles (with exterior data the faces take a launch of
+    // their own, launch_boundary_faces, and nb_bdy is 0: the prescribed-state
+    // path would set this kernel's register allocation)
     const int field = (int)(b % nf);
     const int64_t e = m.E_int + (b / nf) * kEdgeTile + l;
-    if (e < E) boundary_body<N, T, DM>(m, opbase<T>(m), e, field, u, flux);
+    if (e < E) boundary_body<N, T, DM, false>(m, opbase<T>(m), e, field, u, flux);
     return;
   }
   int64_t tile;
@@ -526,8 +528,14 @@ template <int N, typename P>
 hipError_t edge_mfma_t(const DevMesh& m, int nfields, const void* u, void* flux, hipStream_t st) {
   using T = typename Mma<P>::T;
   const int64_t nbi = (m.E_int + kEdgeTile - 1) / kEdgeTile;
-  const int64_t nbb = ((m.E_bdy + kEdgeTile - 1) / kEdgeTile + 7) / 8 * 8;
+  int64_t nbb = ((m.E_bdy + kEdgeTile - 1) / kEdgeTile + 7) / 8 * 8;
   if (m.E_int + m.E_bdy == 0) return hipSuccess;
+  if (m.ghost) {
+    const hipError_t eb = launch_boundary_faces(m, sizeof(T) == 8, nfields, u, flux, st);
+    if (eb != hipSuccess) return eb;
+    nbb = 0;
+  }
+  if (nbi + nbb == 0) return hipSuccess;
   dim3 grid((unsigned)((nbi + nbb) * nfields));
   const T* uu = (const T*)u;
   T* ff = (T*)flux;
