@@ -347,7 +347,9 @@ ardg_status ardg_batch_workspace_bytes(ardg_batch batch, int32_t scheme, int32_t
 /* Advance every mesh i by nsteps steps of size dt[i] (host array): u_devs[i]
  * is mesh i's FP64 state [K_i][Np_i] on the device (host array of n device
  * pointers).  Same schemes and precisions as ardg_rk_step; results equal the
- * per-mesh ardg_rk_step up to rounding. */
+ * per-mesh ardg_rk_step up to rounding.  E_UNSUPPORTED if a mesh no longer
+ * meets ardg_batch_create's conditions (exterior data, a velocity or another
+ * diffusion form set since), before anything is enqueued. */
 ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
                             double* const* u_devs, void* work_dev, const double* dt,
                             int32_t nsteps, void* hip_stream);

@@ -1388,6 +1388,13 @@ ardg_status tune(ardg_batch b, int precision) {
 
 extern "C" {
 
+// What the batched kernels are built for: one field with constant D, no
+// velocity, no exterior data (their boundary faces take the mirror-ghost
+// path only), the scalar equation.
+static bool batch_mesh_ok(ardg_mesh m) {
+  return m->dm.dmode == DM_CONST && !m->dm.conv && m->nfields_D == 1 && !m->dm.ghost && m->dm.ns == NS_OFF;
+}
+
 ardg_status ardg_batch_create(const ardg_mesh* meshes, int32_t n, const char* tune_cache, ardg_batch* out) {
   if (!out) return fail(ARDG_E_INVALID_ARG, "batch_create: null out");
   *out = nullptr;
@@ -1398,7 +1405,7 @@ ardg_status ardg_batch_create(const ardg_mesh* meshes, int32_t n, const char* tu
     if (!m) return fail(ARDG_E_INVALID_ARG, "batch_create: null mesh");
     if (m->device < 0 || m->device != dev)
       return fail(ARDG_E_INVALID_ARG, "batch_create: meshes must live on one device");
-    if (m->dm.dmode != DM_CONST || m->dm.conv || m->nfields_D != 1 || m->dm.ghost || m->dm.ns != NS_OFF)
+    if (!batch_mesh_ok(m))
       return fail(ARDG_E_UNSUPPORTED,
                   "batch_create: meshes need one field, constant D, no velocity and zero Dirichlet data");
   }
@@ -1551,6 +1558,12 @@ ardg_status ardg_batch_step(ardg_batch batch, int32_t scheme, int32_t precision,
   const size_t n = batch->meshes.size();
   for (size_t i = 0; i < n; ++i)
     if (!u_devs[i] || !std::isfinite(dt[i])) return fail(ARDG_E_INVALID_ARG, "batch_step: bad state pointer or dt");
+  // the meshes are referenced: one changed since the batch was made may no
+  // longer be one the batched kernels handle
+  for (size_t i = 0; i < n; ++i)
+    if (!batch_mesh_ok(batch->meshes[i]))
+      return fail(ARDG_E_UNSUPPORTED, "batch_step: mesh " + std::to_string(i) +
+                                          " no longer has one field, constant D, no velocity and zero Dirichlet data");
   if (nsteps == 0) return ARDG_OK;
   DeviceGuard g(batch->device);
   ardg_status s = tune(batch, precision);

@@ -410,8 +410,8 @@ __device__ inline void interior_flux(const DevMesh& m, cptr<T> op, int field, T 
   }
 }
 
-// One lane per edge.
-template <int N, typename T, int DM>
+// One lane per edge (GH as for boundary_body).
+template <int N, typename T, int DM, bool GH = true>
 __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int field,
                                  const T* __restrict__ u, T* __restrict__ flux) {
   constexpr OpLayout L(N);
@@ -462,7 +462,7 @@ __device__ inline void edge_body(const DevMesh& m, cptr<T> op, int64_t e, int fi
     interior_flux<N, T, DM, kBoth>(m, op, field, c, mu1, mu2, g, vn, D1d, D2d, tr1, tr2, F);
   } else {
     T gtr[Nfp];
-    boundary_flux<N, T, DM>(m, op, e, field, uf, F, tr1, vn, gtr);
+    boundary_flux<N, T, DM, GH>(m, op, e, field, uf, F, tr1, vn, gtr);
     if (m.conv) boundary_upwind<N, T>(m, op, vn, tr1, gtr, F);
   }
   T* out = flux + ((int64_t)field * E + e) * Nfp;

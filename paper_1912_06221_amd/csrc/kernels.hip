@@ -290,7 +290,9 @@ __global__ __launch_bounds__(2 * kSplitTile) void batch_edge_split_kernel(const 
       edge_split_finish<N, T, DM_CONST, false>(P->m, 0, (T*)P->flux, in, S.part);
     } else {
       const int64_t e = P->m.E_int + (int64_t)(-1 - t) * (2 * kSplitTile) + threadIdx.x;
-      if (e < P->m.E_int + P->m.E_bdy) boundary_body<N, T, DM_CONST>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+      // batched meshes carry no exterior data (mirror-ghost path only)
+      if (e < P->m.E_int + P->m.E_bdy)
+        boundary_body<N, T, DM_CONST, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
     }
     __syncthreads();
   }
@@ -456,7 +458,7 @@ __global__ __launch_bounds__(TILE) void batch_edge_kernel(const BatchProb* __res
     const int64_t e = (int64_t)__builtin_amdgcn_readfirstlane(w.y) * TILE + threadIdx.x;
     if (e < P->m.E_int + P->m.E_bdy) {
       const T* vin = in_u ? (const T*)(const void*)P->u : (const T*)P->v;
-      edge_body<N, T, DM_CONST>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
+      edge_body<N, T, DM_CONST, false>(P->m, opbase<T>(P->m), e, 0, vin, (T*)P->flux);
     }
   }
 }

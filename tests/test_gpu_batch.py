@@ -131,3 +131,32 @@ def test_batch_workload_sampled():
         r = to_np(ud)
         err = np.abs(to_np(us[i]) - r).max() / np.abs(r).max()
         assert err <= 1e-5, (i, err)
+
+
+def test_batch_refuses_meshes_changed_after_creation():
+    """The batch references its meshes: one that takes exterior data or a
+    velocity after the batch was made is refused at the next step (the
+    batched kernels carry neither), and accepted again once restored."""
+    import torch
+    from paper_1912_06221_amd import ardg
+    print("batch refuses changed meshes", flush=True)
+    probs = _problems(SPECS[:3])
+    b = ardg.Batch([pr[2] for pr in probs])
+    us = [to_dev(W.random_nodal((1, mesh.K, ops.Np), seed=i)) for i, (mesh, ops, _, _, _) in enumerate(probs)]
+    work = ardg.alloc_workspace(b.workspace_bytes(ardg.RK4, ardg.FP64), us[0].device)
+    dts = [1e-5] * 3
+    b.step(us, work, dts, 1)
+    lm = probs[1][2]
+    lm.set_boundary_data(np.zeros((1, lm.E_bdy, probs[1][1].Np, 1)), 0.0, 1.0)
+    with pytest.raises(ardg.ArdgError) as ei:
+        b.step(us, work, dts, 1)
+    assert ei.value.status == -6   # ARDG_E_UNSUPPORTED
+    lm.set_boundary_data(None, 0.0, 1.0)
+    lm.set_velocity((0.0, 0.0, 0.0, -1.0, 1.0, 0.0))
+    with pytest.raises(ardg.ArdgError):
+        b.step(us, work, dts, 1)
+    lm.set_velocity(None)
+    b.step(us, work, dts, 1)
+    torch.cuda.synchronize()
+    for u in us:
+        assert bool(torch.isfinite(u).all())
