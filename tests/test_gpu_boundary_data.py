@@ -45,6 +45,9 @@ CASES = [
     (6, 4, "element", None, 1),
     (6, 3, "element2", (0.0, 0.0, 0.0, -1.0, 1.0, 0.0), 1),
     (5, 6, "const", None, 1),
+    # Algorithm 1 at N = 6: the tiled kernels hand faces with exterior data to
+    # a launch of their own
+    (4, 6, "element", None, 1),
 ]
 
 
